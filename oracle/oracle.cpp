@@ -1,0 +1,958 @@
+// FP64 CPU oracle for the dual adaptive explicit time integration (DAETI)
+// method of Mountris & Pueyo, "A dual adaptive explicit time integration
+// algorithm for efficiently solving the cardiac monodomain equation".
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+// reference the GPU library is checked against.  Only the test suite, the
+// smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+// code, header, table or constant with the GPU library.
+//
+// What it computes (paper Sec. 2):
+//   * FE stiffness K and row-sum lumped mass m of the diffusion problem,
+//     eq. (2b)-(2c), on Q1 line / quad / hex elements (2^d Gauss points).
+//   * The Gershgorin stable step, eq. (3):
+//       dt_s = 0.9 * min_i m_ii / (k_ii + sum_{j!=i} |k_ij|)
+//     and the diffusion substep count l and dt_ad = dt/(2l) (Sec. 2).
+//   * Strang splitting B(dt/2) A(dt) B(dt/2) per outer step (Sec. 2): B is
+//     forward Euler on dV/dt = -M^-1 K V + s(t); A advances every node's cell
+//     model with k substeps of dt/k, k = min(k0 + floor|dV/dt|, k_max),
+//     k0 = 5 if dV/dt > 0 else 1, k_max = floor(dt/dt0) (Sec. 2).
+//   * Gates by Rush-Larsen, everything else by forward Euler.
+//   * First upward crossing time of a voltage threshold (local activation
+//     time, Sec. 3.3), kept in FP64.
+//
+// Readings of points the paper leaves open are listed in the project's design
+// notes; the ones that change arithmetic are restated where they are used.
+//
+// Cell models:
+//   * linear test model   dV/dt = -g (V - E)
+//   * Mitchell & Schaeffer, Bull. Math. Biol. 65:767 (2003), two variables.
+//   * ten Tusscher & Panfilov, Am. J. Physiol. Heart Circ. Physiol.
+//     291:H1088 (2006), epicardial, 19 state variables, with the current
+//     formulations carried over from ten Tusscher et al., Am. J. Physiol.
+//     286:H1573 (2004).
+//
+// Build: g++ -O2 -fopenmp -ffp-contract=off -shared -fPIC (see build.py).
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <algorithm>
+#include <string>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+std::string g_err;
+int fail(const char* msg) { g_err = msg; return -1; }
+
+// ---------------------------------------------------------------------------
+// finite elements: Q1 shape functions on [-1,1]^d, 2-point Gauss rule
+// ---------------------------------------------------------------------------
+// Reference coordinates of the element nodes, in the ordering of the mesh
+// description (line: x-,x+; quad: counter-clockwise; hex: z- face then z+).
+const double REF_LINE[2][1] = {{-1}, {1}};
+const double REF_QUAD[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+const double REF_HEX[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                              {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+double ref_coord(int nen, int a, int d) {
+  if (nen == 2) return REF_LINE[a][d];
+  if (nen == 4) return REF_QUAD[a][d];
+  return REF_HEX[a][d];
+}
+
+// N_a(xi) = prod_d (1 + xi_d xa_d)/2 and its xi-gradient.
+void shape(int dim, int nen, const double* xi, double* N, double* dN /* nen*dim */) {
+  for (int a = 0; a < nen; ++a) {
+    double f[3];
+    for (int d = 0; d < dim; ++d) f[d] = 0.5 * (1.0 + xi[d] * ref_coord(nen, a, d));
+    double p = 1.0;
+    for (int d = 0; d < dim; ++d) p *= f[d];
+    N[a] = p;
+    for (int d = 0; d < dim; ++d) {
+      double g = 0.5 * ref_coord(nen, a, d);
+      for (int e = 0; e < dim; ++e)
+        if (e != d) g *= f[e];
+      dN[a * dim + d] = g;
+    }
+  }
+}
+
+// Inverse and determinant of a dim x dim matrix (dim <= 3), row-major.
+double invert(int dim, const double* A, double* Ai) {
+  if (dim == 1) {
+    Ai[0] = 1.0 / A[0];
+    return A[0];
+  }
+  if (dim == 2) {
+    double det = A[0] * A[3] - A[1] * A[2];
+    Ai[0] = A[3] / det;
+    Ai[1] = -A[1] / det;
+    Ai[2] = -A[2] / det;
+    Ai[3] = A[0] / det;
+    return det;
+  }
+  double c00 = A[4] * A[8] - A[5] * A[7];
+  double c01 = A[5] * A[6] - A[3] * A[8];
+  double c02 = A[3] * A[7] - A[4] * A[6];
+  double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  Ai[0] = c00 / det;
+  Ai[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+  Ai[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+  Ai[3] = c01 / det;
+  Ai[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+  Ai[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+  Ai[6] = c02 / det;
+  Ai[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+  Ai[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+  return det;
+}
+
+// Element stiffness Ke[a][b] = int grad N_a . D grad N_b and lumped mass
+// me[a] = int N_a (the row sum of the consistent mass, since sum_b N_b = 1).
+int element_matrices(int dim, int nen, const double* X /* nen*dim */, const double* D,
+                     double* Ke, double* me) {
+  const double g = 1.0 / std::sqrt(3.0);
+  const int nq = 1 << dim;
+  for (int i = 0; i < nen * nen; ++i) Ke[i] = 0.0;
+  for (int a = 0; a < nen; ++a) me[a] = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    double xi[3];
+    for (int d = 0; d < dim; ++d) xi[d] = ((q >> d) & 1) ? g : -g;
+    double N[8], dN[24];
+    shape(dim, nen, xi, N, dN);
+    // J[d][e] = dx_e / dxi_d
+    double J[9] = {0}, Ji[9];
+    for (int d = 0; d < dim; ++d)
+      for (int e = 0; e < dim; ++e) {
+        double s = 0.0;
+        for (int a = 0; a < nen; ++a) s += dN[a * dim + d] * X[a * dim + e];
+        J[d * dim + e] = s;
+      }
+    double detJ = invert(dim, J, Ji);
+    if (!(detJ > 0.0)) return -1;
+    // grad_x N_a = J^-1 grad_xi N_a
+    double G[24];
+    for (int a = 0; a < nen; ++a)
+      for (int e = 0; e < dim; ++e) {
+        double s = 0.0;
+        for (int d = 0; d < dim; ++d) s += Ji[e * dim + d] * dN[a * dim + d];
+        G[a * dim + e] = s;
+      }
+    for (int a = 0; a < nen; ++a) {
+      me[a] += N[a] * detJ;
+      for (int b = 0; b < nen; ++b) {
+        double s = 0.0;
+        for (int d = 0; d < dim; ++d)
+          for (int e = 0; e < dim; ++e) s += G[a * dim + d] * D[d * dim + e] * G[b * dim + e];
+        Ke[a * nen + b] += s * detJ;
+      }
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// cell models
+// ---------------------------------------------------------------------------
+enum { M_LINEAR = 0, M_MS = 1, M_TP06 = 2 };
+
+int model_nstates(int m) { return m == M_LINEAR ? 1 : (m == M_MS ? 2 : 19); }
+int model_nparams(int m) { return m == M_LINEAR ? 2 : (m == M_MS ? 5 : 6); }
+
+// Rates of one cell.  For every state y the model reports either a forward
+// Euler slope (is_gate = 0: rate = dy/dt) or Rush-Larsen data (is_gate = 1:
+// inf = y_inf, tau = time constant).  State 0 is always V.
+struct Rates {
+  double rate[19];
+  double inf[19];
+  double tau[19];
+  int is_gate[19];
+  // Ca buffering: slopes of the *total* concentrations of states 3,4,5
+  int buffered;
+};
+
+// Linear test model: dV/dt = -g (V - E).   p = {g, E}
+void rates_linear(const double* y, const double* p, Rates& r) {
+  r.buffered = 0;
+  r.is_gate[0] = 0;
+  r.rate[0] = -p[0] * (y[0] - p[1]);
+}
+
+// Mitchell-Schaeffer: dv/dt = h v^2 (1-v)/tau_in - v/tau_out,
+// dh/dt = (1-h)/tau_open if v < v_gate, else -h/tau_close.
+// p = {tau_in, tau_out, tau_open, tau_close, v_gate}.  The gate is written in
+// Rush-Larsen form: h_inf = 1 (tau_open) below v_gate, 0 (tau_close) at or
+// above it.
+void rates_ms(const double* y, const double* p, Rates& r) {
+  double v = y[0], h = y[1];
+  r.buffered = 0;
+  r.is_gate[0] = 0;
+  r.rate[0] = h * v * v * (1.0 - v) / p[0] - v / p[1];
+  r.is_gate[1] = 1;
+  if (v < p[4]) {
+    r.inf[1] = 1.0;
+    r.tau[1] = p[2];
+  } else {
+    r.inf[1] = 0.0;
+    r.tau[1] = p[3];
+  }
+}
+
+// --- ten Tusscher-Panfilov 2006, epicardial --------------------------------
+// state order: 0 V, 1 K_i, 2 Na_i, 3 Ca_i, 4 Ca_ss, 5 Ca_SR, 6 Rbar,
+//              7 m, 8 h, 9 j, 10 xr1, 11 xr2, 12 xs, 13 r, 14 s,
+//              15 d, 16 f, 17 f2, 18 fCass
+// p = {Ko, scale gNa, scale gCaL, scale gKr, scale gKs, scale gK1}
+namespace tp {
+const double R = 8314.472, T = 310.0, F = 96485.3415;
+const double Cm = 0.185;                 // uF, cell capacitance
+const double Vc = 0.016404, Vsr = 0.001094, Vss = 0.00005468;  // nL
+const double Nao = 140.0, Cao = 2.0;
+const double GNa = 14.838, GK1 = 5.405, Gto = 0.294, GKr = 0.153, GKs = 0.392;
+const double pKNa = 0.03;
+const double GCaL = 3.980e-5;
+const double kNaCa = 1000.0, gam = 0.35, KmCa = 1.38, KmNai = 87.5, ksat = 0.1, alf = 2.5;
+const double PNaK = 2.724, KmK = 1.0, KmNa = 40.0;
+const double GpK = 0.0146, GpCa = 0.1238, KpCa = 0.0005;
+const double GbNa = 0.00029, GbCa = 0.000592;
+const double Vmaxup = 0.006375, Kup = 0.00025;
+const double Vrel = 0.102, k1p = 0.15, k2p = 0.045, k3 = 0.060, k4 = 0.005;
+const double EC = 1.5, maxsr = 2.5, minsr = 1.0;
+const double Vleak = 0.00036, Vxfer = 0.0038;
+const double Bufc = 0.2, Kbufc = 0.001;
+const double Bufsr = 10.0, Kbufsr = 0.3;
+const double Bufss = 0.4, Kbufss = 0.00025;
+
+// Published initial values of the model's code release (not pre-paced).
+const double INIT[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0,
+                         0.0,   0.75,  0.75, 0.0,     1.0,     0.0, 0.0,
+                         1.0,   0.0,   1.0,  1.0,     1.0};
+}  // namespace tp
+
+// Ionic currents of TP06 (pA/pF) at state y; also used by qualitative tests.
+struct TPCurrents {
+  double INa, IK1, Ito, IKr, IKs, ICaL, INaCa, INaK, IpCa, IpK, IbNa, IbCa;
+  double Irel, Iup, Ileak, Ixfer;
+  double Iion;
+};
+
+void tp06_currents(const double* y, const double* p, TPCurrents& c) {
+  using namespace tp;
+  const double V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5],
+               Rb = y[6];
+  const double m = y[7], h = y[8], j = y[9], xr1 = y[10], xr2 = y[11], xs = y[12];
+  const double r = y[13], s = y[14], d = y[15], f = y[16], f2 = y[17], fcass = y[18];
+  const double Ko = p[0];
+  const double RTF = R * T / F;
+  const double EK = RTF * std::log(Ko / Ki);
+  const double ENa = RTF * std::log(Nao / Nai);
+  const double ECa = 0.5 * RTF * std::log(Cao / Cai);
+  const double EKs = RTF * std::log((Ko + pKNa * Nao) / (Ki + pKNa * Nai));
+
+  c.INa = p[1] * GNa * m * m * m * h * j * (V - ENa);
+
+  const double aK1 = 0.1 / (1.0 + std::exp(0.06 * (V - EK - 200.0)));
+  const double bK1 = (3.0 * std::exp(0.0002 * (V - EK + 100.0)) + std::exp(0.1 * (V - EK - 10.0))) /
+                     (1.0 + std::exp(-0.5 * (V - EK)));
+  const double xK1 = aK1 / (aK1 + bK1);
+  c.IK1 = p[5] * GK1 * std::sqrt(Ko / 5.4) * xK1 * (V - EK);
+
+  c.Ito = Gto * r * s * (V - EK);
+  c.IKr = p[3] * GKr * std::sqrt(Ko / 5.4) * xr1 * xr2 * (V - EK);
+  c.IKs = p[4] * GKs * xs * xs * (V - EKs);
+
+  // L-type current; x/(e^x - 1) -> 1 at x = 0 (removable singularity at V=15)
+  const double x = 2.0 * (V - 15.0) * F / (R * T);
+  const double xe = (x == 0.0) ? 1.0 : x / std::expm1(x);
+  // 4 (V-15) F^2/(RT) (0.25 Cass e^x - Cao)/(e^x - 1) = 2 F (x/(e^x-1)) (0.25 Cass e^x - Cao)
+  c.ICaL = p[2] * GCaL * d * f * f2 * fcass * 2.0 * F * xe * (0.25 * Cass * std::exp(x) - Cao);
+
+  const double eg = std::exp(gam * V * F / (R * T));
+  const double eg1 = std::exp((gam - 1.0) * V * F / (R * T));
+  c.INaCa = kNaCa * (eg * Nai * Nai * Nai * Cao - eg1 * Nao * Nao * Nao * Cai * alf) /
+            ((KmNai * KmNai * KmNai + Nao * Nao * Nao) * (KmCa + Cao) * (1.0 + ksat * eg1));
+  c.INaK = PNaK * Ko * Nai /
+           ((Ko + KmK) * (Nai + KmNa) *
+            (1.0 + 0.1245 * std::exp(-0.1 * V * F / (R * T)) + 0.0353 * std::exp(-V * F / (R * T))));
+  c.IpCa = GpCa * Cai / (KpCa + Cai);
+  c.IpK = GpK * (V - EK) / (1.0 + std::exp((25.0 - V) / 5.98));
+  c.IbNa = GbNa * (V - ENa);
+  c.IbCa = GbCa * (V - ECa);
+
+  const double kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
+  const double k1 = k1p / kcasr;
+  const double O = k1 * Cass * Cass * Rb / (k3 + k1 * Cass * Cass);
+  c.Irel = Vrel * O * (CaSR - Cass);
+  c.Iup = Vmaxup / (1.0 + Kup * Kup / (Cai * Cai));
+  c.Ileak = Vleak * (CaSR - Cai);
+  c.Ixfer = Vxfer * (Cass - Cai);
+
+  c.Iion = c.INa + c.IK1 + c.Ito + c.IKr + c.IKs + c.ICaL + c.INaCa + c.INaK + c.IpCa + c.IpK +
+           c.IbNa + c.IbCa;
+}
+
+void rates_tp06(const double* y, const double* p, Rates& r) {
+  using namespace tp;
+  TPCurrents c;
+  tp06_currents(y, p, c);
+  const double V = y[0], Cass = y[4], CaSR = y[5], Rb = y[6];
+
+  for (int i = 0; i < 7; ++i) r.is_gate[i] = 0;
+  for (int i = 7; i < 19; ++i) r.is_gate[i] = 1;
+  r.buffered = 1;
+
+  r.rate[0] = -c.Iion;
+  r.rate[1] = -(c.IK1 + c.Ito + c.IKr + c.IKs - 2.0 * c.INaK + c.IpK) * Cm / (Vc * F);
+  r.rate[2] = -(c.INa + c.IbNa + 3.0 * c.INaK + 3.0 * c.INaCa) * Cm / (Vc * F);
+  // slopes of total (free + buffered) calcium in cytosol, subspace and SR
+  r.rate[3] = -(c.IbCa + c.IpCa - 2.0 * c.INaCa) * Cm / (2.0 * Vc * F) +
+              (Vsr / Vc) * (c.Ileak - c.Iup) + c.Ixfer;
+  r.rate[4] = -c.ICaL * Cm / (2.0 * Vss * F) + (Vsr / Vss) * c.Irel - (Vc / Vss) * c.Ixfer;
+  r.rate[5] = c.Iup - c.Ileak - c.Irel;
+  const double kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
+  const double k2 = k2p * kcasr;
+  r.rate[6] = -k2 * Cass * Rb + k4 * (1.0 - Rb);
+
+  // m
+  {
+    double e = 1.0 / (1.0 + std::exp((-56.86 - V) / 9.03));
+    r.inf[7] = e * e;
+    double am = 1.0 / (1.0 + std::exp((-60.0 - V) / 5.0));
+    double bm = 0.1 / (1.0 + std::exp((V + 35.0) / 5.0)) + 0.10 / (1.0 + std::exp((V - 50.0) / 200.0));
+    r.tau[7] = am * bm;
+  }
+  // h, j
+  {
+    double e = 1.0 / (1.0 + std::exp((V + 71.55) / 7.43));
+    r.inf[8] = e * e;
+    r.inf[9] = e * e;
+    double ah, bh, aj, bj;
+    if (V >= -40.0) {
+      ah = 0.0;
+      bh = 0.77 / (0.13 * (1.0 + std::exp(-(V + 10.66) / 11.1)));
+      aj = 0.0;
+      bj = 0.6 * std::exp(0.057 * V) / (1.0 + std::exp(-0.1 * (V + 32.0)));
+    } else {
+      ah = 0.057 * std::exp(-(V + 80.0) / 6.8);
+      bh = 2.7 * std::exp(0.079 * V) + 3.1e5 * std::exp(0.3485 * V);
+      aj = (-2.5428e4 * std::exp(0.2444 * V) - 6.948e-6 * std::exp(-0.04391 * V)) * (V + 37.78) /
+           (1.0 + std::exp(0.311 * (V + 79.23)));
+      bj = 0.02424 * std::exp(-0.01052 * V) / (1.0 + std::exp(-0.1378 * (V + 40.14)));
+    }
+    r.tau[8] = 1.0 / (ah + bh);
+    r.tau[9] = 1.0 / (aj + bj);
+  }
+  // xr1, xr2
+  {
+    r.inf[10] = 1.0 / (1.0 + std::exp((-26.0 - V) / 7.0));
+    double a = 450.0 / (1.0 + std::exp((-45.0 - V) / 10.0));
+    double b = 6.0 / (1.0 + std::exp((V + 30.0) / 11.5));
+    r.tau[10] = a * b;
+    r.inf[11] = 1.0 / (1.0 + std::exp((V + 88.0) / 24.0));
+    a = 3.0 / (1.0 + std::exp((-60.0 - V) / 20.0));
+    b = 1.12 / (1.0 + std::exp((V - 60.0) / 20.0));
+    r.tau[11] = a * b;
+  }
+  // xs
+  {
+    r.inf[12] = 1.0 / (1.0 + std::exp((-5.0 - V) / 14.0));
+    double a = 1400.0 / std::sqrt(1.0 + std::exp((5.0 - V) / 6.0));
+    double b = 1.0 / (1.0 + std::exp((V - 35.0) / 15.0));
+    r.tau[12] = a * b + 80.0;
+  }
+  // r, s (epicardial)
+  {
+    r.inf[13] = 1.0 / (1.0 + std::exp((20.0 - V) / 6.0));
+    r.tau[13] = 9.5 * std::exp(-(V + 40.0) * (V + 40.0) / 1800.0) + 0.8;
+    r.inf[14] = 1.0 / (1.0 + std::exp((V + 20.0) / 5.0));
+    r.tau[14] = 85.0 * std::exp(-(V + 45.0) * (V + 45.0) / 320.0) +
+                5.0 / (1.0 + std::exp((V - 20.0) / 5.0)) + 3.0;
+  }
+  // d, f, f2, fCass
+  {
+    r.inf[15] = 1.0 / (1.0 + std::exp((-8.0 - V) / 7.5));
+    double a = 1.4 / (1.0 + std::exp((-35.0 - V) / 13.0)) + 0.25;
+    double b = 1.4 / (1.0 + std::exp((V + 5.0) / 5.0));
+    double g = 1.0 / (1.0 + std::exp((50.0 - V) / 20.0));
+    r.tau[15] = a * b + g;
+
+    r.inf[16] = 1.0 / (1.0 + std::exp((V + 20.0) / 7.0));
+    a = 1102.5 * std::exp(-(V + 27.0) * (V + 27.0) / 225.0);
+    b = 200.0 / (1.0 + std::exp((13.0 - V) / 10.0));
+    g = 180.0 / (1.0 + std::exp((V + 30.0) / 10.0)) + 20.0;
+    r.tau[16] = a + b + g;
+
+    r.inf[17] = 0.67 / (1.0 + std::exp((V + 35.0) / 7.0)) + 0.33;
+    a = 600.0 * std::exp(-(V + 25.0) * (V + 25.0) / 170.0);
+    b = 31.0 / (1.0 + std::exp((25.0 - V) / 10.0));
+    g = 16.0 / (1.0 + std::exp((V + 30.0) / 10.0));
+    r.tau[17] = a + b + g;
+
+    double q = (Cass / 0.05) * (Cass / 0.05);
+    r.inf[18] = 0.6 / (1.0 + q) + 0.4;
+    r.tau[18] = 80.0 / (1.0 + q) + 2.0;
+  }
+}
+
+// Free concentration c >= 0 whose total c + B c/(c + K) equals `total`:
+// the positive root of c^2 + (B + K - total) c - K total = 0.
+double free_from_total(double total, double B, double K) {
+  double b = B + K - total;
+  return 0.5 * (-b + std::sqrt(b * b + 4.0 * K * total));
+}
+double total_from_free(double c, double B, double K) { return c + B * c / (c + K); }
+
+void model_rates(int model, const double* y, const double* p, Rates& r) {
+  if (model == M_LINEAR)
+    rates_linear(y, p, r);
+  else if (model == M_MS)
+    rates_ms(y, p, r);
+  else
+    rates_tp06(y, p, r);
+}
+
+// One substep of length h from y (all rates taken at the substep start):
+// Rush-Larsen for gates, forward Euler for the rest (TP06 calcium through its
+// buffered totals).  If vclamp, V is held.
+void cell_substep(int model, double* y, const double* p, double h, int vclamp) {
+  Rates r;
+  model_rates(model, y, p, r);
+  const int S = model_nstates(model);
+  double yn[19];
+  for (int i = 0; i < S; ++i) {
+    if (r.is_gate[i]) {
+      yn[i] = r.inf[i] + (y[i] - r.inf[i]) * std::exp(-h / r.tau[i]);
+    } else if (r.buffered && i == 3) {
+      yn[i] = free_from_total(total_from_free(y[i], tp::Bufc, tp::Kbufc) + h * r.rate[i], tp::Bufc,
+                              tp::Kbufc);
+    } else if (r.buffered && i == 4) {
+      yn[i] = free_from_total(total_from_free(y[i], tp::Bufss, tp::Kbufss) + h * r.rate[i],
+                              tp::Bufss, tp::Kbufss);
+    } else if (r.buffered && i == 5) {
+      yn[i] = free_from_total(total_from_free(y[i], tp::Bufsr, tp::Kbufsr) + h * r.rate[i],
+                              tp::Bufsr, tp::Kbufsr);
+    } else {
+      yn[i] = y[i] + h * r.rate[i];
+    }
+  }
+  if (vclamp) yn[0] = y[0];
+  for (int i = 0; i < S; ++i) y[i] = yn[i];
+}
+
+// Reaction substep count (Sec. 2): k0 = 5 for dV/dt > 0, else 1;
+// k = k0 + floor|dV/dt|, capped at k_max.
+int k_rule(double dvdt, int k_max) {
+  double k0 = dvdt > 0.0 ? 5.0 : 1.0;
+  double k = k0 + std::floor(std::fabs(dvdt));
+  if (!(k <= (double)k_max)) return k_max;   // also catches NaN
+  return (int)k;
+}
+
+// Diffusion substep count (Sec. 2): l = floor(dt/(2 dt_s)) when dt/2 > dt_s,
+// else 1.  l_round = 1 selects the ceiling instead (dt_ad <= dt_s).
+int l_rule(double dt, double dt_s, int l_round) {
+  if (!(0.5 * dt > dt_s)) return 1;
+  double x = dt / (2.0 * dt_s);
+  double l = l_round ? std::ceil(x) : std::floor(x);
+  if (l < 1.0) l = 1.0;
+  return (int)l;
+}
+
+// ---------------------------------------------------------------------------
+// simulation
+// ---------------------------------------------------------------------------
+struct Stim {
+  std::vector<int32_t> nodes;
+  double t_on, dur, amp;
+};
+
+struct Sim {
+  int dim = 0, nen = 0;
+  int64_t n = 0;
+  // CSR of K (with diagonal), lumped mass
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  std::vector<double> mass;
+  // instances
+  std::vector<int64_t> inst_off;   // n_inst + 1
+  std::vector<int32_t> inst_of;    // node -> instance
+  // model
+  int model = -1;
+  int S = 0, P = 0;
+  std::vector<double> state;       // S * n, SoA (state 0 = V)
+  std::vector<double> params;      // P * n, SoA
+  std::vector<double> vprev;       // n
+  std::vector<double> lat;         // n, -1 = not activated
+  std::vector<int32_t> lastk;      // n
+  double lat_thr = 0.0;
+  double dt0 = 0.01;
+  std::vector<Stim> stims;
+  std::vector<double> stim_rate;   // n, scratch
+  // method
+  int method = 0;      // 0 DAETI, 1 OSTAR (l = 1), 2 OST (k = 1, l = 1)
+  int dvdt_src = 0;    // 0: (V_b^n - V_b^{n-1})/dt ; 1: reaction rate at A-entry
+  int l_round = 0;     // 0 floor, 1 ceil
+  int vclamp = 0;
+  // time discretisation
+  double dt = -1.0;
+  std::vector<double> dt_s, gmax;  // per instance
+  std::vector<int> l;              // per instance
+  std::vector<double> dt_ad;       // per instance
+  int k_max = 1;
+  int64_t step = 0;
+  // k trace
+  int ktrace_mode = 0;             // 0 off, 1 record, 2 replay
+  uint8_t* ktrace = nullptr;
+  double* dtrace = nullptr;
+  int64_t ktrace_steps = 0;
+  // sensors: record V at A-entry of every step
+  std::vector<int32_t> sensors;
+  double* sensor_buf = nullptr;
+  int64_t sensor_steps = 0;
+  std::vector<double> vtmp;
+};
+
+int prepare(Sim* s, double dt) {
+  if (!(dt > 0.0)) return fail("dt must be positive");
+  int ni = (int)s->inst_off.size() - 1;
+  s->dt = dt;
+  s->dt_s.assign(ni, 0.0);
+  s->gmax.assign(ni, 0.0);
+  s->l.assign(ni, 1);
+  s->dt_ad.assign(ni, 0.0);
+  for (int q = 0; q < ni; ++q) {
+    // eq. (3): dt_s = 0.9 min_i m_ii / (k_ii + sum_{j != i} |k_ij|)
+    double rmin = INFINITY, gm = 0.0;
+    for (int64_t i = s->inst_off[q]; i < s->inst_off[q + 1]; ++i) {
+      double kii = 0.0, off = 0.0;
+      for (int64_t p = s->rowptr[i]; p < s->rowptr[i + 1]; ++p) {
+        if (s->col[p] == i)
+          kii += s->val[p];
+        else
+          off += std::fabs(s->val[p]);
+      }
+      double r = s->mass[i] / (kii + off);
+      if (r < rmin) rmin = r;
+      double g = (kii + off) / s->mass[i];
+      if (g > gm) gm = g;
+    }
+    s->dt_s[q] = 0.9 * rmin;
+    s->gmax[q] = gm;
+    int l = l_rule(dt, s->dt_s[q], s->l_round);
+    if (s->method != 0) l = 1;
+    s->l[q] = l;
+    s->dt_ad[q] = dt / (2.0 * l);
+  }
+  double km = std::floor(dt / s->dt0);
+  s->k_max = km < 1.0 ? 1 : (int)km;
+  if (s->method == 2) s->k_max = 1;
+  return 0;
+}
+
+// One diffusion half step B(dt/2) at time t0: l forward Euler substeps of
+// V <- V + dt_ad (-M^-1 K V + s(tau)), tau = t0 + m dt_ad (Jacobi: every row
+// reads the V of the previous substep).
+void diffusion_half(Sim* s, double t0) {
+  const int64_t n = s->n;
+  double* V = s->state.data();
+  int lmax = 0;
+  for (int x : s->l) lmax = std::max(lmax, x);
+  for (int m = 0; m < lmax; ++m) {
+    // stimulus rate per node at this substep
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) s->stim_rate[i] = 0.0;
+    for (const Stim& st : s->stims) {
+      for (int32_t i : st.nodes) {
+        int q = s->inst_of[i];
+        if (m >= s->l[q]) continue;
+        double tau = t0 + m * s->dt_ad[q];
+        if (st.t_on <= tau && tau < st.t_on + st.dur) s->stim_rate[i] += st.amp;
+      }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      int q = s->inst_of[i];
+      if (m >= s->l[q]) {
+        s->vtmp[i] = V[i];
+        continue;
+      }
+      double kv = 0.0;
+      for (int64_t p = s->rowptr[i]; p < s->rowptr[i + 1]; ++p) kv += s->val[p] * V[s->col[p]];
+      s->vtmp[i] = V[i] + s->dt_ad[q] * (-kv / s->mass[i] + s->stim_rate[i]);
+    }
+    std::memcpy(V, s->vtmp.data(), sizeof(double) * n);
+  }
+}
+
+// Step A at outer step n: every node picks k and advances its cell model by
+// dt in k substeps.  Activation time and sensors sample V at A-entry.
+void reaction(Sim* s, int64_t nstep) {
+  const int64_t n = s->n;
+  const int S = s->S, P = s->P;
+  const double dt = s->dt;
+  const double tA = nstep * dt + 0.5 * dt;   // time of the A-entry sample
+  if (s->sensor_buf && nstep < s->sensor_steps) {
+    for (size_t q = 0; q < s->sensors.size(); ++q)
+      s->sensor_buf[nstep * (int64_t)s->sensors.size() + q] = s->state[s->sensors[q]];
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double y[19], p[8];
+    for (int a = 0; a < S; ++a) y[a] = s->state[a * n + i];
+    for (int a = 0; a < P; ++a) p[a] = s->params[a * n + i];
+    const double Vb = y[0];
+    // dV/dt used by the k rule
+    double d;
+    if (s->dvdt_src == 0) {
+      d = (nstep == 0) ? 0.0 : (Vb - s->vprev[i]) / dt;
+    } else {
+      Rates r;
+      model_rates(s->model, y, p, r);
+      d = r.rate[0];
+    }
+    // activation: first upward crossing of the threshold between samples
+    if (nstep > 0 && s->lat[i] < 0.0 && s->vprev[i] < s->lat_thr && Vb >= s->lat_thr) {
+      double w = (s->lat_thr - s->vprev[i]) / (Vb - s->vprev[i]);
+      s->lat[i] = (tA - dt) + w * dt;
+    }
+    s->vprev[i] = Vb;
+    int k = k_rule(d, s->k_max);
+    if (s->ktrace_mode && nstep < s->ktrace_steps) {
+      uint8_t* kt = s->ktrace + nstep * n + i;
+      if (s->ktrace_mode == 1) {
+        *kt = (uint8_t)k;
+        if (s->dtrace) s->dtrace[nstep * n + i] = d;
+      } else {
+        k = *kt;
+      }
+    }
+    s->lastk[i] = k;
+    const double h = dt / k;
+    for (int sub = 0; sub < k; ++sub) cell_substep(s->model, y, p, h, s->vclamp);
+    for (int a = 0; a < S; ++a) s->state[a * n + i] = y[a];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface (ctypes)
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* orc_last_error() { return g_err.c_str(); }
+
+void* orc_create(int dim, int64_t n_nodes, const double* xyz, int etype, int64_t n_elems,
+                 const int32_t* conn, const double* D_elem, const double* sigma, int32_t n_inst,
+                 const int64_t* inst_node_off) {
+  if (dim < 1 || dim > 3 || n_nodes <= 0 || n_elems < 0 || etype != (1 << dim)) {
+    fail("bad mesh description");
+    return nullptr;
+  }
+  Sim* s = new Sim();
+  s->dim = dim;
+  s->nen = etype;
+  s->n = n_nodes;
+  const int nen = etype;
+  // assemble row by row into small sorted lists
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(n_nodes);
+  s->mass.assign(n_nodes, 0.0);
+  for (int64_t e = 0; e < n_elems; ++e) {
+    double X[24], Ke[64], me[8];
+    for (int a = 0; a < nen; ++a) {
+      int32_t g = conn[e * nen + a];
+      if (g < 0 || g >= n_nodes) {
+        delete s;
+        fail("connectivity index out of range");
+        return nullptr;
+      }
+      for (int d = 0; d < dim; ++d) X[a * dim + d] = xyz[(int64_t)g * dim + d];
+    }
+    if (element_matrices(dim, nen, X, D_elem + e * dim * dim, Ke, me) != 0) {
+      delete s;
+      fail("non-positive Jacobian");
+      return nullptr;
+    }
+    for (int a = 0; a < nen; ++a) {
+      int32_t ga = conn[e * nen + a];
+      s->mass[ga] += me[a];
+      for (int b = 0; b < nen; ++b) {
+        int32_t gb = conn[e * nen + b];
+        auto& row = rows[ga];
+        bool found = false;
+        for (auto& pr : row)
+          if (pr.first == gb) {
+            pr.second += Ke[a * nen + b];
+            found = true;
+            break;
+          }
+        if (!found) row.push_back({gb, Ke[a * nen + b]});
+      }
+    }
+  }
+  // per-node conductivity: off-diagonals scaled by (sigma_i + sigma_j)/2,
+  // diagonal reset so that every row sums to zero
+  s->rowptr.assign(n_nodes + 1, 0);
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    auto& row = rows[i];
+    std::sort(row.begin(), row.end());
+    s->rowptr[i + 1] = s->rowptr[i] + (int64_t)row.size();
+  }
+  s->col.resize(s->rowptr[n_nodes]);
+  s->val.resize(s->rowptr[n_nodes]);
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    int64_t p = s->rowptr[i];
+    double offsum = 0.0;
+    int64_t pdiag = -1;
+    for (auto& pr : rows[i]) {
+      s->col[p] = pr.first;
+      double v = pr.second;
+      if (pr.first == i) {
+        pdiag = p;
+      } else if (sigma) {
+        v *= 0.5 * (sigma[i] + sigma[pr.first]);
+      }
+      s->val[p] = v;
+      if (pr.first != i) offsum += v;
+      ++p;
+    }
+    if (sigma && pdiag >= 0) s->val[pdiag] = -offsum;
+  }
+  if (n_inst <= 1 || !inst_node_off) {
+    s->inst_off = {0, n_nodes};
+  } else {
+    s->inst_off.assign(inst_node_off, inst_node_off + n_inst + 1);
+  }
+  s->inst_of.assign(n_nodes, 0);
+  for (size_t q = 0; q + 1 < s->inst_off.size(); ++q)
+    for (int64_t i = s->inst_off[q]; i < s->inst_off[q + 1]; ++i) s->inst_of[i] = (int32_t)q;
+  s->vtmp.assign(n_nodes, 0.0);
+  s->stim_rate.assign(n_nodes, 0.0);
+  return s;
+}
+
+void orc_destroy(void* h) { delete (Sim*)h; }
+
+int64_t orc_nnz(void* h) { return ((Sim*)h)->rowptr.back(); }
+
+int orc_get_matrix(void* h, int64_t* rowptr, int32_t* col, double* val, double* mass) {
+  Sim* s = (Sim*)h;
+  std::memcpy(rowptr, s->rowptr.data(), sizeof(int64_t) * (s->n + 1));
+  std::memcpy(col, s->col.data(), sizeof(int32_t) * s->col.size());
+  std::memcpy(val, s->val.data(), sizeof(double) * s->val.size());
+  std::memcpy(mass, s->mass.data(), sizeof(double) * s->n);
+  return 0;
+}
+
+int orc_set_model(void* h, int model, int n_params, const double* params,
+                  const double* init_state, double dt0, double lat_thr) {
+  Sim* s = (Sim*)h;
+  if (model < 0 || model > 2) return fail("unknown model");
+  if (!(dt0 > 0.0)) return fail("dt0 must be positive");
+  s->model = model;
+  s->S = model_nstates(model);
+  s->P = model_nparams(model);
+  if (params && n_params != s->P) return fail("wrong parameter count");
+  const int64_t n = s->n;
+  s->state.assign((size_t)s->S * n, 0.0);
+  s->params.assign((size_t)s->P * n, 0.0);
+  if (init_state) {
+    std::memcpy(s->state.data(), init_state, sizeof(double) * s->S * n);
+  } else {
+    for (int a = 0; a < s->S; ++a) {
+      double v = 0.0;
+      if (model == M_MS) v = (a == 0) ? 0.0 : 1.0;
+      if (model == M_TP06) v = tp::INIT[a];
+      for (int64_t i = 0; i < n; ++i) s->state[a * n + i] = v;
+    }
+  }
+  if (params) {
+    std::memcpy(s->params.data(), params, sizeof(double) * s->P * n);
+  } else {
+    const double ms[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
+    const double tp6[6] = {5.4, 1, 1, 1, 1, 1};
+    const double lin[2] = {0.0, 0.0};
+    for (int a = 0; a < s->P; ++a) {
+      double v = model == M_MS ? ms[a] : (model == M_TP06 ? tp6[a] : lin[a]);
+      for (int64_t i = 0; i < n; ++i) s->params[a * n + i] = v;
+    }
+  }
+  s->vprev.assign(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) s->vprev[i] = s->state[i];
+  s->lat.assign(n, -1.0);
+  s->lastk.assign(n, 0);
+  s->dt0 = dt0;
+  s->lat_thr = lat_thr;
+  s->step = 0;
+  return 0;
+}
+
+int orc_add_stimulus(void* h, int64_t n, const int32_t* nodes, double t_on, double dur,
+                     double amp) {
+  Sim* s = (Sim*)h;
+  Stim st;
+  for (int64_t q = 0; q < n; ++q) {
+    if (nodes[q] < 0 || nodes[q] >= s->n) return fail("stimulus node out of range");
+    st.nodes.push_back(nodes[q]);
+  }
+  st.t_on = t_on;
+  st.dur = dur;
+  st.amp = amp;
+  s->stims.push_back(st);
+  return 0;
+}
+
+int orc_set_method(void* h, int method, int dvdt_src, int l_round) {
+  Sim* s = (Sim*)h;
+  if (method < 0 || method > 2 || dvdt_src < 0 || dvdt_src > 1 || l_round < 0 || l_round > 1)
+    return fail("bad method flags");
+  s->method = method;
+  s->dvdt_src = dvdt_src;
+  s->l_round = l_round;
+  if (s->dt > 0.0) return prepare(s, s->dt);
+  return 0;
+}
+
+int orc_prepare(void* h, double dt) { return prepare((Sim*)h, dt); }
+
+// out: dt_s, G_max, l, dt_ad, k_max, t, step
+int orc_info(void* h, int inst, double* out) {
+  Sim* s = (Sim*)h;
+  if (s->dt <= 0.0) return fail("not prepared");
+  if (inst < 0 || inst >= (int)s->l.size()) return fail("bad instance");
+  out[0] = s->dt_s[inst];
+  out[1] = s->gmax[inst];
+  out[2] = s->l[inst];
+  out[3] = s->dt_ad[inst];
+  out[4] = s->k_max;
+  out[5] = s->step * s->dt;
+  out[6] = (double)s->step;
+  return 0;
+}
+
+int orc_step(void* h, int64_t n_steps, double dt) {
+  Sim* s = (Sim*)h;
+  if (s->model < 0) return fail("no cell model");
+  if (s->dt != dt) {
+    if (prepare(s, dt) != 0) return -1;
+  }
+  for (int64_t q = 0; q < n_steps; ++q) {
+    const int64_t n = s->step;
+    const double tn = n * dt;
+    diffusion_half(s, tn);
+    reaction(s, n);
+    diffusion_half(s, tn + 0.5 * dt);
+    s->step = n + 1;
+  }
+  return 0;
+}
+
+// fields: 0 V, 1 V_prev, 2 LAT, 3 last k, 16 + j state j
+int orc_get_field(void* h, int field, double* out) {
+  Sim* s = (Sim*)h;
+  const int64_t n = s->n;
+  if (field == 0) std::memcpy(out, s->state.data(), sizeof(double) * n);
+  else if (field == 1) std::memcpy(out, s->vprev.data(), sizeof(double) * n);
+  else if (field == 2) std::memcpy(out, s->lat.data(), sizeof(double) * n);
+  else if (field == 3) for (int64_t i = 0; i < n; ++i) out[i] = s->lastk[i];
+  else if (field >= 16 && field < 16 + s->S)
+    std::memcpy(out, s->state.data() + (int64_t)(field - 16) * n, sizeof(double) * n);
+  else return fail("bad field");
+  return 0;
+}
+
+int orc_set_field(void* h, int field, const double* in) {
+  Sim* s = (Sim*)h;
+  const int64_t n = s->n;
+  if (field == 0) std::memcpy(s->state.data(), in, sizeof(double) * n);
+  else if (field == 1) std::memcpy(s->vprev.data(), in, sizeof(double) * n);
+  else if (field == 2) std::memcpy(s->lat.data(), in, sizeof(double) * n);
+  else if (field >= 16 && field < 16 + s->S)
+    std::memcpy(s->state.data() + (int64_t)(field - 16) * n, in, sizeof(double) * n);
+  else return fail("bad field");
+  return 0;
+}
+
+int orc_set_step(void* h, int64_t step) {
+  ((Sim*)h)->step = step;
+  return 0;
+}
+
+// mode 0 off, 1 record k (and dV/dt if dbuf), 2 replay k.  buf: n_steps * n.
+int orc_set_ktrace(void* h, int mode, uint8_t* buf, double* dbuf, int64_t n_steps) {
+  Sim* s = (Sim*)h;
+  s->ktrace_mode = mode;
+  s->ktrace = buf;
+  s->dtrace = dbuf;
+  s->ktrace_steps = n_steps;
+  return 0;
+}
+
+int orc_set_sensors(void* h, int32_t n, const int32_t* nodes, double* buf, int64_t n_steps) {
+  Sim* s = (Sim*)h;
+  s->sensors.assign(nodes, nodes + n);
+  s->sensor_buf = buf;
+  s->sensor_steps = n_steps;
+  return 0;
+}
+
+int orc_set_vclamp(void* h, int on) {
+  ((Sim*)h)->vclamp = on;
+  return 0;
+}
+
+// --- cell-level helpers ------------------------------------------------------
+int orc_model_nstates(int model) { return model_nstates(model); }
+int orc_model_nparams(int model) { return model_nparams(model); }
+
+int orc_model_init(int model, double* y) {
+  const int S = model_nstates(model);
+  for (int a = 0; a < S; ++a)
+    y[a] = model == M_TP06 ? tp::INIT[a] : (model == M_MS ? (a == 0 ? 0.0 : 1.0) : 0.0);
+  return 0;
+}
+
+// Advance one cell by `dt` in k substeps (k frozen).
+int orc_cell_advance(int model, const double* p, double* y, int k, double dt, int vclamp) {
+  if (k < 1) return fail("k must be >= 1");
+  for (int q = 0; q < k; ++q) cell_substep(model, y, p, dt / k, vclamp);
+  return 0;
+}
+
+// Rates at a state: out_rate[S], out_inf[S], out_tau[S], out_gate[S]
+int orc_cell_rates(int model, const double* p, const double* y, double* rate, double* inf,
+                   double* tau, int32_t* gate) {
+  Rates r;
+  model_rates(model, y, p, r);
+  const int S = model_nstates(model);
+  for (int a = 0; a < S; ++a) {
+    gate[a] = r.is_gate[a];
+    rate[a] = r.is_gate[a] ? 0.0 : r.rate[a];
+    inf[a] = r.is_gate[a] ? r.inf[a] : 0.0;
+    tau[a] = r.is_gate[a] ? r.tau[a] : 0.0;
+  }
+  return 0;
+}
+
+// TP06 currents: INa IK1 Ito IKr IKs ICaL INaCa INaK IpCa IpK IbNa IbCa Irel Iup Ileak Ixfer Iion
+int orc_tp06_currents(const double* p, const double* y, double* out) {
+  TPCurrents c;
+  tp06_currents(y, p, c);
+  const double v[17] = {c.INa,  c.IK1,  c.Ito,  c.IKr,  c.IKs, c.ICaL, c.INaCa, c.INaK, c.IpCa,
+                        c.IpK,  c.IbNa, c.IbCa, c.Irel, c.Iup, c.Ileak, c.Ixfer, c.Iion};
+  for (int a = 0; a < 17; ++a) out[a] = v[a];
+  return 0;
+}
+
+int orc_k_rule(double dvdt, int k_max) { return k_rule(dvdt, k_max); }
+int orc_l_rule(double dt, double dt_s, int l_round) { return l_rule(dt, dt_s, l_round); }
+
+}  // extern "C"

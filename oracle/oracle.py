@@ -1,0 +1,264 @@
+"""ctypes wrapper of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg use
+this module.  It loads oracle/liboracle.so (built by oracle/build.py from
+oracle/oracle.cpp) and never touches the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+F_V, F_VPREV, F_LAT, F_K, F_STATE0 = 0, 1, 2, 3, 16
+DAETI, OSTAR, OST = 0, 1, 2
+
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_bp = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            import importlib.util
+            spec = importlib.util.spec_from_file_location("oracle_build", os.path.join(HERE, "build.py"))
+            m = importlib.util.module_from_spec(spec)
+            spec.loader.exec_module(m)
+            m.build()
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.orc_last_error.restype = C.c_char_p
+        L.orc_create.restype = vp
+        L.orc_create.argtypes = [C.c_int, C.c_int64, _dp, C.c_int, C.c_int64, _ip, _dp, vp,
+                                 C.c_int32, vp]
+        L.orc_destroy.argtypes = [vp]
+        L.orc_nnz.restype = C.c_int64
+        L.orc_nnz.argtypes = [vp]
+        L.orc_get_matrix.argtypes = [vp, _lp, _ip, _dp, _dp]
+        L.orc_set_model.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_double, C.c_double]
+        L.orc_add_stimulus.argtypes = [vp, C.c_int64, _ip, C.c_double, C.c_double, C.c_double]
+        L.orc_set_method.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.orc_prepare.argtypes = [vp, C.c_double]
+        L.orc_info.argtypes = [vp, C.c_int, _dp]
+        L.orc_step.argtypes = [vp, C.c_int64, C.c_double]
+        L.orc_get_field.argtypes = [vp, C.c_int, _dp]
+        L.orc_set_field.argtypes = [vp, C.c_int, _dp]
+        L.orc_set_step.argtypes = [vp, C.c_int64]
+        L.orc_set_ktrace.argtypes = [vp, C.c_int, vp, vp, C.c_int64]
+        L.orc_set_sensors.argtypes = [vp, C.c_int32, _ip, vp, C.c_int64]
+        L.orc_set_vclamp.argtypes = [vp, C.c_int]
+        L.orc_model_nstates.argtypes = [C.c_int]
+        L.orc_model_nparams.argtypes = [C.c_int]
+        L.orc_model_init.argtypes = [C.c_int, _dp]
+        L.orc_cell_advance.argtypes = [C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int]
+        L.orc_cell_rates.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _ip]
+        L.orc_tp06_currents.argtypes = [_dp, _dp, _dp]
+        L.orc_k_rule.argtypes = [C.c_double, C.c_int]
+        L.orc_l_rule.argtypes = [C.c_double, C.c_double, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError("oracle: " + lib().orc_last_error().decode())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Oracle:
+    """One FP64 CPU simulation of a workload (mesh + cell model + stimuli)."""
+
+    def __init__(self, mesh, model=None, params=None, init_state=None, dt0=0.01,
+                 lat_threshold=0.0, stimuli=(), method=DAETI, dvdt_source=0,
+                 l_round=0):
+        L = lib()
+        self.mesh = mesh
+        self.n = mesh.n_nodes
+        xyz = _f64(mesh.xyz)
+        conn = _i32(mesh.conn)
+        D = _f64(mesh.D_elem)
+        self._keep = [xyz, conn, D]
+        sig = None
+        if mesh.sigma is not None:
+            sig = _f64(mesh.sigma)
+            self._keep.append(sig)
+        off = None
+        ni = 1
+        if mesh.inst_node_off is not None:
+            off = np.ascontiguousarray(mesh.inst_node_off, dtype=np.int64)
+            self._keep.append(off)
+            ni = len(off) - 1
+        h = L.orc_create(mesh.dim, self.n, xyz, mesh.etype, mesh.n_elems, conn, D,
+                         None if sig is None else sig.ctypes.data, ni,
+                         None if off is None else off.ctypes.data)
+        if not h:
+            raise RuntimeError("oracle: " + L.orc_last_error().decode())
+        self.h = h
+        self.n_inst = ni
+        self.model = None
+        if model is not None:
+            self.set_model(model, params, init_state, dt0, lat_threshold)
+        for st in stimuli:
+            self.add_stimulus(st.nodes, st.t_on, st.duration, st.amplitude)
+        if method != DAETI or dvdt_source or l_round:
+            self.set_method(method, dvdt_source, l_round)
+        self._ktrace = None
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w.mesh, w.model, w.params, None, w.dt0, w.lat_threshold, w.stimuli, **kw)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    # -- setup ---------------------------------------------------------------
+    def set_model(self, model, params=None, init_state=None, dt0=0.01, lat_threshold=0.0):
+        L = lib()
+        self.model = model
+        self.S = L.orc_model_nstates(model)
+        self.P = L.orc_model_nparams(model)
+        p = None if params is None else _f64(params).reshape(self.P, self.n)
+        y0 = None if init_state is None else _f64(init_state).reshape(self.S, self.n)
+        self._p, self._y0 = p, y0
+        _check(L.orc_set_model(self.h, model, self.P, None if p is None else p.ctypes.data,
+                               None if y0 is None else y0.ctypes.data, dt0, lat_threshold))
+
+    def add_stimulus(self, nodes, t_on, duration, amplitude):
+        nodes = _i32(nodes)
+        _check(lib().orc_add_stimulus(self.h, len(nodes), nodes, t_on, duration, amplitude))
+
+    def set_method(self, method=DAETI, dvdt_source=0, l_round=0):
+        _check(lib().orc_set_method(self.h, method, dvdt_source, l_round))
+
+    def prepare(self, dt):
+        _check(lib().orc_prepare(self.h, dt))
+
+    def info(self, inst=0):
+        out = np.zeros(7)
+        _check(lib().orc_info(self.h, inst, out))
+        return dict(dt_s=out[0], G_max=out[1], l=int(out[2]), dt_ad=out[3], k_max=int(out[4]),
+                    t=out[5], step=int(out[6]))
+
+    def matrix(self):
+        """(rowptr, col, val, mass) of the assembled K (with diagonal) and lumped M."""
+        nnz = lib().orc_nnz(self.h)
+        rp = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz, np.float64)
+        m = np.zeros(self.n, np.float64)
+        _check(lib().orc_get_matrix(self.h, rp, col, val, m))
+        return rp, col, val, m
+
+    def dense_K(self):
+        rp, col, val, m = self.matrix()
+        K = np.zeros((self.n, self.n))
+        for i in range(self.n):
+            K[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+        return K, m
+
+    # -- stepping --------------------------------------------------------------
+    def step(self, n_steps, dt):
+        _check(lib().orc_step(self.h, int(n_steps), float(dt)))
+
+    def get(self, field):
+        out = np.zeros(self.n)
+        _check(lib().orc_get_field(self.h, int(field), out))
+        return out
+
+    def set(self, field, values):
+        _check(lib().orc_set_field(self.h, int(field), _f64(values)))
+
+    def state(self, j):
+        return self.get(F_STATE0 + j)
+
+    def set_step(self, step):
+        _check(lib().orc_set_step(self.h, int(step)))
+
+    def set_vclamp(self, on):
+        _check(lib().orc_set_vclamp(self.h, int(on)))
+
+    def record_k(self, n_steps, with_d=False):
+        """Record the k chosen by every node at every step (and dV/dt)."""
+        kb = np.zeros((n_steps, self.n), np.uint8)
+        db = np.zeros((n_steps, self.n), np.float64) if with_d else None
+        self._ktrace = (kb, db)
+        _check(lib().orc_set_ktrace(self.h, 1, kb.ctypes.data,
+                                    None if db is None else db.ctypes.data, n_steps))
+        return kb, db
+
+    def replay_k(self, ktrace):
+        kb = np.ascontiguousarray(ktrace, dtype=np.uint8)
+        self._ktrace = (kb, None)
+        _check(lib().orc_set_ktrace(self.h, 2, kb.ctypes.data, None, kb.shape[0]))
+
+    def ktrace_off(self):
+        _check(lib().orc_set_ktrace(self.h, 0, None, None, 0))
+        self._ktrace = None
+
+    def record_sensors(self, nodes, n_steps):
+        nodes = _i32(nodes)
+        buf = np.zeros((n_steps, len(nodes)), np.float64)
+        self._sens = (nodes, buf)
+        _check(lib().orc_set_sensors(self.h, len(nodes), nodes, buf.ctypes.data, n_steps))
+        return buf
+
+
+# -- cell-level helpers ----------------------------------------------------------
+def model_nstates(model):
+    return lib().orc_model_nstates(model)
+
+
+def model_init(model):
+    y = np.zeros(model_nstates(model))
+    lib().orc_model_init(model, y)
+    return y
+
+
+def cell_advance(model, params, y, k, dt, vclamp=False):
+    y = _f64(y).copy()
+    _check(lib().orc_cell_advance(model, _f64(params), y, int(k), float(dt), int(vclamp)))
+    return y
+
+
+def cell_rates(model, params, y):
+    S = model_nstates(model)
+    rate, inf, tau = np.zeros(S), np.zeros(S), np.zeros(S)
+    gate = np.zeros(S, np.int32)
+    _check(lib().orc_cell_rates(model, _f64(params), _f64(y), rate, inf, tau, gate))
+    return rate, inf, tau, gate.astype(bool)
+
+
+TP06_CURRENTS = ("INa", "IK1", "Ito", "IKr", "IKs", "ICaL", "INaCa", "INaK", "IpCa", "IpK",
+                 "IbNa", "IbCa", "Irel", "Iup", "Ileak", "Ixfer", "Iion")
+
+
+def tp06_currents(params, y):
+    out = np.zeros(17)
+    _check(lib().orc_tp06_currents(_f64(params), _f64(y), out))
+    return dict(zip(TP06_CURRENTS, out))
+
+
+def k_rule(dvdt, k_max):
+    return lib().orc_k_rule(float(dvdt), int(k_max))
+
+
+def l_rule(dt, dt_s, l_round=0):
+    return lib().orc_l_rule(float(dt), float(dt_s), int(l_round))

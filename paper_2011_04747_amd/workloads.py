@@ -1,0 +1,355 @@
+"""Seeded synthetic inputs for the DAETI monodomain solver.
+
+This module only *describes* problems: node coordinates, element
+connectivity, per-element diffusion tensors, per-node conductivity and
+ionic-parameter fields, stimulus node sets and run lengths.  It contains none
+of the solver's arithmetic (no assembly, no time stepping, no cell model), so
+that the FP64 CPU oracle and the HIP path can both consume exactly the same
+arrays without sharing any numerical code.
+
+Element node ordering (both sides rely on it):
+  * line2: x-, x+
+  * quad4: (0,0) (1,0) (1,1) (0,1)                        counter-clockwise
+  * hex8 : the quad4 face at z-, then the quad4 face at z+
+
+Node numbering of structured grids is lexicographic, x fastest:
+  node(ix, iy, iz) = ix + nx*(iy + ny*iz).
+
+The diffusion tensor of every element is D_t*I + (D_l - D_t)*f f^T with f the
+unit fibre direction at the element centroid (monodomain eq. 1, tensor D; the
+paper's 2D sheets use d0 and the transverse ratio rho the same way, Sec. 3.1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# cell-model identifiers (shared vocabulary of both sides' Python wrappers)
+MODEL_LINEAR = 0
+MODEL_MS = 1
+MODEL_TP06 = 2
+
+ETYPE_LINE2 = 2
+ETYPE_QUAD4 = 4
+ETYPE_HEX8 = 8
+
+# Per-node TP06 parameter rows (SoA): extracellular K+ and five conductance
+# scalings.  Defaults are the published epicardial values (Ko = 5.4 mM,
+# scalings 1).
+TP06_PARAM_NAMES = ("Ko", "gNa", "gCaL", "gKr", "gKs", "gK1")
+TP06_PARAM_DEFAULT = (5.4, 1.0, 1.0, 1.0, 1.0, 1.0)
+# Mitchell-Schaeffer parameters (ms), in this row order.
+MS_PARAM_NAMES = ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate")
+MS_PARAM_DEFAULT = (0.3, 6.0, 120.0, 150.0, 0.13)
+LINEAR_PARAM_NAMES = ("g", "E")
+
+# Stimulus amplitudes, dV/dt units (1/ms for Mitchell-Schaeffer, mV/ms for
+# TP06): twice the diastolic threshold of each protocol's stimulus region
+# (Sec. 3.1: 1 ms pulse at twice diastolic threshold).  The thresholds were
+# found by bisection with the FP64 CPU oracle; the script that does so and the
+# values it wrote live under tests/golden/ (calibrate_stimulus.py,
+# stim_thresholds.json) and a test checks these constants against that file.
+STIM_AMP_MS_CABLE = 2.0 * 0.07343750000000002
+STIM_AMP_TP06_CORNER = 2.0 * 25.0
+STIM_AMP_TP06_PLANAR = 2.0 * 28.28125
+
+
+@dataclasses.dataclass
+class Stimulus:
+    nodes: np.ndarray        # int32 node indices
+    t_on: float              # ms
+    duration: float          # ms
+    amplitude: float         # dV/dt units
+
+
+@dataclasses.dataclass
+class Mesh:
+    dim: int
+    xyz: np.ndarray                  # (n_nodes, dim) float64, cm
+    etype: int                       # 2, 4 or 8 nodes per element
+    conn: np.ndarray                 # (n_elems, etype) int32
+    D_elem: np.ndarray               # (n_elems, dim, dim) float64, cm^2/ms
+    sigma: Optional[np.ndarray] = None         # (n_nodes,) conductivity scale
+    inst_node_off: Optional[np.ndarray] = None  # (n_inst+1,) int64
+    inst_elem_off: Optional[np.ndarray] = None  # (n_inst+1,) int64
+    grid_shape: Optional[Tuple[int, ...]] = None
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.conn.shape[0])
+
+    @property
+    def n_instances(self) -> int:
+        return 1 if self.inst_node_off is None else len(self.inst_node_off) - 1
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    model: int
+    params: Optional[np.ndarray]     # (n_params, n_nodes) float64, SoA
+    stimuli: List[Stimulus]
+    dt: float                        # ms, outer split step
+    t_end: float                     # ms
+    dt0: float                       # ms, largest stable cell-model step
+    precision: str                   # "f64" or "f32"
+    lat_threshold: float
+    sensors: Optional[np.ndarray] = None
+    extra: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_steps(self) -> int:
+        return int(round(self.t_end / self.dt))
+
+
+# ---------------------------------------------------------------------------
+# structured grids
+# ---------------------------------------------------------------------------
+def structured_grid(shape: Tuple[int, ...], h: float | Tuple[float, ...]):
+    """Regular grid of Q1 elements: returns (xyz, conn, etype)."""
+    dim = len(shape)
+    hs = (h,) * dim if np.isscalar(h) else tuple(h)
+    axes = [np.arange(n, dtype=np.float64) * hh for n, hh in zip(shape, hs)]
+    mg = np.meshgrid(*axes[::-1], indexing="ij")[::-1]   # x fastest
+    xyz = np.stack([m.reshape(-1) for m in mg], axis=1)
+    if dim == 1:
+        (nx,) = shape
+        i = np.arange(nx - 1)
+        conn = np.stack([i, i + 1], axis=1)
+        et = ETYPE_LINE2
+    elif dim == 2:
+        nx, ny = shape
+        ix, iy = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), indexing="xy")
+        ix = ix.reshape(-1); iy = iy.reshape(-1)
+        n00 = ix + nx * iy
+        conn = np.stack([n00, n00 + 1, n00 + 1 + nx, n00 + nx], axis=1)
+        et = ETYPE_QUAD4
+    elif dim == 3:
+        nx, ny, nz = shape
+        iz, iy, ix = np.meshgrid(np.arange(nz - 1), np.arange(ny - 1),
+                                 np.arange(nx - 1), indexing="ij")
+        ix = ix.reshape(-1); iy = iy.reshape(-1); iz = iz.reshape(-1)
+        b = ix + nx * (iy + ny * iz)
+        pl = nx * ny
+        conn = np.stack([b, b + 1, b + 1 + nx, b + nx,
+                         b + pl, b + pl + 1, b + pl + 1 + nx, b + pl + nx], axis=1)
+        et = ETYPE_HEX8
+    else:
+        raise ValueError("dim must be 1, 2 or 3")
+    return xyz, conn.astype(np.int32), et
+
+
+def centroids(xyz: np.ndarray, conn: np.ndarray) -> np.ndarray:
+    return xyz[conn].mean(axis=1)
+
+
+def fibre_tensor(f: np.ndarray, D_l: float, D_t: float) -> np.ndarray:
+    """Per-element tensors D_t I + (D_l - D_t) f f^T for unit fibres f (E, d)."""
+    d = f.shape[1]
+    return D_t * np.eye(d)[None] + (D_l - D_t) * f[:, :, None] * f[:, None, :]
+
+
+def angle_fibres(theta: np.ndarray, dim: int) -> np.ndarray:
+    f = np.zeros((theta.shape[0], dim))
+    f[:, 0] = np.cos(theta)
+    if dim > 1:
+        f[:, 1] = np.sin(theta)
+    return f
+
+
+def gaussian_random_field(shape: Tuple[int, ...], dx: float, corr_len: float,
+                          seed: int) -> np.ndarray:
+    """Zero-mean, unit-variance field with covariance exp(-r^2 / (2 l^2)).
+
+    White noise is smoothed by a Gaussian kernel of standard deviation l/sqrt(2)
+    (reflecting boundaries) and then standardised.  Returned flat, x fastest.
+    """
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(shape[::-1])                  # index [z][y][x]
+    s = corr_len / math.sqrt(2.0) / dx
+    g = gaussian_filter(w, sigma=s, mode="reflect")
+    g = (g - g.mean()) / g.std()
+    return g.reshape(-1)
+
+
+def lognormal_scale(g: np.ndarray, s: float) -> np.ndarray:
+    """exp(s g - s^2/2): unit-mean log-normal scale from a standard field."""
+    return np.exp(s * g - 0.5 * s * s)
+
+
+def _default_params(names_defaults, n_nodes: int) -> np.ndarray:
+    return np.tile(np.asarray(names_defaults, dtype=np.float64)[:, None], (1, n_nodes))
+
+
+def tp06_params(n_nodes: int) -> np.ndarray:
+    return _default_params(TP06_PARAM_DEFAULT, n_nodes)
+
+
+def ms_params(n_nodes: int) -> np.ndarray:
+    return _default_params(MS_PARAM_DEFAULT, n_nodes)
+
+
+# ---------------------------------------------------------------------------
+# the five workloads (and shrinkable variants with the same structure)
+# ---------------------------------------------------------------------------
+def cable_ms(n_nodes: int = 101, length: float = 1.0, D: float = 0.001,
+             t_end: float = 100.0, dt: float = 0.1, stim_len: float = 0.05,
+             amp: Optional[float] = None) -> Workload:
+    """1D Mitchell-Schaeffer cable, zero-flux ends, FP64 (the parity case)."""
+    h = length / (n_nodes - 1)
+    xyz, conn, et = structured_grid((n_nodes,), h)
+    De = np.full((conn.shape[0], 1, 1), D)
+    mesh = Mesh(1, xyz, et, conn, De, grid_shape=(n_nodes,))
+    nodes = np.nonzero(xyz[:, 0] <= stim_len + 1e-12)[0].astype(np.int32)
+    a = STIM_AMP_MS_CABLE if amp is None else amp
+    return Workload("cable_ms_1d", mesh, MODEL_MS, ms_params(n_nodes),
+                    [Stimulus(nodes, 0.0, 2.0, a)], dt, t_end, 0.01, "f64", 0.5)
+
+
+def _corner_stimulus(xyz: np.ndarray, radius: float, amp: float) -> Stimulus:
+    r2 = xyz[:, 0] ** 2 + xyz[:, 1] ** 2
+    nodes = np.nonzero(r2 <= radius * radius + 1e-12)[0].astype(np.int32)
+    return Stimulus(nodes, 0.0, 1.0, amp)
+
+
+def sheet_tp06(n: int = 201, dx: float = 0.025, D_l: float = 0.0012,
+               D_t: float = 0.0003, theta_max_deg: float = 60.0,
+               t_end: float = 500.0, dt: float = 0.1, precision: str = "f64",
+               amp: Optional[float] = None) -> Workload:
+    """2D TP06 sheet, fibre angle rising linearly 0 -> 60 deg along x."""
+    xyz, conn, et = structured_grid((n, n), dx)
+    c = centroids(xyz, conn)
+    width = (n - 1) * dx
+    theta = np.deg2rad(theta_max_deg) * c[:, 0] / width
+    De = fibre_tensor(angle_fibres(theta, 2), D_l, D_t)
+    mesh = Mesh(2, xyz, et, conn, De, grid_shape=(n, n))
+    a = STIM_AMP_TP06_CORNER if amp is None else amp
+    return Workload("sheet_tp06_2d", mesh, MODEL_TP06, tp06_params(mesh.n_nodes),
+                    [_corner_stimulus(xyz, 0.25, a)], dt, t_end, 0.01,
+                    precision, -40.0)
+
+
+def _slab(shape, dx, D_l, D_t, thickness):
+    xyz, conn, et = structured_grid(shape, dx)
+    c = centroids(xyz, conn)
+    theta = np.deg2rad(-60.0 + 120.0 * c[:, 2] / thickness)
+    De = fibre_tensor(angle_fibres(theta, 3), D_l, D_t)
+    return Mesh(3, xyz, et, conn, De, grid_shape=tuple(shape))
+
+
+def _planar_s1(xyz, amp, depth=0.05, t_on=0.0):
+    nodes = np.nonzero(xyz[:, 0] <= depth + 1e-12)[0].astype(np.int32)
+    return Stimulus(nodes, t_on, 1.0, amp)
+
+
+def ischemic_zone(xyz: np.ndarray, size_xy: Tuple[float, float], z_mid: float,
+                  semi=(0.4, 0.3, 0.25), seed: int = 3) -> np.ndarray:
+    """Boolean mask of nodes in a seeded, z-rotated ellipsoid."""
+    rng = np.random.default_rng(seed)
+    cx = rng.uniform(0.25 * size_xy[0], 0.75 * size_xy[0])
+    cy = rng.uniform(0.25 * size_xy[1], 0.75 * size_xy[1])
+    ang = rng.uniform(0.0, math.pi)
+    dx_ = xyz[:, 0] - cx
+    dy_ = xyz[:, 1] - cy
+    dz_ = xyz[:, 2] - z_mid
+    u = math.cos(ang) * dx_ + math.sin(ang) * dy_
+    v = -math.sin(ang) * dx_ + math.cos(ang) * dy_
+    return (u / semi[0]) ** 2 + (v / semi[1]) ** 2 + (dz_ / semi[2]) ** 2 <= 1.0
+
+
+def slab_ischemic(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,
+                  D_t: float = 0.0003, t_end: float = 1000.0, dt: float = 0.1,
+                  s2_time: float = 320.0, precision: str = "f32",
+                  amp: Optional[float] = None) -> Workload:
+    """3D TP06 slab with an ischemic ellipsoid, S1 at x=0 and cross-field S2."""
+    thickness = (shape[2] - 1) * dx
+    mesh = _slab(shape, dx, D_l, D_t, thickness)
+    xyz = mesh.xyz
+    p = tp06_params(mesh.n_nodes)
+    Lx, Ly = (shape[0] - 1) * dx, (shape[1] - 1) * dx
+    isc = ischemic_zone(xyz, (Lx, Ly), 0.5 * thickness,
+                        semi=(0.4 * Lx / 2.0, 0.3 * Ly / 2.0, 0.25 * thickness / 0.5))
+    p[0, isc] = 8.0           # [K+]o, mM
+    p[1, isc] = 0.7           # g_Na scaling
+    a = STIM_AMP_TP06_PLANAR if amp is None else amp
+    s1 = _planar_s1(xyz, a)
+    s2n = np.nonzero((xyz[:, 0] <= 0.25 * Lx + 1e-12) &
+                     (xyz[:, 1] <= 0.5 * Ly + 1e-12))[0].astype(np.int32)
+    s2 = Stimulus(s2n, s2_time, 1.0, a)
+    return Workload("slab_tp06_3d_ischemic", mesh, MODEL_TP06, p, [s1, s2], dt,
+                    t_end, 0.01, precision, -40.0,
+                    extra={"ischemic_nodes": int(isc.sum())})
+
+
+def batched_sheets(n_inst: int = 64, side_lo: int = 50, side_hi: int = 400,
+                   dx: float = 0.025, D_l: float = 0.0012, D_t: float = 0.0003,
+                   t_end: float = 400.0, dt: float = 0.1, seed: int = 4,
+                   precision: str = "f32", amp: Optional[float] = None) -> Workload:
+    """Independent 2D TP06 sheets of seeded uneven sizes, concatenated.
+
+    Instance i has s_x x s_y nodes (each side uniform on side_lo..side_hi), a
+    log-normal conductivity field (s = 0.3, correlation length 0.5 cm, seed
+    4000+i) and its own g_Na, g_Kr, g_CaL scalings ~ U(0.5, 1.5).
+    """
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, size=(n_inst, 2))
+    scal = rng.uniform(0.5, 1.5, size=(n_inst, 3))
+    xyzs, conns, Ds, sigmas, params = [], [], [], [], []
+    node_off = [0]
+    elem_off = [0]
+    stim_nodes = []
+    a = STIM_AMP_TP06_CORNER if amp is None else amp
+    for i in range(n_inst):
+        sx, sy = int(sides[i, 0]), int(sides[i, 1])
+        xyz, conn, et = structured_grid((sx, sy), dx)
+        c = centroids(xyz, conn)
+        theta = np.deg2rad(60.0) * c[:, 0] / ((sx - 1) * dx)
+        Ds.append(fibre_tensor(angle_fibres(theta, 2), D_l, D_t))
+        g = gaussian_random_field((sx, sy), dx, 0.5, 4000 + i)
+        sigmas.append(lognormal_scale(g, 0.3))
+        p = tp06_params(sx * sy)
+        p[1] = scal[i, 0]   # g_Na
+        p[3] = scal[i, 1]   # g_Kr
+        p[2] = scal[i, 2]   # g_CaL
+        params.append(p)
+        st = _corner_stimulus(xyz, 0.25, a)
+        stim_nodes.append(st.nodes + node_off[-1])
+        xyzs.append(xyz)
+        conns.append(conn + node_off[-1])
+        node_off.append(node_off[-1] + sx * sy)
+        elem_off.append(elem_off[-1] + conn.shape[0])
+    mesh = Mesh(2, np.concatenate(xyzs), ETYPE_QUAD4, np.concatenate(conns).astype(np.int32),
+                np.concatenate(Ds), np.concatenate(sigmas),
+                np.asarray(node_off, np.int64), np.asarray(elem_off, np.int64))
+    stim = Stimulus(np.concatenate(stim_nodes).astype(np.int32), 0.0, 1.0, a)
+    return Workload("batched_tp06_2d", mesh, MODEL_TP06, np.concatenate(params, axis=1),
+                    [stim], dt, t_end, 0.01, precision, -40.0,
+                    extra={"sides": sides, "scalings": scal})
+
+
+def adjoint_slab(shape=(101, 101, 26), dx: float = 0.01, D_l: float = 0.0012,
+                 D_t: float = 0.0003, t_end: float = 300.0, dt: float = 0.1,
+                 n_sensors: int = 512, precision: str = "f32",
+                 amp: Optional[float] = None) -> Workload:
+    """3D TP06 slab for the adjoint: sensors, perturbed-conductivity target."""
+    thickness = (shape[2] - 1) * dx
+    mesh = _slab(shape, dx, D_l, D_t, thickness)
+    rng = np.random.default_rng(5)
+    sensors = np.sort(rng.choice(mesh.n_nodes, size=min(n_sensors, mesh.n_nodes),
+                                 replace=False)).astype(np.int32)
+    g = gaussian_random_field(tuple(shape), dx, 0.5, 55)
+    sigma_target = lognormal_scale(g, 0.1)
+    a = STIM_AMP_TP06_PLANAR if amp is None else amp
+    return Workload("adjoint_tp06_3d", mesh, MODEL_TP06, tp06_params(mesh.n_nodes),
+                    [_planar_s1(mesh.xyz, a)], dt, t_end, 0.01, precision, -40.0,
+                    sensors=sensors, extra={"sigma_target": sigma_target,
+                                            "ckpt_every": 50})
