@@ -1,0 +1,244 @@
+/*
+ * mono.h - C interface of libmono, an MI355X (gfx950) implementation of the
+ * dual adaptive explicit time integration (DAETI) method for the cardiac
+ * monodomain equation (Mountris & Pueyo, "A dual adaptive explicit time
+ * integration algorithm for efficiently solving the cardiac monodomain
+ * equation").
+ *
+ * Problem (paper Sec. 2, eq. 1):  dV/dt = -I_ion(V, y)/C + div(D grad V) in
+ * Omega, with zero flux on the boundary.  Strang splitting (Sec. 2, eq. 2)
+ * advances one outer step dt as B(dt/2) A(dt) B(dt/2):
+ *   B: l forward Euler substeps of dt_ad = dt/(2l) of dV/dt = -M_L^-1 K V + s,
+ *      with l from the Gershgorin step dt_s of eq. (3);
+ *   A: every node advances its cell model with its own k substeps of dt/k,
+ *      k = min(k0 + floor|dV/dt|, k_max), k0 = 5 if dV/dt > 0 else 1,
+ *      k_max = floor(dt/dt0); gates by Rush-Larsen, the rest forward Euler.
+ *
+ * Conventions for every function:
+ *   - The return value is a mono_status; MONO_OK is 0.  On failure
+ *     mono_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).  No C++ exception crosses this interface.
+ *   - NULL handles, NULL required pointers and bad sizes give MONO_EINVAL.
+ *   - Host arrays passed in are read during the call only (copied); the
+ *     library never keeps a pointer to caller memory except device buffers
+ *     explicitly registered through mono_debug().
+ *   - Device memory of a simulation is owned by the library and released by
+ *     mono_destroy().  The HIP stream given at creation is borrowed: every
+ *     kernel and copy of the simulation is enqueued on it.
+ *   - Functions whose name says "async" only enqueue work; the others
+ *     synchronise the stream before returning.
+ *   - A non-finite V seen by the reaction kernel latches the simulation; the
+ *     next synchronising call returns MONO_ENONFINITE and later stepping
+ *     returns MONO_ESTATE until mono_set_state() rewrites V.
+ *   - A simulation is not thread-safe; distinct simulations are independent.
+ */
+#ifndef MONO_H
+#define MONO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mono_sim mono_sim;
+
+typedef enum {
+  MONO_OK = 0,
+  MONO_EINVAL = -1,       /* bad argument or mesh                           */
+  MONO_ENOMEM = -2,       /* device or host allocation failed               */
+  MONO_EDEVICE = -3,      /* a HIP runtime call failed                      */
+  MONO_ESTATE = -4,       /* call not valid in the simulation's state       */
+  MONO_EUNSUPPORTED = -5, /* valid request this build does not implement    */
+  MONO_ENONFINITE = -6    /* a NaN/Inf potential appeared during stepping   */
+} mono_status;
+
+typedef enum { MONO_F64 = 0, MONO_F32 = 1 } mono_precision;
+
+/* Q1 elements; the value is the number of element nodes.  Node order:
+ * LINE2 x-,x+;  QUAD4 (0,0) (1,0) (1,1) (0,1) in reference coordinates;
+ * HEX8 the QUAD4 face at z- followed by the QUAD4 face at z+. */
+typedef enum { MONO_LINE2 = 2, MONO_QUAD4 = 4, MONO_HEX8 = 8 } mono_element;
+
+/* Cell models.  State 0 is always V.
+ *  LINEAR   dV/dt = -g (V - E)                    params {g, E}, 1 state
+ *  MS       Mitchell & Schaeffer (2003)           params {tau_in, tau_out,
+ *           tau_open, tau_close, v_gate}, states {v, h}, v dimensionless
+ *  TP06_EPI ten Tusscher & Panfilov (2006) epicardial, V in mV,
+ *           params {Ko [mM], gNa, gCaL, gKr, gKs, gK1 scalings}, 19 states
+ *           {V, K_i, Na_i, Ca_i, Ca_ss, Ca_SR, Rbar, m, h, j, xr1, xr2, xs,
+ *            r, s, d, f, f2, fCass}                                         */
+typedef enum { MONO_MODEL_LINEAR = 0, MONO_MODEL_MS = 1, MONO_MODEL_TP06_EPI = 2 } mono_model;
+
+/* DAETI: adaptive k and l (Sec. 2).  OSTAR: l = 1 (adaptive reaction only).
+ * OST: k = l = 1 (the caller picks dt).  The comparison methods of Sec. 3. */
+typedef enum { MONO_DAETI = 0, MONO_OSTAR = 1, MONO_OST = 2 } mono_method;
+
+/* Storage of the diffusion operator.  ELL: general sparse rows (column index
+ * + value per slot, slot-major).  STENCIL: the symmetric operator stored once
+ * per edge at a fixed set of node-index offsets, usable when every edge
+ * (i, j) of an instance has j - i in a set of at most 13 positive offsets
+ * (structured node numbering).  AUTO picks STENCIL when it applies. */
+enum { MONO_LAYOUT_AUTO = 0, MONO_LAYOUT_ELL = 1, MONO_LAYOUT_STENCIL = 2 };
+
+/* Fields of mono_get_state / mono_set_state. */
+enum {
+  MONO_FIELD_V = 0,      /* transmembrane potential                         */
+  MONO_FIELD_VPREV = 1,  /* V at the previous reaction entry                */
+  MONO_FIELD_LAT = 2,    /* activation time [ms], FP64, -1 = not activated   */
+  MONO_FIELD_K = 3,      /* reaction substeps k of the last step (get only)  */
+  MONO_FIELD_STATE0 = 16 /* + j: cell state j (j = 0 is V)                  */
+};
+
+typedef struct {
+  int32_t dim;                  /* 1, 2 or 3                                    */
+  int64_t n_nodes;
+  const double *xyz;            /* n_nodes * dim node coordinates [cm]          */
+  int32_t etype;                /* mono_element matching dim                    */
+  int64_t n_elems;
+  const int32_t *conn;          /* n_elems * etype 0-based node indices         */
+  const double *D_elem;         /* n_elems * dim * dim symmetric positive
+                                   definite diffusion tensors [cm^2/ms]         */
+  const double *sigma_node;     /* n_nodes conductivity scales or NULL (= 1):
+                                   off-diagonal K entries are multiplied by
+                                   (sigma_i + sigma_j)/2, rows keep zero sum    */
+  int32_t prec;                 /* mono_precision of V, states and operator     */
+  void *stream;                 /* hipStream_t, borrowed; NULL = the library
+                                   creates (and later destroys) its own stream  */
+  int32_t n_instances;          /* >= 1; independent tissues concatenated       */
+  const int64_t *inst_node_off; /* n_instances+1 node offsets, or NULL if 1;
+                                   no element may join two instances            */
+  int32_t layout;               /* MONO_LAYOUT_*                                 */
+} mono_mesh_desc;
+
+typedef struct {
+  double dt_s;        /* eq. (3) stable diffusion step [ms] (per instance)     */
+  double G_max;       /* max_i (k_ii + sum_j |k_ij|) / m_ii  [1/ms]            */
+  double lambda_est;  /* power-iteration estimate of lambda_max(M_L^-1 K), or 0 */
+  double dt_ad;       /* diffusion substep [ms] for the last prepared dt       */
+  double dt;          /* outer step of the last prepare [ms]                   */
+  double t;           /* simulated time of the current time level [ms]         */
+  int64_t step;       /* index of the current time level                       */
+  int64_t nnz;        /* stored nonzeros of K including the diagonal           */
+  int32_t l;          /* diffusion substeps per half step                      */
+  int32_t k_max;      /* reaction substep cap                                  */
+  int32_t layout;     /* MONO_LAYOUT_ELL or MONO_LAYOUT_STENCIL in use          */
+  int32_t n_instances;
+  int32_t n_states;
+  int32_t ell_width;  /* ELL slots per row, or stencil offsets per instance    */
+} mono_info;
+
+/* Assemble K and the row-sum lumped mass M_L of the FE diffusion problem
+ * (Sec. 2, eq. 2b-c) in FP64 on the host, upload the chosen layout, and run
+ * the Gershgorin kernel (eq. 3) in FP64 on the device.  Errors: EINVAL for a
+ * bad description, an index out of range, a non-positive element Jacobian or
+ * an element joining two instances; ENOMEM; EDEVICE. */
+mono_status mono_create_mesh(const mono_mesh_desc *desc, mono_sim **out);
+
+/* Choose the cell model.  params: n_params * n_nodes SoA, or NULL for the
+ * model's defaults (uniform rows are stored once).  init_state: n_states *
+ * n_nodes SoA or NULL for the model's published initial values.  dt0 [ms] is
+ * the largest stable cell step: k_max = max(1, floor(dt/dt0)) (Sec. 2).
+ * Resets time, V_prev (= V) and activation times. */
+mono_status mono_set_cell_model(mono_sim *sim, int32_t model, int32_t n_params,
+                                const double *params, const double *init_state, double dt0);
+
+/* Threshold of the activation-time detector (first upward crossing of the
+ * V samples taken at reaction entry, linearly interpolated, FP64). */
+mono_status mono_set_lat_threshold(mono_sim *sim, double v_threshold);
+
+/* Add a stimulus: `amplitude` (dV/dt units) is added to the diffusion
+ * right-hand side of the listed nodes for every substep whose start time tau
+ * has t_on <= tau < t_on + duration.  At most 8 stimuli per simulation. */
+mono_status mono_add_stimulus(mono_sim *sim, int64_t n, const int32_t *nodes, double t_on,
+                              double duration, double amplitude);
+
+/* Method flags.  dvdt_source 0: dV/dt = (V_entry - V_prev_entry)/dt (0 on
+ * the first step); 1: the cell model's own dV/dt at reaction entry.
+ * l_round 0: floor as in the paper; 1: ceiling (dt_ad <= dt_s). */
+mono_status mono_set_method(mono_sim *sim, int32_t method, int32_t dvdt_source, int32_t l_round);
+
+/* Advance n_outer_steps steps of size dt [ms] (async).  flags: bit 0
+ * (MONO_STEP_EAGER) = launch kernels one by one instead of replaying a cached
+ * HIP graph of 32 outer steps; bit 1 (MONO_STEP_TIMED) = launch one by one
+ * with every kernel bracketed by HIP events on the simulation's stream and
+ * add their durations to the totals read by MONO_DEBUG_KTIMES (this mode
+ * synchronises). */
+enum { MONO_STEP_EAGER = 1, MONO_STEP_TIMED = 2 };
+mono_status mono_step(mono_sim *sim, int64_t n_outer_steps, double dt, uint32_t flags);
+
+/* Copy `count` (= n_nodes) values of a field to host memory as FP64. */
+mono_status mono_get_state(mono_sim *sim, int32_t field, double *host_dst, int64_t count);
+
+/* Copy a field device-to-device in the simulation's precision (FP64 for
+ * LAT, uint8 for K); async on the simulation's stream. */
+mono_status mono_get_state_device_async(mono_sim *sim, int32_t field, void *dev_dst);
+
+/* Overwrite a field from host FP64 values (V, VPREV, LAT, STATE0+j). */
+mono_status mono_set_state(mono_sim *sim, int32_t field, const double *host_src, int64_t count);
+
+/* Set the current time level (t = step * dt). */
+mono_status mono_set_time_level(mono_sim *sim, int64_t step);
+
+/* Prepare for outer step dt: l, dt_ad, k_max (also done by mono_step). */
+mono_status mono_prepare(mono_sim *sim, double dt);
+
+/* Diagnostics of instance `inst` (0-based). */
+mono_status mono_get_info(mono_sim *sim, int32_t inst, mono_info *out);
+
+/* Estimate lambda_max(M_L^-1 K) of every instance by `iters` FP64 power
+ * iterations on the device (generalised Rayleigh quotient, a lower bound)
+ * and check dt_ad < 2/lambda_est for the last prepared dt. */
+mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
+
+/* Replace the borrowed stream. */
+mono_status mono_set_stream(mono_sim *sim, void *stream);
+
+/* Wait for the simulation's stream; reports MONO_ENONFINITE if latched. */
+mono_status mono_sync(mono_sim *sim);
+
+void mono_destroy(mono_sim *sim);
+const char *mono_last_error(void);
+
+/* Apply one phase of outer step `step` to the current state (testing the
+ * kernels one launch at a time).  phase 0: diffusion substep `m` of the first
+ * half step; 1: the reaction step; 2: diffusion substep `m` of the second
+ * half step.  Synchronising. */
+mono_status mono_apply_phase(mono_sim *sim, int32_t phase, int64_t step, int32_t m);
+
+/* Test hooks.  `what`:
+ *  MONO_DEBUG_KTRACE: arg -> mono_ktrace (device buffers n_steps x n_nodes,
+ *      uint8, row = step - base_step): record the k each node picks and/or
+ *      replay k from a given trace instead of the rule.
+ *  MONO_DEBUG_VCLAMP: arg -> int32 (1 = the reaction leaves V unchanged).
+ *  MONO_DEBUG_FORCE_L: arg -> int32 (l override for every instance, 0 = off).
+ *  MONO_DEBUG_STATS: arg -> int64[4] {sum of k over nodes and steps, sum over
+ *      wavefronts of 64 * max k, node-steps counted, node-steps at k_max}
+ *      (synchronising; counters run only while enabled with arg int32 1 via
+ *      MONO_DEBUG_STATS_ENABLE).
+ *  MONO_DEBUG_KTIMES: arg -> double[5]; returns {diffusion kernel ms,
+ *      diffusion launches, reaction kernel ms, reaction launches} of the
+ *      MONO_STEP_TIMED steps so far; the totals are reset when arg[4] != 0
+ *      on entry. */
+enum {
+  MONO_DEBUG_KTRACE = 1,
+  MONO_DEBUG_VCLAMP = 2,
+  MONO_DEBUG_FORCE_L = 3,
+  MONO_DEBUG_STATS = 4,
+  MONO_DEBUG_STATS_ENABLE = 5,
+  MONO_DEBUG_KTIMES = 6
+};
+typedef struct {
+  int32_t mode;          /* bit 0 record, bit 1 replay; 0 = off          */
+  uint8_t *record;       /* device, n_steps * n_nodes, or NULL            */
+  const uint8_t *replay; /* device, n_steps * n_nodes, or NULL            */
+  int64_t n_steps;
+  int64_t base_step;
+} mono_ktrace;
+mono_status mono_debug(mono_sim *sim, int32_t what, void *arg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MONO_H */

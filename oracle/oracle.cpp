@@ -557,6 +557,28 @@ int prepare(Sim* s, double dt) {
   return 0;
 }
 
+// Stimulus rate of node i at substep start time tau: the sum of the
+// amplitudes of the stimuli that contain i and are on at tau.
+double stim_rate_at(const Sim* s, int64_t i, double tau) {
+  double r = 0.0;
+  for (const Stim& st : s->stims) {
+    if (!(st.t_on <= tau && tau < st.t_on + st.dur)) continue;
+    if (std::binary_search(st.nodes.begin(), st.nodes.end(), (int32_t)i)) r += st.amp;
+  }
+  return r;
+}
+
+// Row i of diffusion substep m of a half step starting at t0:
+// V_i + dt_ad (-(K V)_i / m_i + s_i(tau)), tau = t0 + m dt_ad.
+double diffusion_row(const Sim* s, const double* V, int64_t i, int m, double t0,
+                     double stim_rate) {
+  int q = s->inst_of[i];
+  if (m >= s->l[q]) return V[i];
+  double kv = 0.0;
+  for (int64_t p = s->rowptr[i]; p < s->rowptr[i + 1]; ++p) kv += s->val[p] * V[s->col[p]];
+  return V[i] + s->dt_ad[q] * (-kv / s->mass[i] + stim_rate);
+}
+
 // One diffusion half step B(dt/2) at time t0: l forward Euler substeps of
 // V <- V + dt_ad (-M^-1 K V + s(tau)), tau = t0 + m dt_ad (Jacobi: every row
 // reads the V of the previous substep).
@@ -578,18 +600,46 @@ void diffusion_half(Sim* s, double t0) {
       }
     }
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
-      int q = s->inst_of[i];
-      if (m >= s->l[q]) {
-        s->vtmp[i] = V[i];
-        continue;
-      }
-      double kv = 0.0;
-      for (int64_t p = s->rowptr[i]; p < s->rowptr[i + 1]; ++p) kv += s->val[p] * V[s->col[p]];
-      s->vtmp[i] = V[i] + s->dt_ad[q] * (-kv / s->mass[i] + s->stim_rate[i]);
-    }
+    for (int64_t i = 0; i < n; ++i) s->vtmp[i] = diffusion_row(s, V, i, m, t0, s->stim_rate[i]);
     std::memcpy(V, s->vtmp.data(), sizeof(double) * n);
   }
+}
+
+// Step A for one node at outer step nstep: y (S states) and p (P params) in,
+// y out; vprev, lat updated; returns the k used.
+int react_node(const Sim* s, int64_t nstep, int64_t i, double* y, const double* p, double& vprev,
+               double& lat) {
+  const double dt = s->dt;
+  const double tA = nstep * dt + 0.5 * dt;   // time of the A-entry sample
+  const double Vb = y[0];
+  // dV/dt used by the k rule
+  double d;
+  if (s->dvdt_src == 0) {
+    d = (nstep == 0) ? 0.0 : (Vb - vprev) / dt;
+  } else {
+    Rates r;
+    model_rates(s->model, y, p, r);
+    d = r.rate[0];
+  }
+  // activation: first upward crossing of the threshold between samples
+  if (nstep > 0 && lat < 0.0 && vprev < s->lat_thr && Vb >= s->lat_thr) {
+    double w = (s->lat_thr - vprev) / (Vb - vprev);
+    lat = (tA - dt) + w * dt;
+  }
+  vprev = Vb;
+  int k = k_rule(d, s->k_max);
+  if (s->ktrace_mode && nstep < s->ktrace_steps) {
+    uint8_t* kt = s->ktrace + nstep * s->n + i;
+    if (s->ktrace_mode == 1) {
+      *kt = (uint8_t)k;
+      if (s->dtrace) s->dtrace[nstep * s->n + i] = d;
+    } else {
+      k = *kt;
+    }
+  }
+  const double h = dt / k;
+  for (int sub = 0; sub < k; ++sub) cell_substep(s->model, y, p, h, s->vclamp);
+  return k;
 }
 
 // Step A at outer step n: every node picks k and advances its cell model by
@@ -597,8 +647,6 @@ void diffusion_half(Sim* s, double t0) {
 void reaction(Sim* s, int64_t nstep) {
   const int64_t n = s->n;
   const int S = s->S, P = s->P;
-  const double dt = s->dt;
-  const double tA = nstep * dt + 0.5 * dt;   // time of the A-entry sample
   if (s->sensor_buf && nstep < s->sensor_steps) {
     for (size_t q = 0; q < s->sensors.size(); ++q)
       s->sensor_buf[nstep * (int64_t)s->sensors.size() + q] = s->state[s->sensors[q]];
@@ -608,35 +656,7 @@ void reaction(Sim* s, int64_t nstep) {
     double y[19], p[8];
     for (int a = 0; a < S; ++a) y[a] = s->state[a * n + i];
     for (int a = 0; a < P; ++a) p[a] = s->params[a * n + i];
-    const double Vb = y[0];
-    // dV/dt used by the k rule
-    double d;
-    if (s->dvdt_src == 0) {
-      d = (nstep == 0) ? 0.0 : (Vb - s->vprev[i]) / dt;
-    } else {
-      Rates r;
-      model_rates(s->model, y, p, r);
-      d = r.rate[0];
-    }
-    // activation: first upward crossing of the threshold between samples
-    if (nstep > 0 && s->lat[i] < 0.0 && s->vprev[i] < s->lat_thr && Vb >= s->lat_thr) {
-      double w = (s->lat_thr - s->vprev[i]) / (Vb - s->vprev[i]);
-      s->lat[i] = (tA - dt) + w * dt;
-    }
-    s->vprev[i] = Vb;
-    int k = k_rule(d, s->k_max);
-    if (s->ktrace_mode && nstep < s->ktrace_steps) {
-      uint8_t* kt = s->ktrace + nstep * n + i;
-      if (s->ktrace_mode == 1) {
-        *kt = (uint8_t)k;
-        if (s->dtrace) s->dtrace[nstep * n + i] = d;
-      } else {
-        k = *kt;
-      }
-    }
-    s->lastk[i] = k;
-    const double h = dt / k;
-    for (int sub = 0; sub < k; ++sub) cell_substep(s->model, y, p, h, s->vclamp);
+    s->lastk[i] = react_node(s, nstep, i, y, p, s->vprev[i], s->lat[i]);
     for (int a = 0; a < S; ++a) s->state[a * n + i] = y[a];
   }
 }
@@ -803,6 +823,8 @@ int orc_add_stimulus(void* h, int64_t n, const int32_t* nodes, double t_on, doub
     if (nodes[q] < 0 || nodes[q] >= s->n) return fail("stimulus node out of range");
     st.nodes.push_back(nodes[q]);
   }
+  std::sort(st.nodes.begin(), st.nodes.end());
+  st.nodes.erase(std::unique(st.nodes.begin(), st.nodes.end()), st.nodes.end());
   st.t_on = t_on;
   st.dur = dur;
   st.amp = amp;
@@ -906,6 +928,41 @@ int orc_set_sensors(void* h, int32_t n, const int32_t* nodes, double* buf, int64
 
 int orc_set_vclamp(void* h, int on) {
   ((Sim*)h)->vclamp = on;
+  return 0;
+}
+
+// --- sampled evaluation (rows of one full-size launch) -----------------------
+// Substep m of the half step that starts at t0, applied to V_in (all n
+// values), evaluated only on `rows`.
+int orc_diffusion_rows(void* h, const double* V_in, double t0, int m, int64_t nrows,
+                       const int64_t* rows, double* out) {
+  Sim* s = (Sim*)h;
+  if (s->dt <= 0.0) return fail("not prepared");
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    if (i < 0 || i >= s->n) return fail("row out of range");
+    const int q = s->inst_of[i];
+    const double tau = t0 + m * s->dt_ad[q];
+    out[r] = diffusion_row(s, V_in, i, m, t0, stim_rate_at(s, i, tau));
+  }
+  return 0;
+}
+
+// Step A of outer step nstep on the given nodes: y (S x nrows, SoA), vprev,
+// lat in/out, k out.  Uses the simulation's parameters of those nodes.
+int orc_reaction_nodes(void* h, int64_t nstep, int64_t nrows, const int64_t* rows, double* y,
+                       double* vprev, double* lat, int32_t* k_out) {
+  Sim* s = (Sim*)h;
+  if (s->dt <= 0.0 || s->model < 0) return fail("not prepared");
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    if (i < 0 || i >= s->n) return fail("node out of range");
+    double yy[19], p[8];
+    for (int a = 0; a < s->S; ++a) yy[a] = y[a * nrows + r];
+    for (int a = 0; a < s->P; ++a) p[a] = s->params[a * s->n + i];
+    k_out[r] = react_node(s, nstep, i, yy, p, vprev[r], lat[r]);
+    for (int a = 0; a < s->S; ++a) y[a * nrows + r] = yy[a];
+  }
   return 0;
 }
 

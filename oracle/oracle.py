@@ -62,6 +62,8 @@ def lib():
         L.orc_cell_advance.argtypes = [C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int]
         L.orc_cell_rates.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _ip]
         L.orc_tp06_currents.argtypes = [_dp, _dp, _dp]
+        L.orc_diffusion_rows.argtypes = [vp, _dp, C.c_double, C.c_int, C.c_int64, _lp, _dp]
+        L.orc_reaction_nodes.argtypes = [vp, C.c_int64, C.c_int64, _lp, _dp, _dp, _dp, _ip]
         L.orc_k_rule.argtypes = [C.c_double, C.c_int]
         L.orc_l_rule.argtypes = [C.c_double, C.c_double, C.c_int]
         _lib = L
@@ -212,6 +214,22 @@ class Oracle:
     def ktrace_off(self):
         _check(lib().orc_set_ktrace(self.h, 0, None, None, 0))
         self._ktrace = None
+
+    def diffusion_rows(self, V_in, t0, m, rows):
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.zeros(len(rows))
+        _check(lib().orc_diffusion_rows(self.h, _f64(V_in), float(t0), int(m), len(rows), rows, out))
+        return out
+
+    def reaction_nodes(self, nstep, rows, y, vprev, lat):
+        """Step A on `rows` from states y (S x len(rows)); returns (y, vprev, lat, k)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        y = _f64(y).copy()
+        vp = _f64(vprev).copy()
+        la = _f64(lat).copy()
+        k = np.zeros(len(rows), np.int32)
+        _check(lib().orc_reaction_nodes(self.h, int(nstep), len(rows), rows, y, vp, la, k))
+        return y, vp, la, k
 
     def record_sensors(self, nodes, n_steps):
         nodes = _i32(nodes)

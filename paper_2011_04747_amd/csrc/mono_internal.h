@@ -1,0 +1,157 @@
+// Internal declarations of libmono (host runtime <-> HIP kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mono.h"
+
+namespace mono {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
+constexpr int kMaxStim = 8;        // stimuli per simulation
+constexpr int kMaxOffsets = 13;    // positive stencil offsets (27-point hex stencil)
+constexpr int kMaxParams = 8;
+constexpr int kMaxStates = 19;
+
+// ---------------------------------------------------------------------------
+// host-side FE assembly (assembly.cpp)
+// ---------------------------------------------------------------------------
+struct HostCSR {
+  int64_t n = 0;
+  std::vector<int64_t> rp;    // n + 1
+  std::vector<int32_t> col;   // sorted per row, includes the diagonal
+  std::vector<double> val;    // K entries
+  std::vector<double> mass;   // row-sum lumped mass
+};
+
+// Assemble K (with per-node conductivity scaling) and the lumped mass.
+// Returns 0 or a MONO_E* code with a message in err.
+int assemble_fe(const mono_mesh_desc* d, HostCSR& K, std::string& err);
+
+struct EllHost {
+  int width = 0;
+  std::vector<int32_t> col;   // width * Np, slot-major
+  std::vector<double> val;    // a_ij = -k_ij / m_i
+};
+void build_ell(const HostCSR& K, int64_t Np, EllHost& out);
+
+struct StencilHost {
+  int P = 0;                   // offsets per instance (padded)
+  std::vector<int32_t> off;    // n_inst * P positive offsets
+  std::vector<double> e;       // P * Np, e[p][i] = -k(i, i + off_p) or 0
+  std::vector<double> minv;    // Np, 1 / m_i
+};
+// Returns false when some instance needs more than kMaxOffsets offsets.
+bool build_stencil(const HostCSR& K, const std::vector<int64_t>& inst_off, int64_t Np,
+                   StencilHost& out);
+
+// ---------------------------------------------------------------------------
+// kernel argument blocks
+// ---------------------------------------------------------------------------
+struct StimTable {
+  int n;
+  double t_on[kMaxStim];
+  double t_end[kMaxStim];
+  double amp[kMaxStim];
+};
+
+struct StepClock {
+  const int64_t* base;   // device: index of the first step of this launch sequence
+  int64_t g;             // offset of this step within the sequence
+  double dt;
+};
+
+template <typename T>
+struct DiffArgs {
+  int64_t n, Np;
+  const T* Vin;
+  T* Vout;
+  // ELL
+  int W;
+  const int32_t* col;
+  const T* val;
+  // STENCIL
+  int P;
+  const T* e;
+  const T* minv;
+  const int32_t* off;        // n_inst * P
+  // instances
+  const int32_t* inst;       // per node, or nullptr for a single instance
+  const int64_t* inst_off;   // n_inst + 1 first nodes of the instances
+  const int32_t* l;          // per instance substep counts
+  const double* dt_ad;       // per instance
+  // stimulus
+  const uint8_t* stim_mask;  // per node bit set, or nullptr
+  StimTable stim;
+  // time of this substep: tau = step*dt (+ dt/2 for the second half) + m*dt_ad
+  StepClock clk;
+  int half;
+  int m;
+};
+
+struct KTraceArgs {
+  int mode;                  // bit 0 record, bit 1 replay
+  uint8_t* rec;
+  const uint8_t* rep;
+  int64_t base, steps;
+};
+
+template <typename T>
+struct IonArgs {
+  int64_t n, Np;
+  T* V;
+  T* st;                     // (S - 1) * Np
+  T* vprev;
+  double* lat;
+  uint8_t* lastk;
+  const T* par;              // per-node parameter rows (P * Np) where non-uniform
+  T par_uniform[kMaxParams];
+  uint32_t par_pernode;      // bit a set: row a is per node
+  StepClock clk;
+  int k_max;
+  double lat_thr;
+  int dvdt_src;
+  int vclamp;
+  KTraceArgs kt;
+  int* flag;                 // non-finite latch
+  unsigned long long* stats; // 4 counters or nullptr
+};
+
+// ---------------------------------------------------------------------------
+// launchers (kernels_*.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_diffusion(int layout, const DiffArgs<T>& a, hipStream_t s);
+
+template <typename T>
+void launch_ionic(int model, const IonArgs<T>& a, hipStream_t s);
+
+void launch_advance_clock(int64_t* base, int64_t by, hipStream_t s);
+
+// Gershgorin rows in FP64 on CSR: r_i = m_i/(k_ii + sum|k_ij|), g_i = 1/r_i,
+// then per-instance min r and max g.
+void launch_gershgorin(int64_t n, const int64_t* rp, const int32_t* col, const double* val,
+                       const double* mass, double* r, double* g, hipStream_t s);
+void launch_segmented_minmax(int n_inst, const int64_t* inst_off, const double* r,
+                             const double* g, double* rmin, double* gmax, hipStream_t s);
+
+// power iteration helpers (FP64, CSR)
+void launch_spmv_csr(int64_t n, const int64_t* rp, const int32_t* col, const double* val,
+                     const double* x, double* y, hipStream_t s);
+void launch_segmented_dots(int n_inst, const int64_t* inst_off, const double* x,
+                           const double* kx, const double* mass, double* xkx, double* xmx,
+                           hipStream_t s);
+void launch_power_update(int64_t n, const int32_t* inst, const double* kx, const double* mass,
+                         const double* xmx, double* x, hipStream_t s);
+void launch_power_init(int64_t n, double* x, hipStream_t s);
+
+template <typename T>
+void launch_convert(int64_t n, const T* src, double* dst, hipStream_t s);
+template <typename T>
+void launch_convert_from(int64_t n, const double* src, T* dst, hipStream_t s);
+
+}  // namespace mono

@@ -1,0 +1,990 @@
+// libmono runtime: the C interface of include/mono.h.
+//
+// Owns the device buffers of a simulation, derives the time discretisation
+// of the DAETI method (paper Sec. 2: Gershgorin step of eq. 3, diffusion
+// substep count l, reaction cap k_max) and enqueues the split step
+// B(dt/2) A(dt) B(dt/2) on the simulation's stream, replaying a cached HIP
+// graph of a chunk of outer steps so that per-launch host overhead is paid
+// once per chunk.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mono_internal.h"
+
+using namespace mono;
+
+namespace {
+
+thread_local std::string t_err;
+
+mono_status fail(mono_status s, const std::string& m) {
+  t_err = m;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(MONO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+constexpr int kGraphChunk = 32;   // outer steps per captured graph
+
+// published initial values of the TP06 code release (not pre-paced)
+const double kTP06Init[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0, 0.0, 0.75, 0.75,
+                              0.0,   1.0,   0.0,  0.0,     1.0,     0.0, 1.0, 1.0, 1.0};
+const double kMSParams[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
+const double kTP06Params[6] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0};
+
+int model_states(int m) { return m == MONO_MODEL_LINEAR ? 1 : (m == MONO_MODEL_MS ? 2 : 19); }
+int model_params(int m) { return m == MONO_MODEL_LINEAR ? 2 : (m == MONO_MODEL_MS ? 5 : 6); }
+double default_lat_threshold(int m) {
+  return m == MONO_MODEL_TP06_EPI ? -40.0 : (m == MONO_MODEL_MS ? 0.5 : 0.0);
+}
+
+}  // namespace
+
+struct mono_sim {
+  int prec = MONO_F64;
+  size_t es = 8;               // bytes per state value
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int dim = 0;
+  int64_t n = 0, Np = 0;
+  int n_inst = 1;
+  std::vector<int64_t> inst_off;
+  int32_t* d_inst = nullptr;
+  int64_t* d_inst_off = nullptr;
+  // operator
+  int layout = MONO_LAYOUT_ELL;
+  int W = 0, P = 0;
+  int32_t* d_col = nullptr;
+  void* d_val = nullptr;
+  void* d_e = nullptr;
+  void* d_minv = nullptr;
+  int32_t* d_off = nullptr;
+  int64_t nnz = 0;
+  HostCSR K;
+  std::vector<double> dt_s, gmax, lambda;
+  // cell model
+  int model = -1, S = 0, Pm = 0;
+  void* d_V[2] = {nullptr, nullptr};
+  void* d_st = nullptr;
+  void* d_vprev = nullptr;
+  double* d_lat = nullptr;
+  uint8_t* d_k = nullptr;
+  void* d_par = nullptr;
+  uint32_t par_pernode = 0;
+  double par_uniform[kMaxParams] = {0};
+  double lat_thr = 0.0;
+  double dt0 = 0.01;
+  StimTable stim{};
+  uint8_t* d_mask = nullptr;
+  // method and discretisation
+  int method = MONO_DAETI, dvdt_src = 0, l_round = 0;
+  double dt = -1.0;
+  std::vector<int32_t> l;
+  std::vector<double> dt_ad;
+  int l_max = 1, k_max = 1;
+  int32_t* d_l = nullptr;
+  double* d_dtad = nullptr;
+  int64_t step = 0;
+  int64_t* d_base = nullptr;
+  int* d_flag = nullptr;
+  bool latched = false;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool g_valid = false;
+  // debug
+  KTraceArgs kt{};
+  int vclamp = 0, force_l = 0;
+  unsigned long long* d_stats = nullptr;
+  bool stats_on = false;
+  // per-kernel timing of MONO_STEP_TIMED calls: [0] diffusion, [1] reaction
+  std::vector<hipEvent_t> ev_pool;
+  double ktime_ms[2] = {0.0, 0.0};
+  int64_t klaunches[2] = {0, 0};
+};
+
+namespace {
+
+void drop_graph(mono_sim* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->gexec = nullptr;
+  s->graph = nullptr;
+  s->g_valid = false;
+}
+
+// upload n_host doubles into a device array of the simulation's precision
+mono_status upload_real(mono_sim* s, void* dst, const double* src, size_t count) {
+  if (count == 0) return MONO_OK;
+  if (s->prec == MONO_F64) {
+    HIP_TRY(hipMemcpy(dst, src, count * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> tmp(count);
+    for (size_t i = 0; i < count; ++i) tmp[i] = (float)src[i];
+    HIP_TRY(hipMemcpy(dst, tmp.data(), count * 4, hipMemcpyHostToDevice));
+  }
+  return MONO_OK;
+}
+
+mono_status download_real(mono_sim* s, double* dst, const void* src, size_t count) {
+  if (count == 0) return MONO_OK;
+  if (s->prec == MONO_F64) {
+    HIP_TRY(hipMemcpyAsync(dst, src, count * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else {
+    std::vector<float> tmp(count);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), src, count * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t i = 0; i < count; ++i) dst[i] = tmp[i];
+  }
+  return MONO_OK;
+}
+
+mono_status check_flag(mono_sim* s) {
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, s->d_flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (f) {
+    s->latched = true;
+    return fail(MONO_ENONFINITE, "non-finite membrane potential during stepping");
+  }
+  return MONO_OK;
+}
+
+// Time discretisation for outer step dt (Sec. 2).
+mono_status prepare(mono_sim* s, double dt) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MONO_EINVAL, "dt must be positive");
+  std::vector<int32_t> l(s->n_inst);
+  std::vector<double> dad(s->n_inst);
+  for (int q = 0; q < s->n_inst; ++q) {
+    int lq = 1;
+    if (0.5 * dt > s->dt_s[q]) {
+      const double x = dt / (2.0 * s->dt_s[q]);
+      const double r = s->l_round ? std::ceil(x) : std::floor(x);
+      lq = r < 1.0 ? 1 : (int)r;
+    }
+    if (s->method != MONO_DAETI) lq = 1;
+    if (s->force_l > 0) lq = s->force_l;
+    l[q] = lq;
+    dad[q] = dt / (2.0 * lq);
+  }
+  double km = std::floor(dt / s->dt0);
+  int kmax = km < 1.0 ? 1 : (km > 255.0 ? 255 : (int)km);
+  if (s->method == MONO_OST) kmax = 1;
+  const bool changed = (l != s->l) || (dad != s->dt_ad) || kmax != s->k_max || dt != s->dt;
+  if (changed) {
+    // kernels already enqueued may still read the per-instance tables
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->l = l;
+    s->dt_ad = dad;
+    s->k_max = kmax;
+    s->dt = dt;
+    s->l_max = *std::max_element(l.begin(), l.end());
+    HIP_TRY(hipMemcpy(s->d_l, l.data(), l.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_dtad, dad.data(), dad.size() * sizeof(double), hipMemcpyHostToDevice));
+    drop_graph(s);
+  }
+  return MONO_OK;
+}
+
+template <typename T>
+DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
+  DiffArgs<T> a{};
+  a.n = s->n;
+  a.Np = s->Np;
+  a.Vin = (const T*)s->d_V[pass_in & 1];
+  a.Vout = (T*)s->d_V[(pass_in + 1) & 1];
+  a.W = s->W;
+  a.col = s->d_col;
+  a.val = (const T*)s->d_val;
+  a.P = s->P;
+  a.e = (const T*)s->d_e;
+  a.minv = (const T*)s->d_minv;
+  a.off = s->d_off;
+  a.inst = s->n_inst > 1 ? s->d_inst : nullptr;
+  a.inst_off = s->d_inst_off;
+  a.l = s->d_l;
+  a.dt_ad = s->d_dtad;
+  a.stim_mask = s->d_mask;
+  a.stim = s->stim;
+  a.clk.base = s->d_base;
+  a.clk.g = g;
+  a.clk.dt = s->dt;
+  a.half = half;
+  a.m = m;
+  return a;
+}
+
+template <typename T>
+IonArgs<T> ion_args(mono_sim* s, void* V, int64_t g) {
+  IonArgs<T> a{};
+  a.n = s->n;
+  a.Np = s->Np;
+  a.V = (T*)V;
+  a.st = (T*)s->d_st;
+  a.vprev = (T*)s->d_vprev;
+  a.lat = s->d_lat;
+  a.lastk = s->d_k;
+  a.par = (const T*)s->d_par;
+  for (int q = 0; q < kMaxParams; ++q) a.par_uniform[q] = (T)s->par_uniform[q];
+  a.par_pernode = s->par_pernode;
+  a.clk.base = s->d_base;
+  a.clk.g = g;
+  a.clk.dt = s->dt;
+  a.k_max = s->k_max;
+  a.lat_thr = s->lat_thr;
+  a.dvdt_src = s->dvdt_src;
+  a.vclamp = s->vclamp;
+  a.kt = s->kt;
+  a.flag = s->d_flag;
+  a.stats = s->stats_on ? s->d_stats : nullptr;
+  return a;
+}
+
+// Enqueue `count` outer steps with clock offsets 0..count-1 and advance the
+// device clock by count.  With `ev` non-null every kernel is bracketed by a
+// pair of events (appended as {start, stop, class}).
+struct TimedPair {
+  hipEvent_t a, b;
+  int cls;
+};
+
+template <typename T>
+void enqueue_steps(mono_sim* s, int64_t count, std::vector<TimedPair>* ev) {
+  const int L = s->l_max;
+  size_t next = 0;
+  auto mark = [&](int cls, bool start) {
+    if (!ev) return;
+    if (start) {
+      TimedPair p{s->ev_pool[next], s->ev_pool[next + 1], cls};
+      next += 2;
+      ev->push_back(p);
+      (void)hipEventRecord(p.a, s->stream);
+    } else {
+      (void)hipEventRecord(ev->back().b, s->stream);
+    }
+  };
+  for (int64_t g = 0; g < count; ++g) {
+    for (int m = 0; m < L; ++m) {
+      mark(0, true);
+      launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->stream);
+      mark(0, false);
+    }
+    mark(1, true);
+    launch_ionic<T>(s->model, ion_args<T>(s, s->d_V[L & 1], g), s->stream);
+    mark(1, false);
+    for (int m = 0; m < L; ++m) {
+      mark(0, true);
+      launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->stream);
+      mark(0, false);
+    }
+  }
+  launch_advance_clock(s->d_base, count, s->stream);
+}
+
+void enqueue(mono_sim* s, int64_t count, std::vector<TimedPair>* ev = nullptr) {
+  if (s->prec == MONO_F64)
+    enqueue_steps<double>(s, count, ev);
+  else
+    enqueue_steps<float>(s, count, ev);
+}
+
+// Eager steps with every kernel timed by HIP events on the simulation's
+// stream (synchronising); adds to the per-class totals.
+mono_status enqueue_timed(mono_sim* s, int64_t count) {
+  const int64_t per_step = 2 * s->l_max + 1;
+  const int64_t chunk = 64;
+  for (int64_t done = 0; done < count;) {
+    const int64_t c = std::min(chunk, count - done);
+    const size_t need = (size_t)(2 * per_step * c);
+    while (s->ev_pool.size() < need) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      s->ev_pool.push_back(e);
+    }
+    std::vector<TimedPair> ev;
+    ev.reserve(per_step * c);
+    // the device clock of this chunk starts at the current time level
+    enqueue(s, c, &ev);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (const TimedPair& p : ev) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+      s->ktime_ms[p.cls] += ms;
+      s->klaunches[p.cls] += 1;
+    }
+    done += c;
+  }
+  return MONO_OK;
+}
+
+mono_status ensure_graph(mono_sim* s) {
+  if (s->g_valid) return MONO_OK;
+  drop_graph(s);
+  HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  enqueue(s, kGraphChunk);
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamEndCapture(s->stream, &g));
+  s->graph = g;
+  HIP_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+  s->g_valid = true;
+  return MONO_OK;
+}
+
+mono_status require_model(mono_sim* s) {
+  if (!s) return fail(MONO_EINVAL, "NULL simulation");
+  if (s->model < 0) return fail(MONO_ESTATE, "no cell model set");
+  return MONO_OK;
+}
+
+void* field_ptr(mono_sim* s, int field, size_t& es) {
+  es = s->es;
+  if (field == MONO_FIELD_V || field == MONO_FIELD_STATE0) return s->d_V[0];
+  if (field == MONO_FIELD_VPREV) return s->d_vprev;
+  if (field == MONO_FIELD_LAT) {
+    es = 8;
+    return s->d_lat;
+  }
+  if (field == MONO_FIELD_K) {
+    es = 1;
+    return s->d_k;
+  }
+  if (field > MONO_FIELD_STATE0 && field < MONO_FIELD_STATE0 + s->S)
+    return (char*)s->d_st + (size_t)(field - MONO_FIELD_STATE0 - 1) * s->Np * s->es;
+  return nullptr;
+}
+
+void free_model(mono_sim* s) {
+  dfree(s->d_V[0]);
+  dfree(s->d_V[1]);
+  dfree(s->d_st);
+  dfree(s->d_vprev);
+  dfree(s->d_lat);
+  dfree(s->d_k);
+  dfree(s->d_par);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* mono_last_error(void) { return t_err.c_str(); }
+
+mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
+  if (!d || !out) return fail(MONO_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (d->dim < 1 || d->dim > 3) return fail(MONO_EINVAL, "dim must be 1, 2 or 3");
+  if (d->etype != (1 << d->dim)) return fail(MONO_EINVAL, "etype does not match dim");
+  if (d->n_nodes < 1 || d->n_nodes > (int64_t)INT32_MAX - 1024)
+    return fail(MONO_EINVAL, "n_nodes out of range");
+  if (d->n_elems < 0) return fail(MONO_EINVAL, "n_elems must be >= 0");
+  if (d->prec != MONO_F64 && d->prec != MONO_F32) return fail(MONO_EINVAL, "bad precision");
+  if (d->layout < MONO_LAYOUT_AUTO || d->layout > MONO_LAYOUT_STENCIL)
+    return fail(MONO_EINVAL, "bad layout");
+  const int ni = d->n_instances < 1 ? 1 : d->n_instances;
+  std::vector<int64_t> off;
+  if (ni == 1 || !d->inst_node_off) {
+    if (ni > 1) return fail(MONO_EINVAL, "inst_node_off required for several instances");
+    off = {0, d->n_nodes};
+  } else {
+    off.assign(d->inst_node_off, d->inst_node_off + ni + 1);
+    if (off[0] != 0 || off[ni] != d->n_nodes) return fail(MONO_EINVAL, "bad instance offsets");
+    for (int q = 0; q < ni; ++q)
+      if (off[q + 1] <= off[q]) return fail(MONO_EINVAL, "empty or decreasing instance");
+  }
+  mono_sim* s = new mono_sim();
+  s->prec = d->prec;
+  s->es = d->prec == MONO_F64 ? 8 : 4;
+  s->dim = d->dim;
+  s->n = d->n_nodes;
+  s->Np = (d->n_nodes + kBlock - 1) / kBlock * kBlock;
+  s->n_inst = ni;
+  s->inst_off = off;
+  auto bail = [&](mono_status st) {
+    mono_destroy(s);
+    return st;
+  };
+  std::string err;
+  int rc = assemble_fe(d, s->K, err);
+  if (rc != MONO_OK) return bail(fail((mono_status)rc, err));
+  s->nnz = (int64_t)s->K.col.size();
+  // instance ids; elements must not join instances
+  std::vector<int32_t> inst(s->n, 0);
+  for (int q = 0; q < ni; ++q)
+    for (int64_t i = off[q]; i < off[q + 1]; ++i) inst[i] = q;
+  if (ni > 1) {
+    const int nen = d->etype;
+    for (int64_t e = 0; e < d->n_elems; ++e) {
+      const int32_t q0 = inst[d->conn[e * nen]];
+      for (int a = 1; a < nen; ++a)
+        if (inst[d->conn[e * nen + a]] != q0)
+          return bail(fail(MONO_EINVAL, "element joins two instances"));
+    }
+  }
+  // stream
+  if (d->stream) {
+    s->stream = (hipStream_t)d->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(MONO_EDEVICE, "hipStreamCreate failed"));
+    s->own_stream = true;
+  }
+  // small per-instance arrays, clock and flags
+  if (dalloc(&s->d_base, 1) || dalloc(&s->d_flag, 1) || dalloc(&s->d_l, ni) ||
+      dalloc(&s->d_dtad, ni) || dalloc(&s->d_inst_off, ni + 1))
+    return bail(fail(MONO_ENOMEM, "device allocation failed"));
+  if (hipMemsetAsync(s->d_base, 0, 8, s->stream) ||
+      hipMemsetAsync(s->d_flag, 0, sizeof(int), s->stream) || hipStreamSynchronize(s->stream) ||
+      hipMemcpy(s->d_inst_off, off.data(), (ni + 1) * 8, hipMemcpyHostToDevice))
+    return bail(fail(MONO_EDEVICE, "device initialisation failed"));
+  if (ni > 1) {
+    std::vector<int32_t> ip(s->Np, ni - 1);
+    std::copy(inst.begin(), inst.end(), ip.begin());
+    if (dalloc(&s->d_inst, s->Np)) return bail(fail(MONO_ENOMEM, "device allocation failed"));
+    if (hipMemcpy(s->d_inst, ip.data(), s->Np * 4, hipMemcpyHostToDevice))
+      return bail(fail(MONO_EDEVICE, "upload failed"));
+  }
+  // eq. (3) in FP64 on the device
+  {
+    int64_t *rp = nullptr;
+    int32_t* col = nullptr;
+    double *val = nullptr, *mass = nullptr, *r = nullptr, *g = nullptr, *rmin = nullptr,
+           *gmx = nullptr;
+    bool ok = !dalloc(&rp, s->n + 1) && !dalloc(&col, s->nnz) && !dalloc(&val, s->nnz) &&
+              !dalloc(&mass, s->n) && !dalloc(&r, s->n) && !dalloc(&g, s->n) &&
+              !dalloc(&rmin, ni) && !dalloc(&gmx, ni);
+    std::vector<double> hr(ni), hg(ni);
+    if (ok)
+      ok = !hipMemcpy(rp, s->K.rp.data(), (s->n + 1) * 8, hipMemcpyHostToDevice) &&
+           !hipMemcpy(col, s->K.col.data(), s->nnz * 4, hipMemcpyHostToDevice) &&
+           !hipMemcpy(val, s->K.val.data(), s->nnz * 8, hipMemcpyHostToDevice) &&
+           !hipMemcpy(mass, s->K.mass.data(), s->n * 8, hipMemcpyHostToDevice);
+    if (ok) {
+      launch_gershgorin(s->n, rp, col, val, mass, r, g, s->stream);
+      launch_segmented_minmax(ni, s->d_inst_off, r, g, rmin, gmx, s->stream);
+      ok = !hipMemcpyAsync(hr.data(), rmin, ni * 8, hipMemcpyDeviceToHost, s->stream) &&
+           !hipMemcpyAsync(hg.data(), gmx, ni * 8, hipMemcpyDeviceToHost, s->stream) &&
+           !hipStreamSynchronize(s->stream) && !hipGetLastError();
+    }
+    dfree(rp);
+    dfree(col);
+    dfree(val);
+    dfree(mass);
+    dfree(r);
+    dfree(g);
+    dfree(rmin);
+    dfree(gmx);
+    if (!ok) return bail(fail(MONO_EDEVICE, "Gershgorin kernel failed"));
+    s->dt_s.resize(ni);
+    s->gmax = hg;
+    s->lambda.assign(ni, 0.0);
+    for (int q = 0; q < ni; ++q) {
+      if (!(hr[q] > 0.0) || !std::isfinite(hr[q]))
+        return bail(fail(MONO_EINVAL, "degenerate stiffness (no diffusion) in an instance"));
+      s->dt_s[q] = 0.9 * hr[q];
+    }
+  }
+  // operator layout
+  int layout = d->layout;
+  StencilHost sh;
+  bool stencil_ok = false;
+  if (layout != MONO_LAYOUT_ELL) stencil_ok = build_stencil(s->K, off, s->Np, sh);
+  if (layout == MONO_LAYOUT_STENCIL && !stencil_ok)
+    return bail(fail(MONO_EUNSUPPORTED, "mesh numbering has too many stencil offsets"));
+  if (layout == MONO_LAYOUT_AUTO) layout = stencil_ok ? MONO_LAYOUT_STENCIL : MONO_LAYOUT_ELL;
+  s->layout = layout;
+  if (layout == MONO_LAYOUT_STENCIL) {
+    s->P = sh.P;
+    if (dalloc((char**)&s->d_e, (size_t)sh.P * s->Np * s->es) ||
+        dalloc((char**)&s->d_minv, s->Np * s->es) || dalloc(&s->d_off, sh.off.size()))
+      return bail(fail(MONO_ENOMEM, "device allocation failed"));
+    mono_status st = upload_real(s, s->d_e, sh.e.data(), sh.e.size());
+    if (st == MONO_OK) st = upload_real(s, s->d_minv, sh.minv.data(), sh.minv.size());
+    if (st != MONO_OK) return bail(st);
+    if (hipMemcpy(s->d_off, sh.off.data(), sh.off.size() * 4, hipMemcpyHostToDevice))
+      return bail(fail(MONO_EDEVICE, "upload failed"));
+  } else {
+    EllHost eh;
+    build_ell(s->K, s->Np, eh);
+    s->W = eh.width;
+    if (dalloc(&s->d_col, eh.col.size()) || dalloc((char**)&s->d_val, eh.val.size() * s->es))
+      return bail(fail(MONO_ENOMEM, "device allocation failed"));
+    if (hipMemcpy(s->d_col, eh.col.data(), eh.col.size() * 4, hipMemcpyHostToDevice))
+      return bail(fail(MONO_EDEVICE, "upload failed"));
+    mono_status st = upload_real(s, s->d_val, eh.val.data(), eh.val.size());
+    if (st != MONO_OK) return bail(st);
+  }
+  *out = s;
+  return MONO_OK;
+}
+
+void mono_destroy(mono_sim* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  drop_graph(s);
+  free_model(s);
+  dfree(s->d_inst);
+  dfree(s->d_inst_off);
+  dfree(s->d_col);
+  dfree(s->d_val);
+  dfree(s->d_e);
+  dfree(s->d_minv);
+  dfree(s->d_off);
+  dfree(s->d_mask);
+  dfree(s->d_l);
+  dfree(s->d_dtad);
+  dfree(s->d_base);
+  dfree(s->d_flag);
+  dfree(s->d_stats);
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
+                                const double* params, const double* init_state, double dt0) {
+  if (!s) return fail(MONO_EINVAL, "NULL simulation");
+  if (model < MONO_MODEL_LINEAR || model > MONO_MODEL_TP06_EPI)
+    return fail(MONO_EINVAL, "unknown cell model");
+  if (!(dt0 > 0.0)) return fail(MONO_EINVAL, "dt0 must be positive");
+  const int S = model_states(model), P = model_params(model);
+  if (params && n_params != P) return fail(MONO_EINVAL, "wrong number of parameter rows");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  drop_graph(s);
+  free_model(s);
+  s->model = model;
+  s->S = S;
+  s->Pm = P;
+  const size_t Np = s->Np, es = s->es;
+  if (dalloc((char**)&s->d_V[0], Np * es) || dalloc((char**)&s->d_V[1], Np * es) ||
+      dalloc((char**)&s->d_st, (size_t)std::max(S - 1, 1) * Np * es) ||
+      dalloc((char**)&s->d_vprev, Np * es) || dalloc(&s->d_lat, Np) || dalloc(&s->d_k, Np))
+    return fail(MONO_ENOMEM, "device allocation failed");
+  HIP_TRY(hipMemsetAsync(s->d_V[0], 0, Np * es, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_V[1], 0, Np * es, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_st, 0, (size_t)std::max(S - 1, 1) * Np * es, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_k, 0, Np, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  // initial state
+  std::vector<double> y((size_t)S * s->n);
+  if (init_state) {
+    std::memcpy(y.data(), init_state, y.size() * 8);
+  } else {
+    for (int a = 0; a < S; ++a) {
+      double v = 0.0;
+      if (model == MONO_MODEL_TP06_EPI) v = kTP06Init[a];
+      if (model == MONO_MODEL_MS) v = (a == 0) ? 0.0 : 1.0;
+      std::fill(y.begin() + (size_t)a * s->n, y.begin() + (size_t)(a + 1) * s->n, v);
+    }
+  }
+  mono_status st = upload_real(s, s->d_V[0], y.data(), s->n);
+  if (st == MONO_OK) st = upload_real(s, s->d_vprev, y.data(), s->n);
+  for (int a = 1; a < S && st == MONO_OK; ++a)
+    st = upload_real(s, (char*)s->d_st + (size_t)(a - 1) * Np * es, y.data() + (size_t)a * s->n,
+                     s->n);
+  if (st != MONO_OK) return st;
+  {
+    std::vector<double> lat(s->n, -1.0);
+    HIP_TRY(hipMemcpy(s->d_lat, lat.data(), s->n * 8, hipMemcpyHostToDevice));
+  }
+  // parameters: uniform rows are passed by value, the others stored per node
+  s->par_pernode = 0;
+  std::vector<double> pu(P);
+  for (int a = 0; a < P; ++a) {
+    double v = model == MONO_MODEL_MS ? kMSParams[a]
+                                      : (model == MONO_MODEL_TP06_EPI ? kTP06Params[a] : 0.0);
+    if (params) {
+      const double* row = params + (size_t)a * s->n;
+      v = row[0];
+      for (int64_t i = 1; i < s->n; ++i)
+        if (row[i] != v) {
+          s->par_pernode |= 1u << a;
+          break;
+        }
+    }
+    s->par_uniform[a] = v;
+  }
+  if (s->par_pernode) {
+    if (dalloc((char**)&s->d_par, (size_t)P * Np * es))
+      return fail(MONO_ENOMEM, "device allocation failed");
+    HIP_TRY(hipMemsetAsync(s->d_par, 0, (size_t)P * Np * es, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int a = 0; a < P; ++a)
+      if (s->par_pernode >> a & 1u) {
+        st = upload_real(s, (char*)s->d_par + (size_t)a * Np * es, params + (size_t)a * s->n, s->n);
+        if (st != MONO_OK) return st;
+      }
+  }
+  s->dt0 = dt0;
+  s->lat_thr = default_lat_threshold(model);
+  s->step = 0;
+  HIP_TRY(hipMemsetAsync(s->d_base, 0, 8, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_flag, 0, sizeof(int), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->latched = false;
+  if (s->dt > 0.0) {
+    const double dt = s->dt;
+    s->dt = -1.0;
+    return prepare(s, dt);
+  }
+  return MONO_OK;
+}
+
+mono_status mono_set_lat_threshold(mono_sim* s, double v) {
+  if (!s || !std::isfinite(v)) return fail(MONO_EINVAL, "bad argument");
+  s->lat_thr = v;
+  drop_graph(s);
+  return MONO_OK;
+}
+
+mono_status mono_add_stimulus(mono_sim* s, int64_t n, const int32_t* nodes, double t_on,
+                              double duration, double amplitude) {
+  if (!s || (n > 0 && !nodes) || n < 0) return fail(MONO_EINVAL, "bad argument");
+  if (s->stim.n >= kMaxStim) return fail(MONO_EUNSUPPORTED, "at most 8 stimuli");
+  if (!std::isfinite(t_on) || !(duration >= 0.0) || !std::isfinite(amplitude))
+    return fail(MONO_EINVAL, "bad stimulus timing or amplitude");
+  std::vector<uint8_t> mask(s->Np, 0);
+  if (s->d_mask) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(mask.data(), s->d_mask, s->Np, hipMemcpyDeviceToHost));
+  } else if (dalloc(&s->d_mask, s->Np)) {
+    return fail(MONO_ENOMEM, "device allocation failed");
+  }
+  const int b = s->stim.n;
+  for (int64_t q = 0; q < n; ++q) {
+    if (nodes[q] < 0 || nodes[q] >= s->n) return fail(MONO_EINVAL, "stimulus node out of range");
+    mask[nodes[q]] |= (uint8_t)(1u << b);
+  }
+  HIP_TRY(hipMemcpy(s->d_mask, mask.data(), s->Np, hipMemcpyHostToDevice));
+  s->stim.t_on[b] = t_on;
+  s->stim.t_end[b] = t_on + duration;
+  s->stim.amp[b] = amplitude;
+  s->stim.n = b + 1;
+  drop_graph(s);
+  return MONO_OK;
+}
+
+mono_status mono_set_method(mono_sim* s, int32_t method, int32_t dvdt_source, int32_t l_round) {
+  if (!s || method < MONO_DAETI || method > MONO_OST || dvdt_source < 0 || dvdt_source > 1 ||
+      l_round < 0 || l_round > 1)
+    return fail(MONO_EINVAL, "bad method flags");
+  s->method = method;
+  s->dvdt_src = dvdt_source;
+  s->l_round = l_round;
+  drop_graph(s);
+  if (s->dt > 0.0) {
+    const double dt = s->dt;
+    s->dt = -1.0;
+    return prepare(s, dt);
+  }
+  return MONO_OK;
+}
+
+mono_status mono_prepare(mono_sim* s, double dt) {
+  if (!s) return fail(MONO_EINVAL, "NULL simulation");
+  return prepare(s, dt);
+}
+
+mono_status mono_step(mono_sim* s, int64_t n_steps, double dt, uint32_t flags) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (n_steps < 0) return fail(MONO_EINVAL, "negative step count");
+  if (s->latched) return fail(MONO_ESTATE, "simulation latched after a non-finite potential");
+  st = prepare(s, dt);
+  if (st != MONO_OK) return st;
+  int64_t left = n_steps;
+  if (flags & 2u) {
+    st = enqueue_timed(s, n_steps);
+    if (st != MONO_OK) return st;
+    HIP_TRY(hipGetLastError());
+    s->step += n_steps;
+    return MONO_OK;
+  }
+  if (!(flags & 1u) && left >= kGraphChunk) {
+    st = ensure_graph(s);
+    if (st != MONO_OK) return st;
+    while (left >= kGraphChunk) {
+      HIP_TRY(hipGraphLaunch(s->gexec, s->stream));
+      left -= kGraphChunk;
+    }
+  }
+  if (left > 0) enqueue(s, left);
+  HIP_TRY(hipGetLastError());
+  s->step += n_steps;
+  return MONO_OK;
+}
+
+mono_status mono_apply_phase(mono_sim* s, int32_t phase, int64_t step, int32_t m) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (s->dt <= 0.0) return fail(MONO_ESTATE, "call mono_prepare first");
+  if (phase < 0 || phase > 2 || step < 0 || m < 0 || m >= s->l_max)
+    return fail(MONO_EINVAL, "bad phase, step or substep");
+  HIP_TRY(hipMemcpyAsync(s->d_base, &step, 8, hipMemcpyHostToDevice, s->stream));
+  if (phase == 1) {
+    if (s->prec == MONO_F64)
+      launch_ionic<double>(s->model, ion_args<double>(s, s->d_V[0], 0), s->stream);
+    else
+      launch_ionic<float>(s->model, ion_args<float>(s, s->d_V[0], 0), s->stream);
+  } else {
+    const int half = phase / 2;
+    if (s->prec == MONO_F64)
+      launch_diffusion<double>(s->layout, diff_args<double>(s, 0, half, m, 0), s->stream);
+    else
+      launch_diffusion<float>(s->layout, diff_args<float>(s, 0, half, m, 0), s->stream);
+    HIP_TRY(hipMemcpyAsync(s->d_V[0], s->d_V[1], s->Np * s->es, hipMemcpyDeviceToDevice,
+                           s->stream));
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(s->d_base, &s->step, 8, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return check_flag(s);
+}
+
+mono_status mono_get_state(mono_sim* s, int32_t field, double* dst, int64_t count) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (!dst || count != s->n) return fail(MONO_EINVAL, "count must equal n_nodes");
+  size_t es = 0;
+  void* src = field_ptr(s, field, es);
+  if (!src) return fail(MONO_EINVAL, "unknown field");
+  if (field == MONO_FIELD_LAT) {
+    HIP_TRY(hipMemcpyAsync(dst, src, s->n * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else if (field == MONO_FIELD_K) {
+    std::vector<uint8_t> k(s->n);
+    HIP_TRY(hipMemcpyAsync(k.data(), src, s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < s->n; ++i) dst[i] = k[i];
+  } else {
+    st = download_real(s, dst, src, s->n);
+    if (st != MONO_OK) return st;
+  }
+  return check_flag(s);
+}
+
+mono_status mono_get_state_device_async(mono_sim* s, int32_t field, void* dev_dst) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (!dev_dst) return fail(MONO_EINVAL, "NULL destination");
+  size_t es = 0;
+  void* src = field_ptr(s, field, es);
+  if (!src) return fail(MONO_EINVAL, "unknown field");
+  HIP_TRY(hipMemcpyAsync(dev_dst, src, s->n * es, hipMemcpyDeviceToDevice, s->stream));
+  return MONO_OK;
+}
+
+mono_status mono_set_state(mono_sim* s, int32_t field, const double* src, int64_t count) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (!src || count != s->n) return fail(MONO_EINVAL, "count must equal n_nodes");
+  if (field == MONO_FIELD_K) return fail(MONO_EINVAL, "field K is read-only");
+  size_t es = 0;
+  void* dst = field_ptr(s, field, es);
+  if (!dst) return fail(MONO_EINVAL, "unknown field");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (field == MONO_FIELD_LAT) {
+    HIP_TRY(hipMemcpy(dst, src, s->n * 8, hipMemcpyHostToDevice));
+  } else {
+    st = upload_real(s, dst, src, s->n);
+    if (st != MONO_OK) return st;
+  }
+  if (field == MONO_FIELD_V || field == MONO_FIELD_STATE0) {
+    HIP_TRY(hipMemsetAsync(s->d_flag, 0, sizeof(int), s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->latched = false;
+  }
+  return MONO_OK;
+}
+
+mono_status mono_set_time_level(mono_sim* s, int64_t step) {
+  if (!s || step < 0) return fail(MONO_EINVAL, "bad argument");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->step = step;
+  HIP_TRY(hipMemcpy(s->d_base, &step, 8, hipMemcpyHostToDevice));
+  return MONO_OK;
+}
+
+mono_status mono_get_info(mono_sim* s, int32_t inst, mono_info* out) {
+  if (!s || !out) return fail(MONO_EINVAL, "NULL argument");
+  if (inst < 0 || inst >= s->n_inst) return fail(MONO_EINVAL, "bad instance index");
+  std::memset(out, 0, sizeof(*out));
+  out->dt_s = s->dt_s[inst];
+  out->G_max = s->gmax[inst];
+  out->lambda_est = s->lambda[inst];
+  out->dt = s->dt > 0.0 ? s->dt : 0.0;
+  if (s->dt > 0.0) {
+    out->dt_ad = s->dt_ad[inst];
+    out->l = s->l[inst];
+    out->k_max = s->k_max;
+    out->t = (double)s->step * s->dt;
+  }
+  out->step = s->step;
+  out->nnz = s->nnz;
+  out->layout = s->layout;
+  out->n_instances = s->n_inst;
+  out->n_states = s->S;
+  out->ell_width = s->layout == MONO_LAYOUT_ELL ? s->W : s->P;
+  return MONO_OK;
+}
+
+mono_status mono_estimate_lambda(mono_sim* s, int32_t iters) {
+  if (!s || iters < 1) return fail(MONO_EINVAL, "bad argument");
+  const int ni = s->n_inst;
+  int64_t* rp = nullptr;
+  int32_t* col = nullptr;
+  double *val = nullptr, *mass = nullptr, *x = nullptr, *kx = nullptr, *xkx = nullptr,
+         *xmx = nullptr;
+  bool ok = !dalloc(&rp, s->n + 1) && !dalloc(&col, s->nnz) && !dalloc(&val, s->nnz) &&
+            !dalloc(&mass, s->n) && !dalloc(&x, s->n) && !dalloc(&kx, s->n) &&
+            !dalloc(&xkx, ni) && !dalloc(&xmx, ni);
+  std::vector<double> a(ni), b(ni);
+  if (ok)
+    ok = !hipMemcpy(rp, s->K.rp.data(), (s->n + 1) * 8, hipMemcpyHostToDevice) &&
+         !hipMemcpy(col, s->K.col.data(), s->nnz * 4, hipMemcpyHostToDevice) &&
+         !hipMemcpy(val, s->K.val.data(), s->nnz * 8, hipMemcpyHostToDevice) &&
+         !hipMemcpy(mass, s->K.mass.data(), s->n * 8, hipMemcpyHostToDevice);
+  if (ok) {
+    const int32_t* inst = ni > 1 ? s->d_inst : nullptr;
+    launch_power_init(s->n, x, s->stream);
+    for (int it = 0; it < iters; ++it) {
+      launch_spmv_csr(s->n, rp, col, val, x, kx, s->stream);
+      launch_segmented_dots(ni, s->d_inst_off, x, kx, mass, xkx, xmx, s->stream);
+      launch_power_update(s->n, inst, kx, mass, xmx, x, s->stream);
+    }
+    launch_spmv_csr(s->n, rp, col, val, x, kx, s->stream);
+    launch_segmented_dots(ni, s->d_inst_off, x, kx, mass, xkx, xmx, s->stream);
+    ok = !hipMemcpyAsync(a.data(), xkx, ni * 8, hipMemcpyDeviceToHost, s->stream) &&
+         !hipMemcpyAsync(b.data(), xmx, ni * 8, hipMemcpyDeviceToHost, s->stream) &&
+         !hipStreamSynchronize(s->stream) && !hipGetLastError();
+  }
+  dfree(rp);
+  dfree(col);
+  dfree(val);
+  dfree(mass);
+  dfree(x);
+  dfree(kx);
+  dfree(xkx);
+  dfree(xmx);
+  if (!ok) return fail(MONO_EDEVICE, "power iteration failed");
+  for (int q = 0; q < ni; ++q) {
+    s->lambda[q] = a[q] / b[q];
+    if (s->dt > 0.0 && !(s->dt_ad[q] < 2.0 / s->lambda[q]))
+      return fail(MONO_ESTATE, "dt_ad violates the forward Euler bound 2/lambda_max");
+  }
+  return MONO_OK;
+}
+
+mono_status mono_set_stream(mono_sim* s, void* stream) {
+  if (!s || !stream) return fail(MONO_EINVAL, "bad argument");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (s->own_stream) HIP_TRY(hipStreamDestroy(s->stream));
+  s->own_stream = false;
+  s->stream = (hipStream_t)stream;
+  return MONO_OK;
+}
+
+mono_status mono_sync(mono_sim* s) {
+  if (!s) return fail(MONO_EINVAL, "NULL simulation");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return check_flag(s);
+}
+
+mono_status mono_debug(mono_sim* s, int32_t what, void* arg) {
+  if (!s) return fail(MONO_EINVAL, "NULL simulation");
+  switch (what) {
+    case MONO_DEBUG_KTRACE: {
+      if (!arg) return fail(MONO_EINVAL, "NULL argument");
+      const mono_ktrace* k = (const mono_ktrace*)arg;
+      if (k->mode < 0 || k->mode > 3 || ((k->mode & 1) && !k->record) ||
+          ((k->mode & 2) && !k->replay) || (k->mode && k->n_steps < 0))
+        return fail(MONO_EINVAL, "bad k-trace description");
+      s->kt.mode = k->mode;
+      s->kt.rec = k->record;
+      s->kt.rep = k->replay;
+      s->kt.base = k->base_step;
+      s->kt.steps = k->mode ? k->n_steps : 0;
+      drop_graph(s);
+      return MONO_OK;
+    }
+    case MONO_DEBUG_VCLAMP:
+      if (!arg) return fail(MONO_EINVAL, "NULL argument");
+      s->vclamp = *(const int32_t*)arg ? 1 : 0;
+      drop_graph(s);
+      return MONO_OK;
+    case MONO_DEBUG_FORCE_L: {
+      if (!arg || *(const int32_t*)arg < 0) return fail(MONO_EINVAL, "bad argument");
+      s->force_l = *(const int32_t*)arg;
+      if (s->dt > 0.0) {
+        const double dt = s->dt;
+        s->dt = -1.0;
+        return prepare(s, dt);
+      }
+      return MONO_OK;
+    }
+    case MONO_DEBUG_STATS_ENABLE: {
+      if (!arg) return fail(MONO_EINVAL, "NULL argument");
+      const bool on = *(const int32_t*)arg != 0;
+      if (on && !s->d_stats && dalloc(&s->d_stats, 4)) return fail(MONO_ENOMEM, "allocation failed");
+      if (on) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        HIP_TRY(hipMemsetAsync(s->d_stats, 0, 4 * sizeof(unsigned long long), s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+      }
+      s->stats_on = on;
+      drop_graph(s);
+      return MONO_OK;
+    }
+    case MONO_DEBUG_STATS: {
+      if (!arg) return fail(MONO_EINVAL, "NULL argument");
+      int64_t* o = (int64_t*)arg;
+      if (!s->d_stats) {
+        std::memset(o, 0, 4 * sizeof(int64_t));
+        return MONO_OK;
+      }
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      HIP_TRY(hipMemcpy(o, s->d_stats, 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+      return MONO_OK;
+    }
+    case MONO_DEBUG_KTIMES: {
+      if (!arg) return fail(MONO_EINVAL, "NULL argument");
+      double* o = (double*)arg;
+      const bool reset = o[4] != 0.0;
+      o[0] = s->ktime_ms[0];
+      o[1] = (double)s->klaunches[0];
+      o[2] = s->ktime_ms[1];
+      o[3] = (double)s->klaunches[1];
+      if (reset) {
+        s->ktime_ms[0] = s->ktime_ms[1] = 0.0;
+        s->klaunches[0] = s->klaunches[1] = 0;
+      }
+      return MONO_OK;
+    }
+    default:
+      return fail(MONO_EINVAL, "unknown debug request");
+  }
+}
+
+}  // extern "C"

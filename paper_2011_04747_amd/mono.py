@@ -1,0 +1,258 @@
+"""Thin ctypes binding of libmono (include/mono.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies streams and device buffers where a device pointer is asked
+for.  Importing this module does not load the library; the first use does,
+and raises if libmono.so has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmono.so")
+
+F64, F32 = 0, 1
+LAYOUT_AUTO, LAYOUT_ELL, LAYOUT_STENCIL = 0, 1, 2
+FIELD_V, FIELD_VPREV, FIELD_LAT, FIELD_K, FIELD_STATE0 = 0, 1, 2, 3, 16
+DAETI, OSTAR, OST = 0, 1, 2
+DEBUG_KTRACE, DEBUG_VCLAMP, DEBUG_FORCE_L, DEBUG_STATS, DEBUG_STATS_ENABLE = 1, 2, 3, 4, 5
+DEBUG_KTIMES = 6
+STEP_EAGER, STEP_TIMED = 1, 2
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSUPPORTED",
+          -6: "ENONFINITE"}
+
+# exported entry points (include/mono.h); tests check every one is present
+EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
+           "mono_add_stimulus", "mono_set_method", "mono_step", "mono_get_state",
+           "mono_get_state_device_async", "mono_set_state", "mono_set_time_level",
+           "mono_prepare", "mono_get_info", "mono_estimate_lambda", "mono_set_stream",
+           "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug")
+
+
+class MonoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("xyz", C.c_void_p),
+                ("etype", C.c_int32), ("n_elems", C.c_int64), ("conn", C.c_void_p),
+                ("D_elem", C.c_void_p), ("sigma_node", C.c_void_p), ("prec", C.c_int32),
+                ("stream", C.c_void_p), ("n_instances", C.c_int32),
+                ("inst_node_off", C.c_void_p), ("layout", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("dt_s", C.c_double), ("G_max", C.c_double), ("lambda_est", C.c_double),
+                ("dt_ad", C.c_double), ("dt", C.c_double), ("t", C.c_double),
+                ("step", C.c_int64), ("nnz", C.c_int64), ("l", C.c_int32), ("k_max", C.c_int32),
+                ("layout", C.c_int32), ("n_instances", C.c_int32), ("n_states", C.c_int32),
+                ("ell_width", C.c_int32)]
+
+
+class KTrace(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("record", C.c_void_p), ("replay", C.c_void_p),
+                ("n_steps", C.c_int64), ("base_step", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmono.so (raises if it is missing: the HIP path is the only path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python paper_2011_04747_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "mono_create_mesh": [C.POINTER(MeshDesc), C.POINTER(vp)],
+            "mono_set_cell_model": [vp, i32, i32, vp, vp, dbl],
+            "mono_set_lat_threshold": [vp, dbl],
+            "mono_add_stimulus": [vp, i64, vp, dbl, dbl, dbl],
+            "mono_set_method": [vp, i32, i32, i32],
+            "mono_step": [vp, i64, dbl, C.c_uint32],
+            "mono_get_state": [vp, i32, vp, i64],
+            "mono_get_state_device_async": [vp, i32, vp],
+            "mono_set_state": [vp, i32, vp, i64],
+            "mono_set_time_level": [vp, i64],
+            "mono_prepare": [vp, dbl],
+            "mono_get_info": [vp, i32, C.POINTER(Info)],
+            "mono_estimate_lambda": [vp, i32],
+            "mono_set_stream": [vp, vp],
+            "mono_sync": [vp],
+            "mono_apply_phase": [vp, i32, i64, i32],
+            "mono_debug": [vp, i32, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.mono_destroy.argtypes = [vp]
+        L.mono_destroy.restype = None
+        L.mono_last_error.argtypes = []
+        L.mono_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MonoError(rc, lib().mono_last_error().decode())
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Sim:
+    """One monodomain simulation on the GPU (a handle of libmono)."""
+
+    def __init__(self, mesh, precision: str = "f64", stream=None, layout: int = LAYOUT_AUTO):
+        L = lib()
+        self.n = mesh.n_nodes
+        self.precision = precision
+        xyz = _c(mesh.xyz, np.float64)
+        conn = _c(mesh.conn, np.int32)
+        D = _c(mesh.D_elem, np.float64)
+        sig = None if mesh.sigma is None else _c(mesh.sigma, np.float64)
+        off = None if mesh.inst_node_off is None else _c(mesh.inst_node_off, np.int64)
+        self.stream = stream
+        d = MeshDesc(mesh.dim, self.n, xyz.ctypes.data, mesh.etype, mesh.n_elems,
+                     conn.ctypes.data, D.ctypes.data, None if sig is None else sig.ctypes.data,
+                     F64 if precision == "f64" else F32,
+                     None if stream is None else int(stream), mesh.n_instances,
+                     None if off is None else off.ctypes.data, layout)
+        h = C.c_void_p()
+        _check(L.mono_create_mesh(C.byref(d), C.byref(h)))
+        self.h = h
+        self.n_instances = mesh.n_instances
+        self.model = None
+
+    @classmethod
+    def from_workload(cls, w, precision: Optional[str] = None, stream=None,
+                      layout: int = LAYOUT_AUTO, with_stimuli: bool = True):
+        s = cls(w.mesh, precision or w.precision, stream, layout)
+        s.set_cell_model(w.model, w.params, None, w.dt0)
+        s.set_lat_threshold(w.lat_threshold)
+        if with_stimuli:
+            for st in w.stimuli:
+                s.add_stimulus(st.nodes, st.t_on, st.duration, st.amplitude)
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mono_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup -------------------------------------------------------------------
+    def set_cell_model(self, model, params=None, init_state=None, dt0=0.01):
+        p = None if params is None else _c(params, np.float64)
+        y = None if init_state is None else _c(init_state, np.float64)
+        npar = 0 if p is None else p.shape[0]
+        _check(lib().mono_set_cell_model(self.h, model, npar, None if p is None else p.ctypes.data,
+                                         None if y is None else y.ctypes.data, dt0))
+        self.model = model
+
+    def set_lat_threshold(self, v):
+        _check(lib().mono_set_lat_threshold(self.h, float(v)))
+
+    def add_stimulus(self, nodes, t_on, duration, amplitude):
+        nodes = _c(nodes, np.int32)
+        _check(lib().mono_add_stimulus(self.h, len(nodes), nodes.ctypes.data, float(t_on),
+                                       float(duration), float(amplitude)))
+
+    def set_method(self, method=DAETI, dvdt_source=0, l_round=0):
+        _check(lib().mono_set_method(self.h, method, dvdt_source, l_round))
+
+    def prepare(self, dt):
+        _check(lib().mono_prepare(self.h, float(dt)))
+
+    # -- stepping ----------------------------------------------------------------
+    def step(self, n_steps, dt, flags=0):
+        _check(lib().mono_step(self.h, int(n_steps), float(dt), int(flags)))
+
+    def sync(self):
+        _check(lib().mono_sync(self.h))
+
+    def apply_phase(self, phase, step, m=0):
+        _check(lib().mono_apply_phase(self.h, int(phase), int(step), int(m)))
+
+    def get(self, field):
+        out = np.zeros(self.n, np.float64)
+        _check(lib().mono_get_state(self.h, int(field), out.ctypes.data, self.n))
+        return out
+
+    def state(self, j):
+        return self.get(FIELD_STATE0 + j)
+
+    def get_device_async(self, field, dst_ptr):
+        _check(lib().mono_get_state_device_async(self.h, int(field), C.c_void_p(int(dst_ptr))))
+
+    def set(self, field, values):
+        v = _c(values, np.float64)
+        assert v.shape == (self.n,)
+        _check(lib().mono_set_state(self.h, int(field), v.ctypes.data, self.n))
+
+    def set_time_level(self, step):
+        _check(lib().mono_set_time_level(self.h, int(step)))
+
+    def info(self, inst=0):
+        i = Info()
+        _check(lib().mono_get_info(self.h, int(inst), C.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    def estimate_lambda(self, iters=100):
+        _check(lib().mono_estimate_lambda(self.h, int(iters)))
+
+    def set_stream(self, stream):
+        _check(lib().mono_set_stream(self.h, C.c_void_p(int(stream))))
+
+    # -- test hooks --------------------------------------------------------------
+    def ktrace(self, mode, record_ptr=None, replay_ptr=None, n_steps=0, base_step=0):
+        kt = KTrace(int(mode), None if record_ptr is None else int(record_ptr),
+                    None if replay_ptr is None else int(replay_ptr), int(n_steps), int(base_step))
+        _check(lib().mono_debug(self.h, DEBUG_KTRACE, C.byref(kt)))
+        self._kt = kt
+
+    def vclamp(self, on):
+        v = C.c_int32(int(on))
+        _check(lib().mono_debug(self.h, DEBUG_VCLAMP, C.byref(v)))
+
+    def force_l(self, l):
+        v = C.c_int32(int(l))
+        _check(lib().mono_debug(self.h, DEBUG_FORCE_L, C.byref(v)))
+
+    def stats_enable(self, on=True):
+        v = C.c_int32(int(on))
+        _check(lib().mono_debug(self.h, DEBUG_STATS_ENABLE, C.byref(v)))
+
+    def stats(self):
+        """(sum k, sum over wavefronts of 64*max k, node-steps, node-steps at k_max)."""
+        out = (C.c_int64 * 4)()
+        _check(lib().mono_debug(self.h, DEBUG_STATS, out))
+        return tuple(out)
+
+    def kernel_times(self, reset=False):
+        """Per-class kernel time of STEP_TIMED steps:
+        {diffusion_ms, diffusion_launches, reaction_ms, reaction_launches}."""
+        out = (C.c_double * 5)()
+        out[4] = 1.0 if reset else 0.0
+        _check(lib().mono_debug(self.h, DEBUG_KTIMES, out))
+        return dict(diffusion_ms=out[0], diffusion_launches=int(out[1]),
+                    reaction_ms=out[2], reaction_launches=int(out[3]))

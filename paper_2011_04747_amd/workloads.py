@@ -353,3 +353,23 @@ def adjoint_slab(shape=(101, 101, 26), dx: float = 0.01, D_l: float = 0.0012,
                     [_planar_s1(mesh.xyz, a)], dt, t_end, 0.01, precision, -40.0,
                     sensors=sensors, extra={"sigma_target": sigma_target,
                                             "ckpt_every": 50})
+
+
+def random_state(model: int, n_nodes: int, seed: int) -> np.ndarray:
+    """Seeded cell states (n_states x n_nodes) spread over each variable's
+    physiological range, for single-launch parity checks at full size."""
+    rng = np.random.default_rng(seed)
+    if model == MODEL_LINEAR:
+        return rng.uniform(-90.0, 40.0, (1, n_nodes))
+    if model == MODEL_MS:
+        return np.vstack([rng.uniform(0.0, 1.0, n_nodes), rng.uniform(0.0, 1.0, n_nodes)])
+    y = np.empty((19, n_nodes))
+    y[0] = rng.uniform(-90.0, 40.0, n_nodes)            # V, mV
+    y[1] = rng.uniform(130.0, 140.0, n_nodes)           # K_i
+    y[2] = rng.uniform(6.0, 12.0, n_nodes)              # Na_i
+    y[3] = 10 ** rng.uniform(-4.5, -3.0, n_nodes)       # Ca_i
+    y[4] = 10 ** rng.uniform(-4.5, -1.0, n_nodes)       # Ca_ss
+    y[5] = rng.uniform(0.5, 4.0, n_nodes)               # Ca_SR
+    y[6] = rng.uniform(0.5, 1.0, n_nodes)               # Rbar
+    y[7:] = rng.uniform(0.0, 1.0, (12, n_nodes))        # gates
+    return y
