@@ -1,0 +1,212 @@
+"""Throughput benchmark of the DAETI monodomain solver on one MI355X.
+
+Workload: the 3D TP06 slab, 2 x 2 x 0.5 cm at dx = 0.01 cm (201 x 201 x 51 =
+2,060,451 nodes), trilinear hexes, fibres rotating -60..+60 deg through the
+wall, a seeded ischemic ellipsoid ([K+]o = 8 mM, g_Na x 0.7), S1 at x = 0 and
+a cross-field S2 at 320 ms, dt = 0.1 ms, FP32 state and operator with FP64
+time, stable-step estimate and activation times.
+
+A step is one outer DAETI step (B(dt/2) A(dt) B(dt/2)) over the whole mesh;
+`value` is node-updates per second over the K timed steps (inputs resident in
+HBM), timed with events on the simulation's stream between device-wide
+synchronisations.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("node-updates/s (ionic+diffusion) at stated accuracy vs FP64 plain; "
+          "adjoint/fwd ratio")
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def _sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (copy-calibrated), or None when absent or when the kernel's
+    sources have changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if _sha(t["sources"]) != t["source_sha"]:
+        return None
+    return t["bytes_per_launch"]
+
+
+def cpu_baseline(w, steps):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the workload."""
+    from oracle.oracle import Oracle
+    o = Oracle.from_workload(w)
+    o.prepare(w.dt)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    o.step(steps, w.dt)
+    el = time.perf_counter() - t0
+    return {"value": w.mesh.n_nodes * steps / el, "unit": "node-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full {w.mesh.n_nodes}-node slab, FP64, first {steps} outer steps "
+                      f"from t=0 (assembly excluded), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=320)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--layout", default="auto", choices=["auto", "ell", "stencil"])
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU halo decomposition is a design, not a build).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2011_04747_amd import mono
+    from paper_2011_04747_amd import workloads as W
+
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    layout = {"auto": mono.LAYOUT_AUTO, "ell": mono.LAYOUT_ELL,
+              "stencil": mono.LAYOUT_STENCIL}[args.layout]
+    w = W.slab_ischemic(precision="f32")
+    n = w.mesh.n_nodes
+    stream = torch.cuda.Stream()
+    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    info = sim.info()
+
+    # warm-up (also builds the cached graph)
+    sim.step(args.warmup, w.dt)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    sim.step(args.steps, w.dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    info = sim.info()
+    value = n * args.steps / (ms * 1e-3)
+
+    v32 = sim.get(mono.FIELD_V)
+    l32 = sim.get(mono.FIELD_LAT)
+    sim.close()
+
+    # per-kernel durations over the same simulated window: an identical
+    # simulation repeats the warm-up, then runs the K timed steps one launch at
+    # a time, each kernel bracketed by HIP events on the simulation's stream;
+    # the substep counts k each node took are read back between steps
+    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    sim.step(args.warmup, w.dt)
+    sim.kernel_times(reset=True)
+    kbuf = torch.zeros(((n + 63) // 64) * 64, dtype=torch.uint8, device="cuda")
+    ksum = kwave = ksat = 0
+    kt_steps = args.steps
+    for _ in range(kt_steps):
+        sim.step(1, w.dt, flags=mono.STEP_TIMED)
+        with torch.cuda.stream(stream):
+            sim.get_device_async(mono.FIELD_K, kbuf.data_ptr())
+            kk = kbuf.to(torch.int64)
+            ksum += int(kk.sum())
+            kwave += 64 * int(kk.view(-1, 64).amax(dim=1).sum())
+            ksat += int((kk[:n] == info["k_max"]).sum())
+    torch.cuda.synchronize()
+    kt = sim.kernel_times()
+    sim.close()
+    d_us = 1e3 * kt["diffusion_ms"] / max(1, kt["diffusion_launches"])
+    r_us = 1e3 * kt["reaction_ms"] / max(1, kt["reaction_launches"])
+
+    # algorithmic work per launch
+    P = info["ell_width"]
+    if info["layout"] == mono.LAYOUT_STENCIL:
+        row_bytes = (P + 3) * 4      # own edges, 1/m, V in, V out
+    else:
+        row_bytes = P * 8 + 2 * 4    # (value, column) per slot, V in, V out
+    diff_bytes = n * row_bytes
+    from oracle.oracle import model_init  # rest state for the op count
+    ops = mono.model_flops(W.MODEL_TP06, model_init(W.MODEL_TP06), W.TP06_PARAM_DEFAULT)
+    f_model = ops["add"] + ops["mul"] + ops["div"] + ops["exp"] + ops["log"] + ops["sqrt"]
+    react_flops = (ksum / kt_steps) * f_model
+    diff_total = kt["diffusion_ms"] / kt_steps
+    react_total = kt["reaction_ms"] / kt_steps
+    diff_roof = {"kernel": "k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL else "k_diff_ell",
+                 "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
+                 "avg_us": d_us, "traffic": _traffic("diffusion")}
+    diff_roof["frac"] = diff_roof["achieved"] / HBM_PEAK_GBS
+    react_roof = {"kernel": "k_ionic<float,TP06>", "bound": "alu",
+                  "achieved": react_flops / (r_us * 1e-6) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                  "unit": "TFLOP/s", "ops_per_substep": ops, "substeps_per_launch": ksum / kt_steps,
+                  "wavefront_efficiency": ksum / kwave if kwave else None, "avg_us": r_us,
+                  "traffic": _traffic("reaction")}
+    react_roof["frac"] = react_roof["achieved"] / FP32_VECTOR_PEAK_TFLOPS
+    dominant = react_roof if react_total >= diff_total else diff_roof
+    roofline = {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+    roofline["kernel"] = dominant["kernel"]
+
+    # accuracy against the FP64 path (itself checked against the FP64 oracle)
+    accuracy = None
+    if not args.no_accuracy:
+        total = args.warmup + args.steps
+        ref = mono.Sim.from_workload(w, "f64", stream=stream.cuda_stream, layout=layout)
+        ref.step(total, w.dt)
+        v64 = ref.get(mono.FIELD_V)
+        l64 = ref.get(mono.FIELD_LAT)
+        ref.close()
+        both = (l32 > 0) & (l64 > 0)
+        accuracy = {"reference": "FP64 path of the same kernels (parity-tested against the "
+                                 "FP64 CPU oracle)",
+                    "t_ms": total * w.dt,
+                    "v_rms_mV": float(np.sqrt(np.mean((v32 - v64) ** 2))),
+                    "v_max_mV": float(np.abs(v32 - v64).max()),
+                    "lat_max_ms": float(np.abs(l32 - l64)[both].max()) if both.any() else None,
+                    "activated_equal": bool(((l32 > 0) == (l64 > 0)).all())}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "slab_tp06_3d_ischemic 201x201x51 (2,060,451 nodes), "
+                                  "Q1 hexes, dx=0.01 cm, dt=0.1 ms, S1+S2",
+                      "nodes": n, "nnz": info["nnz"], "l": info["l"], "dt_ad": info["dt_ad"],
+                      "k_max": info["k_max"],
+                      "layout": "stencil" if info["layout"] == mono.LAYOUT_STENCIL else "ell",
+                      "sim_ms_per_s": w.dt * args.steps / (ms * 1e-3),
+                      "mean_k": ksum / (n * kt_steps), "k_at_kmax_frac": ksat / (n * kt_steps),
+                      "wall_s": wall},
+           "roofline": roofline,
+           "kernels": {"diffusion": diff_roof, "reaction": react_roof,
+                       "ms_per_step": {"diffusion": diff_total, "reaction": react_total}},
+           "accuracy": accuracy, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

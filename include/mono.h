@@ -201,6 +201,13 @@ mono_status mono_sync(mono_sim *sim);
 void mono_destroy(mono_sim *sim);
 const char *mono_last_error(void);
 
+/* Operations of one substep of a cell model at the given state and
+ * parameters (host arrays of the model's sizes), counted on the reaction
+ * kernel's own model code: out[7] = {add/sub, mul, div, exp, log, sqrt,
+ * compare}.  The count follows the branches the state selects.  Host only. */
+mono_status mono_model_flops(int32_t model, const double *state, const double *params,
+                             int64_t *out);
+
 /* Apply one phase of outer step `step` to the current state (testing the
  * kernels one launch at a time).  phase 0: diffusion substep `m` of the first
  * half step; 1: the reaction step; 2: diffusion substep `m` of the second

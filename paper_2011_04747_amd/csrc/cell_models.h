@@ -1,0 +1,315 @@
+// Cell models of the reaction step (paper Sec. 2, step A), written once as
+// templates over the scalar type: the reaction kernel instantiates them in
+// FP32 and FP64, and the host instantiates them on a counting type to obtain
+// the exact arithmetic of one substep.
+//
+// Every model advances one substep of length h from the substep-start state:
+// gates by Rush-Larsen (y <- y_inf + (y - y_inf) exp(-h/tau)), every other
+// variable by forward Euler.  State 0 is V.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mono {
+
+// --- arithmetic primitives --------------------------------------------------
+// FP64 uses IEEE division and the accurate math library throughout.  FP32
+// uses the hardware reciprocal, exp2 and log2 instructions (about 1 ulp each,
+// no denormals) in place of the correctly rounded multi-instruction
+// sequences; the difference is at the 1e-6 relative level, far inside the
+// FP32 tolerances, and cuts the substep's instruction count severalfold.
+__host__ __device__ __forceinline__ double xexp(double x) { return exp(x); }
+__host__ __device__ __forceinline__ double xexpm1(double x) { return expm1(x); }
+__host__ __device__ __forceinline__ double xlog(double x) { return log(x); }
+__host__ __device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ double xrcp(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ double xfloor(double x) { return floor(x); }
+__host__ __device__ __forceinline__ float xexpm1(float x) { return expm1f(x); }
+__host__ __device__ __forceinline__ float xfloor(float x) { return floorf(x); }
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ float xexp(float x) { return __expf(x); }
+__device__ __forceinline__ float xlog(float x) { return __logf(x); }
+__device__ __forceinline__ float xsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float xrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+#else
+inline float xexp(float x) { return expf(x); }
+inline float xlog(float x) { return logf(x); }
+inline float xsqrt(float x) { return sqrtf(x); }
+inline float xrcp(float x) { return 1.0f / x; }
+#endif
+
+template <typename T>
+__host__ __device__ __forceinline__ T xdiv(T a, T b) {
+  return a * xrcp(b);
+}
+// logistic 1 / (1 + e^z)
+template <typename T>
+__host__ __device__ __forceinline__ T sig(T z) {
+  return xrcp(T(1) + xexp(z));
+}
+// Rush-Larsen update with the rate 1/tau given directly
+template <typename T>
+__host__ __device__ __forceinline__ T rl_rate(T y, T yinf, T rate, T h) {
+  return yinf + (y - yinf) * xexp(-h * rate);
+}
+template <typename T>
+__host__ __device__ __forceinline__ T rush_larsen(T y, T yinf, T tau, T h) {
+  return rl_rate(y, yinf, xrcp(tau), h);
+}
+
+// ---------------------------------------------------------------------------
+// linear test model: dV/dt = -g (V - E);  p = {g, E}
+// ---------------------------------------------------------------------------
+struct LinearModel {
+  static constexpr int S = 1, P = 2;
+  template <typename T>
+  __host__ __device__ static T vrate(const T* y, const T* p) { return -p[0] * (y[0] - p[1]); }
+  template <typename T>
+  __host__ __device__ static void substep(T* y, const T* p, T h, bool clamp) {
+    if (!clamp) y[0] = y[0] + h * (-p[0] * (y[0] - p[1]));
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Mitchell & Schaeffer (2003): v' = h v^2 (1-v)/tau_in - v/tau_out;
+// h' = (1-h)/tau_open below v_gate, -h/tau_close from v_gate up.
+// p = {tau_in, tau_out, tau_open, tau_close, v_gate}
+// ---------------------------------------------------------------------------
+struct MSModel {
+  static constexpr int S = 2, P = 5;
+  template <typename T>
+  __host__ __device__ static T vrate(const T* y, const T* p) {
+    const T v = y[0];
+    return xdiv(y[1] * v * v * (T(1) - v), p[0]) - xdiv(v, p[1]);
+  }
+  template <typename T>
+  __host__ __device__ static void substep(T* y, const T* p, T h, bool clamp) {
+    const T v = y[0], g = y[1];
+    const T dv = xdiv(g * v * v * (T(1) - v), p[0]) - xdiv(v, p[1]);
+    const bool open = v < p[4];
+    y[1] = rush_larsen(g, open ? T(1) : T(0), open ? p[2] : p[3], h);
+    if (!clamp) y[0] = v + h * dv;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// ten Tusscher & Panfilov (2006), epicardial cell.
+// y = {V, Ki, Nai, Cai, Cass, CaSR, Rbar, m, h, j, xr1, xr2, xs, r, s, d, f,
+//      f2, fCass};  p = {Ko, gNa, gCaL, gKr, gKs, gK1 scalings}
+// Currents in pA/pF, concentrations in mM, time in ms.  Ca_i, Ca_ss and
+// Ca_SR are buffered instantaneously: forward Euler moves the total
+// (free + bound) amount and the free value is recovered from the quadratic.
+// ---------------------------------------------------------------------------
+namespace tp06 {
+constexpr double kR = 8314.472, kT = 310.0, kF = 96485.3415;
+constexpr double kRTF = kR * kT / kF;      // mV
+constexpr double kFRT = kF / (kR * kT);    // 1/mV
+constexpr double kCap = 0.185;             // cell capacitance (uF)
+constexpr double kVc = 0.016404, kVsr = 0.001094, kVss = 0.00005468;
+constexpr double kNao = 140.0, kCao = 2.0;
+constexpr double kGNa = 14.838, kGK1 = 5.405, kGto = 0.294, kGKr = 0.153, kGKs = 0.392;
+constexpr double kPKNa = 0.03, kGCaL = 3.980e-5;
+constexpr double kNaCaMax = 1000.0, kNaCaGam = 0.35, kKmCa = 1.38, kKmNai = 87.5;
+constexpr double kNaCaSat = 0.1, kNaCaAlpha = 2.5;
+constexpr double kPNaK = 2.724, kKmK = 1.0, kKmNa = 40.0;
+constexpr double kGpK = 0.0146, kGpCa = 0.1238, kKpCa = 0.0005, kGbNa = 0.00029, kGbCa = 0.000592;
+constexpr double kVmaxUp = 0.006375, kKup = 0.00025, kVrel = 0.102;
+constexpr double kK1p = 0.15, kK2p = 0.045, kK3 = 0.060, kK4 = 0.005;
+constexpr double kEC = 1.5, kMaxSR = 2.5, kMinSR = 1.0, kVleak = 0.00036, kVxfer = 0.0038;
+constexpr double kBufc = 0.2, kKbufc = 0.001, kBufsr = 10.0, kKbufsr = 0.3;
+constexpr double kBufss = 0.4, kKbufss = 0.00025;
+// concentration change per unit current: Cm / (V F)
+constexpr double kCurToConc = kCap / (kVc * kF);
+}  // namespace tp06
+
+// free concentration c from a new total c_tot = c + B c / (c + K), i.e. the
+// positive root of c^2 + (B + K - c_tot) c - K c_tot = 0, in the form that
+// avoids cancellation
+template <typename T>
+__host__ __device__ __forceinline__ T free_from_total(T tot, T B, T K) {
+  const T b = B + K - tot;
+  const T c = K * tot;
+  const T disc = xsqrt(b * b + T(4) * c);
+  return (b >= T(0)) ? xdiv(T(2) * c, b + disc) : T(0.5) * (disc - b);
+}
+template <typename T>
+__host__ __device__ __forceinline__ T total_from_free(T c, T B, T K) {
+  return c + xdiv(B * c, c + K);
+}
+
+template <typename T>
+struct TP06Fluxes {
+  T Iion, INa, IbNa, INaK, INaCa, IK, ICaL, IbCa, IpCa;   // IK: K+ carrying currents
+  T Irel, Iup, Ileak, Ixfer;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP06Fluxes<T>& c) {
+  using namespace tp06;
+  const T V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5], Rb = y[6];
+  const T Ko = p[0];
+  const T rtf = T(kRTF), frt = T(kFRT);
+  const T EK = rtf * xlog(xdiv(Ko, Ki));
+  const T ENa = rtf * xlog(xdiv(T(kNao), Nai));
+  const T ECa = T(0.5) * rtf * xlog(xdiv(T(kCao), Cai));
+  const T EKs = rtf * xlog(xdiv(Ko + T(kPKNa * kNao), Ki + T(kPKNa) * Nai));
+  const T sqKo = xsqrt(Ko * T(1.0 / 5.4));
+
+  const T m = y[7], hh = y[8], jj = y[9];
+  c.INa = p[1] * T(kGNa) * m * m * m * hh * jj * (V - ENa);
+
+  const T vk = V - EK;
+  const T aK1 = T(0.1) * sig(T(0.06) * (vk - T(200)));
+  const T bK1 = (T(3) * xexp(T(0.0002) * (vk + T(100))) + xexp(T(0.1) * (vk - T(10)))) *
+                sig(T(-0.5) * vk);
+  const T IK1 = p[5] * T(kGK1) * sqKo * xdiv(aK1, aK1 + bK1) * vk;
+  const T Ito = T(kGto) * y[13] * y[14] * vk;
+  const T IKr = p[3] * T(kGKr) * sqKo * y[10] * y[11] * vk;
+  const T IKs = p[4] * T(kGKs) * y[12] * y[12] * (V - EKs);
+  const T IpK = T(kGpK) * vk * sig((T(25) - V) * T(1.0 / 5.98));
+
+  // L-type Ca current with the removable singularity at V = 15 mV handled
+  // through x / (e^x - 1)
+  const T x = T(2) * (V - T(15)) * frt;
+  const T xe = (x == T(0)) ? T(1) : xdiv(x, xexpm1(x));
+  c.ICaL = p[2] * T(kGCaL * 2.0 * kF) * y[15] * y[16] * y[17] * y[18] * xe *
+           (T(0.25) * Cass * xexp(x) - T(kCao));
+
+  // e^{-VF/RT} serves the Na/Ca exchanger and the Na/K pump
+  const T u = xexp(-V * frt);
+  const T eg = xexp(T(kNaCaGam) * V * frt);
+  const T eg1 = eg * u;
+  const T denom = T((kKmNai * kKmNai * kKmNai + kNao * kNao * kNao) * (kKmCa + kCao));
+  c.INaCa = T(kNaCaMax) *
+            xdiv(eg * Nai * Nai * Nai * T(kCao) - eg1 * T(kNao * kNao * kNao * kNaCaAlpha) * Cai,
+                 denom * (T(1) + T(kNaCaSat) * eg1));
+  c.INaK = T(kPNaK) * xdiv(Ko * Nai, (Ko + T(kKmK)) * (Nai + T(kKmNa)) *
+                                         (T(1) + T(0.1245) * xexp(T(-0.1) * V * frt) +
+                                          T(0.0353) * u));
+  c.IpCa = T(kGpCa) * xdiv(Cai, T(kKpCa) + Cai);
+  c.IbNa = T(kGbNa) * (V - ENa);
+  c.IbCa = T(kGbCa) * (V - ECa);
+  c.IK = IK1 + Ito + IKr + IKs + IpK;
+  c.Iion = c.INa + c.IK + c.ICaL + c.INaCa + c.INaK + c.IpCa + c.IbNa + c.IbCa;
+
+  const T r_sr = xdiv(T(kEC), CaSR);
+  const T kcasr = T(kMaxSR) - T(kMaxSR - kMinSR) * xrcp(T(1) + r_sr * r_sr);
+  const T k1 = xdiv(T(kK1p), kcasr);
+  const T cs2 = Cass * Cass;
+  c.Irel = T(kVrel) * xdiv(k1 * cs2 * Rb, T(kK3) + k1 * cs2) * (CaSR - Cass);
+  const T ci2 = Cai * Cai;
+  c.Iup = T(kVmaxUp) * xdiv(ci2, ci2 + T(kKup * kKup));
+  c.Ileak = T(kVleak) * (CaSR - Cai);
+  c.Ixfer = T(kVxfer) * (Cass - Cai);
+}
+
+struct TP06Model {
+  static constexpr int S = 19, P = 6;
+  template <typename T>
+  __host__ __device__ static T vrate(const T* y, const T* p) {
+    TP06Fluxes<T> c;
+    tp06_fluxes(y, p, c);
+    return -c.Iion;
+  }
+  template <typename T>
+  __host__ __device__ static void substep(T* y, const T* p, T h, bool clamp) {
+    using namespace tp06;
+    TP06Fluxes<T> c;
+    tp06_fluxes(y, p, c);
+    const T V = y[0];
+    const T cc = T(kCurToConc);
+    // forward Euler: V, Ki, Nai, Rbar; buffered totals of Ca_i, Ca_ss, Ca_SR
+    const T dKi = -(c.IK - T(2) * c.INaK) * cc;
+    const T dNai = -(c.INa + c.IbNa + T(3) * c.INaK + T(3) * c.INaCa) * cc;
+    const T dCai = -(c.IbCa + c.IpCa - T(2) * c.INaCa) * T(0.5) * cc +
+                   T(kVsr / kVc) * (c.Ileak - c.Iup) + c.Ixfer;
+    const T dCass = -c.ICaL * T(kCap / (2.0 * kVss * kF)) + T(kVsr / kVss) * c.Irel -
+                    T(kVc / kVss) * c.Ixfer;
+    const T dCaSR = c.Iup - c.Ileak - c.Irel;
+    const T r_sr = xdiv(T(kEC), y[5]);
+    const T kcasr = T(kMaxSR) - T(kMaxSR - kMinSR) * xrcp(T(1) + r_sr * r_sr);
+    const T dRb = -T(kK2p) * kcasr * y[4] * y[6] + T(kK4) * (T(1) - y[6]);
+
+    // gates from the substep-start V (and Ca_ss for fCass); rates 1/tau are
+    // formed directly where tau = 1/(alpha + beta)
+    T g[12];
+    {
+      const T e = sig((T(-56.86) - V) * T(1.0 / 9.03));
+      const T am = sig((T(-60) - V) * T(0.2));
+      const T bm = T(0.1) * sig((V + T(35)) * T(0.2)) + T(0.1) * sig((V - T(50)) * T(0.005));
+      g[0] = rush_larsen(y[7], e * e, am * bm, h);
+    }
+    {
+      const T e = sig((V + T(71.55)) * T(1.0 / 7.43));
+      const T inf = e * e;
+      T rh, rj;
+      if (V >= T(-40)) {
+        rh = T(0.77 / 0.13) * sig(-(V + T(10.66)) * T(1.0 / 11.1));
+        rj = T(0.6) * xexp(T(0.057) * V) * sig(T(-0.1) * (V + T(32)));
+      } else {
+        rh = T(0.057) * xexp(-(V + T(80)) * T(1.0 / 6.8)) + T(2.7) * xexp(T(0.079) * V) +
+             T(3.1e5) * xexp(T(0.3485) * V);
+        rj = (T(-2.5428e4) * xexp(T(0.2444) * V) - T(6.948e-6) * xexp(T(-0.04391) * V)) *
+                 (V + T(37.78)) * sig(T(0.311) * (V + T(79.23))) +
+             T(0.02424) * xexp(T(-0.01052) * V) * sig(T(-0.1378) * (V + T(40.14)));
+      }
+      g[1] = rl_rate(y[8], inf, rh, h);
+      g[2] = rl_rate(y[9], inf, rj, h);
+    }
+    const T s30 = sig((V + T(30)) * T(0.1));    // shared by f and f2
+    {
+      const T a1 = T(450) * sig((T(-45) - V) * T(0.1));
+      const T b1 = T(6) * sig((V + T(30)) * T(1.0 / 11.5));
+      g[3] = rush_larsen(y[10], sig((T(-26) - V) * T(1.0 / 7.0)), a1 * b1, h);
+      const T a2 = T(3) * sig((T(-60) - V) * T(0.05));
+      const T b2 = T(1.12) * sig((V - T(60)) * T(0.05));
+      g[4] = rush_larsen(y[11], sig((V + T(88)) * T(1.0 / 24.0)), a2 * b2, h);
+    }
+    {
+      const T a = T(1400) * xrcp(xsqrt(T(1) + xexp((T(5) - V) * T(1.0 / 6.0))));
+      const T b = sig((V - T(35)) * T(1.0 / 15.0));
+      g[5] = rush_larsen(y[12], sig((T(-5) - V) * T(1.0 / 14.0)), a * b + T(80), h);
+    }
+    {
+      const T vr = V + T(40), vs = V + T(45);
+      g[6] = rush_larsen(y[13], sig((T(20) - V) * T(1.0 / 6.0)),
+                         T(9.5) * xexp(-vr * vr * T(1.0 / 1800.0)) + T(0.8), h);
+      g[7] = rush_larsen(y[14], sig((V + T(20)) * T(0.2)),
+                         T(85) * xexp(-vs * vs * T(1.0 / 320.0)) + T(5) * sig((V - T(20)) * T(0.2)) +
+                             T(3),
+                         h);
+    }
+    {
+      const T ad = T(1.4) * sig((T(-35) - V) * T(1.0 / 13.0)) + T(0.25);
+      const T bd = T(1.4) * sig((V + T(5)) * T(0.2));
+      const T gd = sig((T(50) - V) * T(0.05));
+      g[8] = rush_larsen(y[15], sig((T(-8) - V) * T(1.0 / 7.5)), ad * bd + gd, h);
+      const T vf = V + T(27);
+      const T tf = T(1102.5) * xexp(-vf * vf * T(1.0 / 225.0)) +
+                   T(200) * sig((T(13) - V) * T(0.1)) + T(180) * s30 + T(20);
+      g[9] = rush_larsen(y[16], sig((V + T(20)) * T(1.0 / 7.0)), tf, h);
+      const T vf2 = V + T(25);
+      const T tf2 = T(600) * xexp(-vf2 * vf2 * T(1.0 / 170.0)) +
+                    T(31) * sig((T(25) - V) * T(0.1)) + T(16) * s30;
+      g[10] = rush_larsen(y[17], T(0.67) * sig((V + T(35)) * T(1.0 / 7.0)) + T(0.33), tf2, h);
+      const T q = (y[4] * T(20)) * (y[4] * T(20));
+      const T r1q = xrcp(T(1) + q);
+      g[11] = rush_larsen(y[18], T(0.6) * r1q + T(0.4), T(80) * r1q + T(2), h);
+    }
+
+    // commit
+    y[3] = free_from_total(total_from_free(y[3], T(kBufc), T(kKbufc)) + h * dCai, T(kBufc),
+                           T(kKbufc));
+    y[4] = free_from_total(total_from_free(y[4], T(kBufss), T(kKbufss)) + h * dCass, T(kBufss),
+                           T(kKbufss));
+    y[5] = free_from_total(total_from_free(y[5], T(kBufsr), T(kKbufsr)) + h * dCaSR, T(kBufsr),
+                           T(kKbufsr));
+    y[1] = y[1] + h * dKi;
+    y[2] = y[2] + h * dNai;
+    y[6] = y[6] + h * dRb;
+    for (int a = 0; a < 12; ++a) y[7 + a] = g[a];
+    if (!clamp) y[0] = V - h * c.Iion;
+  }
+};
+
+}  // namespace mono

@@ -116,7 +116,7 @@ struct mono_sim {
   // debug
   KTraceArgs kt{};
   int vclamp = 0, force_l = 0;
-  unsigned long long* d_stats = nullptr;
+  unsigned long long* d_stats = nullptr;   // 4 counters, 16 apart
   bool stats_on = false;
   // per-kernel timing of MONO_STEP_TIMED calls: [0] diffusion, [1] reaction
   std::vector<hipEvent_t> ev_pool;
@@ -947,10 +947,10 @@ mono_status mono_debug(mono_sim* s, int32_t what, void* arg) {
     case MONO_DEBUG_STATS_ENABLE: {
       if (!arg) return fail(MONO_EINVAL, "NULL argument");
       const bool on = *(const int32_t*)arg != 0;
-      if (on && !s->d_stats && dalloc(&s->d_stats, 4)) return fail(MONO_ENOMEM, "allocation failed");
+      if (on && !s->d_stats && dalloc(&s->d_stats, 64)) return fail(MONO_ENOMEM, "allocation failed");
       if (on) {
         HIP_TRY(hipStreamSynchronize(s->stream));
-        HIP_TRY(hipMemsetAsync(s->d_stats, 0, 4 * sizeof(unsigned long long), s->stream));
+        HIP_TRY(hipMemsetAsync(s->d_stats, 0, 64 * sizeof(unsigned long long), s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
       }
       s->stats_on = on;
@@ -965,7 +965,9 @@ mono_status mono_debug(mono_sim* s, int32_t what, void* arg) {
         return MONO_OK;
       }
       HIP_TRY(hipStreamSynchronize(s->stream));
-      HIP_TRY(hipMemcpy(o, s->d_stats, 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+      unsigned long long h[64];
+      HIP_TRY(hipMemcpy(h, s->d_stats, sizeof(h), hipMemcpyDeviceToHost));
+      for (int q = 0; q < 4; ++q) o[q] = (int64_t)h[q * 16];
       return MONO_OK;
     }
     case MONO_DEBUG_KTIMES: {

@@ -32,7 +32,8 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_add_stimulus", "mono_set_method", "mono_step", "mono_get_state",
            "mono_get_state_device_async", "mono_set_state", "mono_set_time_level",
            "mono_prepare", "mono_get_info", "mono_estimate_lambda", "mono_set_stream",
-           "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug")
+           "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
+           "mono_model_flops")
 
 
 class MonoError(RuntimeError):
@@ -92,6 +93,7 @@ def lib():
             "mono_sync": [vp],
             "mono_apply_phase": [vp, i32, i64, i32],
             "mono_debug": [vp, i32, vp],
+            "mono_model_flops": [i32, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -112,6 +114,16 @@ def _check(rc):
 
 def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def model_flops(model, state, params):
+    """Operation counts of one cell-model substep at `state` (host-side count
+    on the kernel's own model code): dict add, mul, div, exp, log, sqrt, cmp."""
+    y = _c(state, np.float64)
+    p = _c(params, np.float64)
+    out = np.zeros(7, np.int64)
+    _check(lib().mono_model_flops(int(model), y.ctypes.data, p.ctypes.data, out.ctypes.data))
+    return dict(zip(("add", "mul", "div", "exp", "log", "sqrt", "cmp"), (int(v) for v in out)))
 
 
 class Sim:
