@@ -39,15 +39,17 @@ def _sha(paths):
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel):
+def _traffic(kernel, workload, launch):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary (copy-calibrated), or None when absent or when the kernel's
-    sources have changed since the counters were taken."""
+    summary (copy-calibrated), or None when absent, taken on another workload
+    or launch shape, or when the kernel's sources have changed since."""
     p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
+    if t.get("bench_workload") != workload or t.get("launch") not in (None, launch):
+        return None
     if _sha(t["sources"]) != t["source_sha"]:
         return None
     return t["bytes_per_launch"]
@@ -74,6 +76,8 @@ def main():
     ap.add_argument("--steps", type=int, default=320)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--layout", default="auto", choices=["auto", "ell", "stencil"])
+    ap.add_argument("--workload", default="slab", choices=["slab", "batched"])
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -90,10 +94,21 @@ def main():
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     layout = {"auto": mono.LAYOUT_AUTO, "ell": mono.LAYOUT_ELL,
               "stencil": mono.LAYOUT_STENCIL}[args.layout]
-    w = W.slab_ischemic(precision="f32")
+    if args.workload == "slab":
+        w = W.slab_ischemic(precision="f32")
+        wl_name = ("slab_tp06_3d_ischemic 201x201x51 (2,060,451 nodes), Q1 hexes, dx=0.01 cm, "
+                   "dt=0.1 ms, S1+S2")
+    else:
+        w = W.batched_sheets(precision="f32")
+        wl_name = (f"batched_tp06_2d: 64 sheets, sides U{{50..400}} seed 4, "
+                   f"{w.mesh.n_nodes} nodes, log-normal sigma, dt=0.1 ms")
     n = w.mesh.n_nodes
     stream = torch.cuda.Stream()
     sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    launch = sim.launch()
+    if not args.no_tune:
+        from paper_2011_04747_amd import autotune
+        launch = autotune.tune(sim, w.dt)
     info = sim.info()
 
     # warm-up (also builds the cached graph)
@@ -120,6 +135,7 @@ def main():
     # a time, each kernel bracketed by HIP events on the simulation's stream;
     # the substep counts k each node took are read back between steps
     sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    sim.set_launch(**launch)
     sim.step(args.warmup, w.dt)
     sim.kernel_times(reset=True)
     kbuf = torch.zeros(((n + 63) // 64) * 64, dtype=torch.uint8, device="cuda")
@@ -145,6 +161,8 @@ def main():
         row_bytes = (P + 3) * 4      # own edges, 1/m, V in, V out
     else:
         row_bytes = P * 8 + 2 * 4    # (value, column) per slot, V in, V out
+    if info["n_instances"] > 1:
+        row_bytes += 4               # instance id of the row
     diff_bytes = n * row_bytes
     from oracle.oracle import model_init  # rest state for the op count
     ops = mono.model_flops(W.MODEL_TP06, model_init(W.MODEL_TP06), W.TP06_PARAM_DEFAULT)
@@ -152,16 +170,17 @@ def main():
     react_flops = (ksum / kt_steps) * f_model
     diff_total = kt["diffusion_ms"] / kt_steps
     react_total = kt["reaction_ms"] / kt_steps
-    diff_roof = {"kernel": "k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL else "k_diff_ell",
+    diff_roof = {"kernel": ("k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL
+                            else "k_diff_ell") + f"<float,{P}>",
                  "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
-                 "avg_us": d_us, "traffic": _traffic("diffusion")}
+                 "avg_us": d_us, "traffic": _traffic("diffusion", args.workload, launch)}
     diff_roof["frac"] = diff_roof["achieved"] / HBM_PEAK_GBS
     react_roof = {"kernel": "k_ionic<float,TP06>", "bound": "alu",
                   "achieved": react_flops / (r_us * 1e-6) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                   "unit": "TFLOP/s", "ops_per_substep": ops, "substeps_per_launch": ksum / kt_steps,
                   "wavefront_efficiency": ksum / kwave if kwave else None, "avg_us": r_us,
-                  "traffic": _traffic("reaction")}
+                  "traffic": _traffic("reaction", args.workload, launch)}
     react_roof["frac"] = react_roof["achieved"] / FP32_VECTOR_PEAK_TFLOPS
     dominant = react_roof if react_total >= diff_total else diff_roof
     roofline = {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
@@ -193,8 +212,7 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": "slab_tp06_3d_ischemic 201x201x51 (2,060,451 nodes), "
-                                  "Q1 hexes, dx=0.01 cm, dt=0.1 ms, S1+S2",
+           "config": {"workload": wl_name, "launch": launch,
                       "nodes": n, "nnz": info["nnz"], "l": info["l"], "dt_ad": info["dt_ad"],
                       "k_max": info["k_max"],
                       "layout": "stencil" if info["layout"] == mono.LAYOUT_STENCIL else "ell",

@@ -192,6 +192,22 @@ mono_status mono_get_info(mono_sim *sim, int32_t inst, mono_info *out);
  * and check dt_ad < 2/lambda_est for the last prepared dt. */
 mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
 
+/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32).  Block sizes
+ * 128, 256 or 512 lanes; rows per lane of the stencil diffusion kernel 1, 2
+ * or 4 (FP64: 1 or 2; ignored by the ELL layout); XCD remap 0/1 (deal
+ * contiguous row ranges to each of the 8 XCDs); graph_steps 1..8192 outer
+ * steps per captured HIP graph (a whole run can be one graph).  Results do
+ * not depend on the shape (bitwise). */
+typedef struct {
+  int32_t diff_block;
+  int32_t diff_rows_per_lane;
+  int32_t diff_xcd_remap;
+  int32_t react_block;
+  int32_t graph_steps;
+} mono_launch;
+mono_status mono_set_launch(mono_sim *sim, const mono_launch *cfg);
+mono_status mono_get_launch(mono_sim *sim, mono_launch *out);
+
 /* Replace the borrowed stream. */
 mono_status mono_set_stream(mono_sim *sim, void *stream);
 

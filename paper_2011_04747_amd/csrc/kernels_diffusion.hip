@@ -17,12 +17,50 @@
 
 namespace mono {
 
-__device__ __forceinline__ int64_t xcd_row_block(int64_t nb) {
-  // hardware dispatch: workgroup b runs on XCD b % 8
+// Workgroup index of this block.  With `remap`, logical blocks are dealt so
+// that XCD x (which receives hardware workgroups x, x+8, x+16, ...) owns one
+// contiguous range of rows.
+__device__ __forceinline__ int64_t row_block(int64_t nb, int remap) {
   const int64_t b = blockIdx.x;
+  if (!remap) return b;
   const int64_t x = b & 7, idx = b >> 3;
   const int64_t per = nb >> 3, rem = nb & 7;
   return x * per + (x < rem ? x : rem) + idx;
+}
+
+// R consecutive values starting at an R-aligned index, in one vector access
+template <int R, typename T>
+__device__ __forceinline__ void vload(const T* p, T (&v)[R]) {
+  if constexpr (R == 1) {
+    v[0] = p[0];
+  } else if constexpr (R == 2 && sizeof(T) == 4) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  } else if constexpr (R == 4 && sizeof(T) == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  } else if constexpr (R == 2 && sizeof(T) == 8) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = p[r];
+  }
+}
+template <int R, typename T>
+__device__ __forceinline__ void vstore(T* p, const T (&v)[R]) {
+  if constexpr (R == 1) {
+    p[0] = v[0];
+  } else if constexpr (R == 2 && sizeof(T) == 4) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  } else if constexpr (R == 4 && sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 2 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r] = v[r];
+  }
 }
 
 __device__ __forceinline__ double tmul(double a, double b) { return __dmul_rn(a, b); }
@@ -53,10 +91,10 @@ __device__ __forceinline__ T stimulus_rate(const DiffArgs<T>& a, int64_t i, doub
   return r;
 }
 
-template <typename T, bool BATCHED>
-__global__ __launch_bounds__(kBlock) void k_diff_ell(DiffArgs<T> a) {
-  const int64_t nb = (a.n + kBlock - 1) / kBlock;
-  const int64_t i = xcd_row_block(nb) * kBlock + threadIdx.x;
+template <typename T, bool BATCHED, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_diff_ell(DiffArgs<T> a) {
+  const int64_t nb = (a.n + BLOCK - 1) / BLOCK;
+  const int64_t i = row_block(nb, a.xcd) * BLOCK + threadIdx.x;
   if (i >= a.n) return;
   const int q = BATCHED ? a.inst[i] : 0;
   const T vi = a.Vin[i];
@@ -82,79 +120,133 @@ __global__ __launch_bounds__(kBlock) void k_diff_ell(DiffArgs<T> a) {
 // entries of absent neighbours are zero, so clamping only keeps loads in
 // bounds; a backward neighbour before the instance's first node belongs to
 // another instance (whose slots mean other offsets) and is skipped.
-template <typename T, int P, bool BATCHED>
-__global__ __launch_bounds__(kBlock) void k_diff_stencil(DiffArgs<T> a) {
-  const int64_t nb = (a.n + kBlock - 1) / kBlock;
-  const int64_t i = xcd_row_block(nb) * kBlock + threadIdx.x;
-  if (i >= a.n) return;
-  const int q = BATCHED ? a.inst[i] : 0;
-  const T vi = a.Vin[i];
-  if (BATCHED && a.m >= a.l[q]) {
-    a.Vout[i] = vi;
-    return;
-  }
-  const int32_t* off = a.off + (int64_t)q * P;
+// Each lane owns RPL consecutive rows: its own edges, 1/m, V_i and the result
+// move as RPL-wide vector accesses; the neighbour gathers stay scalar.
+// P = 0 reads the number of offsets at run time.  Padding rows (n <= i < Np)
+// have zero edges, zero 1/m and zero potential, so they are computed as 0.
+template <typename T, int P, bool BATCHED, int BLOCK, int RPL>
+__global__ __launch_bounds__(BLOCK) void k_diff_stencil(DiffArgs<T> a) {
+  const int64_t nlanes = (a.n + RPL - 1) / RPL;
+  const int64_t nb = (nlanes + BLOCK - 1) / BLOCK;
+  const int64_t lane = row_block(nb, a.xcd) * BLOCK + threadIdx.x;
+  const int64_t i0 = lane * RPL;
+  if (i0 >= a.n) return;
+  const int np = P > 0 ? P : a.P;
   const int64_t last = a.n - 1;
-  const int64_t first = BATCHED ? a.inst_off[q] : 0;
-  T acc = T(0);
+  T vi[RPL], acc[RPL];
+  vload<RPL>(a.Vin + i0, vi);
+  int q[RPL];
+  int64_t first[RPL];
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int64_t o = off[p];
-    const int64_t jf = i + o;
-    const int64_t jb = i - o;
-    const T wf = a.e[(int64_t)p * a.Np + i];
-    const int64_t jbc = jb >= first ? jb : first;
-    const T wb = (jb >= first) ? a.e[(int64_t)p * a.Np + jbc] : T(0);
-    const T vf = a.Vin[jf <= last ? jf : last];
-    const T vb = a.Vin[jbc];
-    acc += wf * (vf - vi);
-    acc += wb * (vb - vi);
+  for (int r = 0; r < RPL; ++r) {
+    q[r] = BATCHED ? a.inst[i0 + r] : 0;
+    first[r] = BATCHED ? a.inst_off[q[r]] : 0;
+    acc[r] = T(0);
   }
-  const double dt_ad = a.dt_ad[q];
-  const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
-  const T r = a.minv[i] * acc + stimulus_rate(a, i, tau);
-  a.Vout[i] = vi + (T)dt_ad * r;
+  auto edge = [&](int p) {
+    T wf[RPL];
+    vload<RPL>(a.e + (int64_t)p * a.Np + i0, wf);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int64_t i = i0 + r;
+      const int64_t o = a.off[(int64_t)q[r] * np + p];
+      const int64_t jf = i + o;
+      const int64_t jb = i - o;
+      const int64_t jbc = jb >= first[r] ? jb : first[r];
+      const T wb = (jb >= first[r]) ? a.e[(int64_t)p * a.Np + jbc] : T(0);
+      const T vf = a.Vin[jf <= last ? jf : last];
+      const T vb = a.Vin[jbc];
+      acc[r] += wf[r] * (vf - vi[r]);
+      acc[r] += wb * (vb - vi[r]);
+    }
+  };
+  if constexpr (P > 0) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) edge(p);
+  } else {
+    for (int p = 0; p < np; ++p) edge(p);
+  }
+  T mv[RPL], out[RPL];
+  vload<RPL>(a.minv + i0, mv);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int64_t i = i0 + r;
+    if (BATCHED && a.m >= a.l[q[r]]) {
+      out[r] = vi[r];
+      continue;
+    }
+    const double dt_ad = a.dt_ad[q[r]];
+    const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
+    const T sr = (i < a.n) ? stimulus_rate(a, i, tau) : T(0);
+    out[r] = vi[r] + (T)dt_ad * (mv[r] * acc[r] + sr);
+  }
+  vstore<RPL>(a.Vout + i0, out);
+}
+
+template <typename T, int P, bool BATCHED, int BLOCK, int RPL>
+static void launch_stencil_k(const DiffArgs<T>& a, hipStream_t s) {
+  const int64_t nlanes = (a.n + RPL - 1) / RPL;
+  const dim3 grid((unsigned)((nlanes + BLOCK - 1) / BLOCK));
+  hipLaunchKernelGGL((k_diff_stencil<T, P, BATCHED, BLOCK, RPL>), grid, dim3(BLOCK), 0, s, a);
+}
+
+template <typename T, int P, bool BATCHED, int BLOCK>
+static void launch_stencil_r(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (c.diff_rpl == 4) return launch_stencil_k<T, P, BATCHED, BLOCK, 4>(a, s);
+  }
+  if (c.diff_rpl == 2) return launch_stencil_k<T, P, BATCHED, BLOCK, 2>(a, s);
+  launch_stencil_k<T, P, BATCHED, BLOCK, 1>(a, s);
+}
+
+template <typename T, int P, bool BATCHED>
+static void launch_stencil_b(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (c.diff_block == 128) return launch_stencil_r<T, P, BATCHED, 128>(a, c, s);
+  if (c.diff_block == 512) return launch_stencil_r<T, P, BATCHED, 512>(a, c, s);
+  launch_stencil_r<T, P, BATCHED, 256>(a, c, s);
 }
 
 template <typename T, int P>
-static void launch_stencil_p(const DiffArgs<T>& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.n + kBlock - 1) / kBlock));
+static void launch_stencil_p(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
   if (a.inst)
-    hipLaunchKernelGGL((k_diff_stencil<T, P, true>), grid, dim3(kBlock), 0, s, a);
+    launch_stencil_b<T, P, true>(a, c, s);
   else
-    hipLaunchKernelGGL((k_diff_stencil<T, P, false>), grid, dim3(kBlock), 0, s, a);
+    launch_stencil_b<T, P, false>(a, c, s);
+}
+
+template <typename T, bool BATCHED, int BLOCK>
+static void launch_ell_k(const DiffArgs<T>& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + BLOCK - 1) / BLOCK));
+  hipLaunchKernelGGL((k_diff_ell<T, BATCHED, BLOCK>), grid, dim3(BLOCK), 0, s, a);
+}
+template <typename T, bool BATCHED>
+static void launch_ell_b(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (c.diff_block == 128) return launch_ell_k<T, BATCHED, 128>(a, s);
+  if (c.diff_block == 512) return launch_ell_k<T, BATCHED, 512>(a, s);
+  launch_ell_k<T, BATCHED, 256>(a, s);
 }
 
 template <typename T>
-void launch_diffusion(int layout, const DiffArgs<T>& a, hipStream_t s) {
+void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
   if (a.n <= 0) return;
-  const dim3 grid((unsigned)((a.n + kBlock - 1) / kBlock));
   if (layout == MONO_LAYOUT_ELL) {
     if (a.inst)
-      hipLaunchKernelGGL((k_diff_ell<T, true>), grid, dim3(kBlock), 0, s, a);
+      launch_ell_b<T, true>(a, c, s);
     else
-      hipLaunchKernelGGL((k_diff_ell<T, false>), grid, dim3(kBlock), 0, s, a);
+      launch_ell_b<T, false>(a, c, s);
     return;
   }
   switch (a.P) {
-    case 1: launch_stencil_p<T, 1>(a, s); break;
-    case 2: launch_stencil_p<T, 2>(a, s); break;
-    case 3: launch_stencil_p<T, 3>(a, s); break;
-    case 4: launch_stencil_p<T, 4>(a, s); break;
-    case 5: launch_stencil_p<T, 5>(a, s); break;
-    case 6: launch_stencil_p<T, 6>(a, s); break;
-    case 7: launch_stencil_p<T, 7>(a, s); break;
-    case 8: launch_stencil_p<T, 8>(a, s); break;
-    case 9: launch_stencil_p<T, 9>(a, s); break;
-    case 10: launch_stencil_p<T, 10>(a, s); break;
-    case 11: launch_stencil_p<T, 11>(a, s); break;
-    case 12: launch_stencil_p<T, 12>(a, s); break;
-    default: launch_stencil_p<T, 13>(a, s); break;
+    case 1: launch_stencil_p<T, 1>(a, c, s); break;
+    case 4: launch_stencil_p<T, 4>(a, c, s); break;
+    case 13: launch_stencil_p<T, 13>(a, c, s); break;
+    default: launch_stencil_p<T, 0>(a, c, s); break;
   }
 }
 
-template void launch_diffusion<float>(int, const DiffArgs<float>&, hipStream_t);
-template void launch_diffusion<double>(int, const DiffArgs<double>&, hipStream_t);
+template void launch_diffusion<float>(int, const DiffArgs<float>&, const LaunchCfg&, hipStream_t);
+template void launch_diffusion<double>(int, const DiffArgs<double>&, const LaunchCfg&,
+                                       hipStream_t);
 
 __global__ void k_advance_clock(int64_t* base, int64_t by) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *base += by;

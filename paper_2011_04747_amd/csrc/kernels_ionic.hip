@@ -27,9 +27,9 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-template <typename T, class M>
-__global__ __launch_bounds__(kBlock) void k_ionic(IonArgs<T> a) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+template <typename T, class M, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_ionic(IonArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool live = i < a.n;
   const int64_t step = *a.clk.base + a.clk.g;
   const double dt = a.clk.dt;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_ionic(IonArgs<T> a) {
   if (a.stats) {
     // k statistics: wavefront reductions, then one atomic per workgroup and
     // counter (diagnostic path, off by default)
-    __shared__ unsigned long long part[4][kBlock / 64];
+    __shared__ unsigned long long part[4][BLOCK / 64];
     const unsigned long long ks = wave_sum_u64((unsigned long long)k);
     const int kmax = wave_max_i(k);
     const unsigned long long sat = wave_sum_u64((live && k == a.k_max) ? 1ull : 0ull);
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_ionic(IonArgs<T> a) {
     __syncthreads();
     if (threadIdx.x < 4) {
       unsigned long long v = 0;
-      for (int q = 0; q < kBlock / 64; ++q) v += part[threadIdx.x][q];
+      for (int q = 0; q < BLOCK / 64; ++q) v += part[threadIdx.x][q];
       atomicAdd(&a.stats[threadIdx.x * 16], v);   // one 128-byte line per counter
     }
   }
@@ -103,19 +103,30 @@ __global__ __launch_bounds__(kBlock) void k_ionic(IonArgs<T> a) {
   for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
 }
 
-template <typename T>
-void launch_ionic(int model, const IonArgs<T>& a, hipStream_t s) {
-  if (a.n <= 0) return;
-  const dim3 grid((unsigned)((a.n + kBlock - 1) / kBlock));
-  if (model == MONO_MODEL_LINEAR)
-    hipLaunchKernelGGL((k_ionic<T, LinearModel>), grid, dim3(kBlock), 0, s, a);
-  else if (model == MONO_MODEL_MS)
-    hipLaunchKernelGGL((k_ionic<T, MSModel>), grid, dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_ionic<T, TP06Model>), grid, dim3(kBlock), 0, s, a);
+template <typename T, class M, int BLOCK>
+static void launch_ionic_k(const IonArgs<T>& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + BLOCK - 1) / BLOCK));
+  hipLaunchKernelGGL((k_ionic<T, M, BLOCK>), grid, dim3(BLOCK), 0, s, a);
+}
+template <typename T, class M>
+static void launch_ionic_m(const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (c.react_block == 128) return launch_ionic_k<T, M, 128>(a, s);
+  if (c.react_block == 512) return launch_ionic_k<T, M, 512>(a, s);
+  launch_ionic_k<T, M, 256>(a, s);
 }
 
-template void launch_ionic<float>(int, const IonArgs<float>&, hipStream_t);
-template void launch_ionic<double>(int, const IonArgs<double>&, hipStream_t);
+template <typename T>
+void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (a.n <= 0) return;
+  if (model == MONO_MODEL_LINEAR)
+    launch_ionic_m<T, LinearModel>(a, c, s);
+  else if (model == MONO_MODEL_MS)
+    launch_ionic_m<T, MSModel>(a, c, s);
+  else
+    launch_ionic_m<T, TP06Model>(a, c, s);
+}
+
+template void launch_ionic<float>(int, const IonArgs<float>&, const LaunchCfg&, hipStream_t);
+template void launch_ionic<double>(int, const IonArgs<double>&, const LaunchCfg&, hipStream_t);
 
 }  // namespace mono

@@ -52,6 +52,15 @@ bool build_stencil(const HostCSR& K, const std::vector<int64_t>& inst_off, int64
 // ---------------------------------------------------------------------------
 // kernel argument blocks
 // ---------------------------------------------------------------------------
+// Launch shapes chosen per simulation (by the autotuner or the caller).
+struct LaunchCfg {
+  int diff_block = 256;   // 128, 256 or 512 lanes per workgroup
+  int diff_rpl = 1;       // stencil rows per lane: 1, 2 or 4 (FP32 only)
+  int diff_xcd = 1;       // deal row ranges to XCDs
+  int react_block = 256;  // 128, 256 or 512
+  int graph_steps = 32;   // outer steps per captured HIP graph
+};
+
 struct StimTable {
   int n;
   double t_on[kMaxStim];
@@ -91,6 +100,7 @@ struct DiffArgs {
   StepClock clk;
   int half;
   int m;
+  int xcd;                   // remap workgroups to contiguous rows per XCD
 };
 
 struct KTraceArgs {
@@ -125,10 +135,10 @@ struct IonArgs {
 // launchers (kernels_*.hip)
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_diffusion(int layout, const DiffArgs<T>& a, hipStream_t s);
+void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s);
 
 template <typename T>
-void launch_ionic(int model, const IonArgs<T>& a, hipStream_t s);
+void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s);
 
 void launch_advance_clock(int64_t* base, int64_t by, hipStream_t s);
 

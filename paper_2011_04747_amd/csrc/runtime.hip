@@ -45,7 +45,6 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-constexpr int kGraphChunk = 32;   // outer steps per captured graph
 
 // published initial values of the TP06 code release (not pre-paced)
 const double kTP06Init[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0, 0.0, 0.75, 0.75,
@@ -113,6 +112,7 @@ struct mono_sim {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool g_valid = false;
+  LaunchCfg lc;
   // debug
   KTraceArgs kt{};
   int vclamp = 0, force_l = 0;
@@ -233,6 +233,7 @@ DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   a.clk.dt = s->dt;
   a.half = half;
   a.m = m;
+  a.xcd = s->lc.diff_xcd;
   return a;
 }
 
@@ -288,15 +289,15 @@ void enqueue_steps(mono_sim* s, int64_t count, std::vector<TimedPair>* ev) {
   for (int64_t g = 0; g < count; ++g) {
     for (int m = 0; m < L; ++m) {
       mark(0, true);
-      launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->stream);
+      launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->lc, s->stream);
       mark(0, false);
     }
     mark(1, true);
-    launch_ionic<T>(s->model, ion_args<T>(s, s->d_V[L & 1], g), s->stream);
+    launch_ionic<T>(s->model, ion_args<T>(s, s->d_V[L & 1], g), s->lc, s->stream);
     mark(1, false);
     for (int m = 0; m < L; ++m) {
       mark(0, true);
-      launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->stream);
+      launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
       mark(0, false);
     }
   }
@@ -343,7 +344,7 @@ mono_status ensure_graph(mono_sim* s) {
   if (s->g_valid) return MONO_OK;
   drop_graph(s);
   HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-  enqueue(s, kGraphChunk);
+  enqueue(s, s->lc.graph_steps);
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamEndCapture(s->stream, &g));
   s->graph = g;
@@ -722,12 +723,13 @@ mono_status mono_step(mono_sim* s, int64_t n_steps, double dt, uint32_t flags) {
     s->step += n_steps;
     return MONO_OK;
   }
-  if (!(flags & 1u) && left >= kGraphChunk) {
+  const int64_t chunk = s->lc.graph_steps;
+  if (!(flags & 1u) && left >= chunk) {
     st = ensure_graph(s);
     if (st != MONO_OK) return st;
-    while (left >= kGraphChunk) {
+    while (left >= chunk) {
       HIP_TRY(hipGraphLaunch(s->gexec, s->stream));
-      left -= kGraphChunk;
+      left -= chunk;
     }
   }
   if (left > 0) enqueue(s, left);
@@ -745,15 +747,16 @@ mono_status mono_apply_phase(mono_sim* s, int32_t phase, int64_t step, int32_t m
   HIP_TRY(hipMemcpyAsync(s->d_base, &step, 8, hipMemcpyHostToDevice, s->stream));
   if (phase == 1) {
     if (s->prec == MONO_F64)
-      launch_ionic<double>(s->model, ion_args<double>(s, s->d_V[0], 0), s->stream);
+      launch_ionic<double>(s->model, ion_args<double>(s, s->d_V[0], 0), s->lc, s->stream);
     else
-      launch_ionic<float>(s->model, ion_args<float>(s, s->d_V[0], 0), s->stream);
+      launch_ionic<float>(s->model, ion_args<float>(s, s->d_V[0], 0), s->lc, s->stream);
   } else {
     const int half = phase / 2;
     if (s->prec == MONO_F64)
-      launch_diffusion<double>(s->layout, diff_args<double>(s, 0, half, m, 0), s->stream);
+      launch_diffusion<double>(s->layout, diff_args<double>(s, 0, half, m, 0), s->lc,
+                               s->stream);
     else
-      launch_diffusion<float>(s->layout, diff_args<float>(s, 0, half, m, 0), s->stream);
+      launch_diffusion<float>(s->layout, diff_args<float>(s, 0, half, m, 0), s->lc, s->stream);
     HIP_TRY(hipMemcpyAsync(s->d_V[0], s->d_V[1], s->Np * s->es, hipMemcpyDeviceToDevice,
                            s->stream));
   }
@@ -894,6 +897,38 @@ mono_status mono_estimate_lambda(mono_sim* s, int32_t iters) {
     if (s->dt > 0.0 && !(s->dt_ad[q] < 2.0 / s->lambda[q]))
       return fail(MONO_ESTATE, "dt_ad violates the forward Euler bound 2/lambda_max");
   }
+  return MONO_OK;
+}
+
+mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
+  if (!s || !c) return fail(MONO_EINVAL, "NULL argument");
+  auto okb = [](int b) { return b == 128 || b == 256 || b == 512; };
+  const int maxr = s->prec == MONO_F32 ? 4 : 2;
+  if (!okb(c->diff_block) || !okb(c->react_block))
+    return fail(MONO_EINVAL, "block sizes must be 128, 256 or 512");
+  if (!(c->diff_rows_per_lane == 1 || c->diff_rows_per_lane == 2 ||
+        c->diff_rows_per_lane == 4) || c->diff_rows_per_lane > maxr)
+    return fail(MONO_EINVAL, "rows per lane must be 1, 2 or 4 (FP64: 1 or 2)");
+  if (c->diff_xcd_remap < 0 || c->diff_xcd_remap > 1) return fail(MONO_EINVAL, "bad remap flag");
+  if (c->graph_steps < 1 || c->graph_steps > 8192)
+    return fail(MONO_EINVAL, "graph_steps must be in 1..8192");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->lc.diff_block = c->diff_block;
+  s->lc.diff_rpl = c->diff_rows_per_lane;
+  s->lc.diff_xcd = c->diff_xcd_remap;
+  s->lc.react_block = c->react_block;
+  s->lc.graph_steps = c->graph_steps;
+  drop_graph(s);
+  return MONO_OK;
+}
+
+mono_status mono_get_launch(mono_sim* s, mono_launch* c) {
+  if (!s || !c) return fail(MONO_EINVAL, "NULL argument");
+  c->diff_block = s->lc.diff_block;
+  c->diff_rows_per_lane = s->lc.diff_rpl;
+  c->diff_xcd_remap = s->lc.diff_xcd;
+  c->react_block = s->lc.react_block;
+  c->graph_steps = s->lc.graph_steps;
   return MONO_OK;
 }
 

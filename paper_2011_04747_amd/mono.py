@@ -33,7 +33,7 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_get_state_device_async", "mono_set_state", "mono_set_time_level",
            "mono_prepare", "mono_get_info", "mono_estimate_lambda", "mono_set_stream",
            "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
-           "mono_model_flops")
+           "mono_model_flops", "mono_set_launch", "mono_get_launch")
 
 
 class MonoError(RuntimeError):
@@ -56,6 +56,12 @@ class Info(C.Structure):
                 ("step", C.c_int64), ("nnz", C.c_int64), ("l", C.c_int32), ("k_max", C.c_int32),
                 ("layout", C.c_int32), ("n_instances", C.c_int32), ("n_states", C.c_int32),
                 ("ell_width", C.c_int32)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("diff_block", C.c_int32), ("diff_rows_per_lane", C.c_int32),
+                ("diff_xcd_remap", C.c_int32), ("react_block", C.c_int32),
+                ("graph_steps", C.c_int32)]
 
 
 class KTrace(C.Structure):
@@ -94,6 +100,8 @@ def lib():
             "mono_apply_phase": [vp, i32, i64, i32],
             "mono_debug": [vp, i32, vp],
             "mono_model_flops": [i32, vp, vp, vp],
+            "mono_set_launch": [vp, C.POINTER(Launch)],
+            "mono_get_launch": [vp, C.POINTER(Launch)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -231,6 +239,17 @@ class Sim:
 
     def estimate_lambda(self, iters=100):
         _check(lib().mono_estimate_lambda(self.h, int(iters)))
+
+    def launch(self):
+        c = Launch()
+        _check(lib().mono_get_launch(self.h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in Launch._fields_}
+
+    def set_launch(self, **kw):
+        cur = self.launch()
+        cur.update(kw)
+        c = Launch(*(int(cur[k]) for k, _ in Launch._fields_))
+        _check(lib().mono_set_launch(self.h, C.byref(c)))
 
     def set_stream(self, stream):
         _check(lib().mono_set_stream(self.h, C.c_void_p(int(stream))))

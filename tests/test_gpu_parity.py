@@ -425,3 +425,50 @@ def test_determinism_two_runs_bitwise(torch):
         s.step(w.n_steps, w.dt)
         vs.append(s.get(mono.FIELD_V))
     assert (vs[0] == vs[1]).all()
+
+
+# ---------------------------------------------------------------------------
+# launch shapes and the autotuner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["slab", "batch", "cable"])
+def test_launch_shapes_do_not_change_results(torch, which):
+    if which == "slab":
+        w = W.slab_ischemic(shape=(29, 23, 13), t_end=12.0)
+    elif which == "batch":
+        w = W.batched_sheets(n_inst=6, side_lo=13, side_hi=37, t_end=12.0)
+    else:
+        w = W.cable_ms(n_nodes=777, length=7.76, t_end=12.0)
+    ref = None
+    for cfg in ({}, dict(diff_block=128, diff_rows_per_lane=4, diff_xcd_remap=0, react_block=512,
+                         graph_steps=8),
+                dict(diff_block=512, diff_rows_per_lane=2, diff_xcd_remap=1, react_block=128,
+                     graph_steps=120)):
+        s = mono.Sim.from_workload(w, "f32")
+        if cfg:
+            s.set_launch(**cfg)
+        s.step(w.n_steps, w.dt)
+        out = (s.get(mono.FIELD_V), s.state(min(4, s.info()["n_states"] - 1)),
+               s.get(mono.FIELD_LAT))
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(ref, out):
+                assert (a == b).all()
+
+
+def test_autotuner_leaves_state_unchanged(torch, tmp_path, monkeypatch):
+    from paper_2011_04747_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE_DIR", str(tmp_path))
+    w = W.slab_ischemic(shape=(41, 37, 15), t_end=10.0)
+    a = mono.Sim.from_workload(w, "f32")
+    b = mono.Sim.from_workload(w, "f32")
+    a.step(30, w.dt)
+    b.step(30, w.dt)
+    best = autotune.tune(b, w.dt, steps=2, graph_candidates=(8, 16))
+    assert b.launch() == best
+    assert b.info()["step"] == 30
+    a.step(40, w.dt)
+    b.step(40, w.dt)
+    assert (a.get(mono.FIELD_V) == b.get(mono.FIELD_V)).all()
+    again = autotune.tune(b, w.dt)          # cached
+    assert again == best
