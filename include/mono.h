@@ -224,6 +224,16 @@ const char *mono_last_error(void);
 mono_status mono_model_flops(int32_t model, const double *state, const double *params,
                              int64_t *out);
 
+/* Host evaluation, in FP64, of the reaction kernel's own model code: one
+ * substep of length h applied to state[] in place, and the reverse-mode
+ * product of that substep (lam: adjoint of the output in, of the input out;
+ * gp[n_params]: parameter adjoints added).  clamp != 0 holds V fixed.  For
+ * checking the adjoint against finite differences without a device. */
+mono_status mono_model_substep_host(int32_t model, double *state, const double *params,
+                                    double h, int32_t clamp);
+mono_status mono_model_vjp_host(int32_t model, const double *state, const double *params,
+                                double h, int32_t clamp, double *lam, double *gp);
+
 /* Apply one phase of outer step `step` to the current state (testing the
  * kernels one launch at a time).  phase 0: diffusion substep `m` of the first
  * half step; 1: the reaction step; 2: diffusion substep `m` of the second

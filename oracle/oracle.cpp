@@ -159,6 +159,79 @@ int element_matrices(int dim, int nen, const double* X /* nen*dim */, const doub
 }
 
 // ---------------------------------------------------------------------------
+// forward-mode derivatives: a value and its N partial derivatives
+// ---------------------------------------------------------------------------
+template <int N>
+struct DualN {
+  double v;
+  double d[N];
+  DualN() : v(0.0) {
+    for (int k = 0; k < N; ++k) d[k] = 0.0;
+  }
+  DualN(double x) : v(x) {
+    for (int k = 0; k < N; ++k) d[k] = 0.0;
+  }
+};
+template <int N> DualN<N> operator+(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v + b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N> DualN<N> operator-(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v - b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N> DualN<N> operator-(const DualN<N>& a) {
+  DualN<N> r(-a.v);
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N> DualN<N> operator*(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v * b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N> DualN<N> operator/(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v / b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+template <int N> DualN<N> operator+(const DualN<N>& a, double b) { return a + DualN<N>(b); }
+template <int N> DualN<N> operator+(double a, const DualN<N>& b) { return DualN<N>(a) + b; }
+template <int N> DualN<N> operator-(const DualN<N>& a, double b) { return a - DualN<N>(b); }
+template <int N> DualN<N> operator-(double a, const DualN<N>& b) { return DualN<N>(a) - b; }
+template <int N> DualN<N> operator*(const DualN<N>& a, double b) { return a * DualN<N>(b); }
+template <int N> DualN<N> operator*(double a, const DualN<N>& b) { return DualN<N>(a) * b; }
+template <int N> DualN<N> operator/(const DualN<N>& a, double b) { return a / DualN<N>(b); }
+template <int N> DualN<N> operator/(double a, const DualN<N>& b) { return DualN<N>(a) / b; }
+template <int N> bool operator<(const DualN<N>& a, const DualN<N>& b) { return a.v < b.v; }
+template <int N> bool operator<(const DualN<N>& a, double b) { return a.v < b; }
+template <int N> bool operator>=(const DualN<N>& a, double b) { return a.v >= b; }
+template <int N> bool operator==(const DualN<N>& a, double b) { return a.v == b; }
+template <int N> DualN<N> exp(const DualN<N>& a) {
+  DualN<N> r(std::exp(a.v));
+  for (int k = 0; k < N; ++k) r.d[k] = r.v * a.d[k];
+  return r;
+}
+template <int N> DualN<N> expm1(const DualN<N>& a) {
+  DualN<N> r(std::expm1(a.v));
+  const double e = std::exp(a.v);
+  for (int k = 0; k < N; ++k) r.d[k] = e * a.d[k];
+  return r;
+}
+template <int N> DualN<N> log(const DualN<N>& a) {
+  DualN<N> r(std::log(a.v));
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] / a.v;
+  return r;
+}
+template <int N> DualN<N> sqrt(const DualN<N>& a) {
+  DualN<N> r(std::sqrt(a.v));
+  for (int k = 0; k < N; ++k) r.d[k] = 0.5 * a.d[k] / r.v;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // cell models
 // ---------------------------------------------------------------------------
 enum { M_LINEAR = 0, M_MS = 1, M_TP06 = 2 };
@@ -169,17 +242,19 @@ int model_nparams(int m) { return m == M_LINEAR ? 2 : (m == M_MS ? 5 : 6); }
 // Rates of one cell.  For every state y the model reports either a forward
 // Euler slope (is_gate = 0: rate = dy/dt) or Rush-Larsen data (is_gate = 1:
 // inf = y_inf, tau = time constant).  State 0 is always V.
+template <typename Num>
 struct Rates {
-  double rate[19];
-  double inf[19];
-  double tau[19];
+  Num rate[19];
+  Num inf[19];
+  Num tau[19];
   int is_gate[19];
   // Ca buffering: slopes of the *total* concentrations of states 3,4,5
   int buffered;
 };
 
 // Linear test model: dV/dt = -g (V - E).   p = {g, E}
-void rates_linear(const double* y, const double* p, Rates& r) {
+template <typename Num>
+void rates_linear(const Num* y, const Num* p, Rates<Num>& r) {
   r.buffered = 0;
   r.is_gate[0] = 0;
   r.rate[0] = -p[0] * (y[0] - p[1]);
@@ -190,8 +265,10 @@ void rates_linear(const double* y, const double* p, Rates& r) {
 // p = {tau_in, tau_out, tau_open, tau_close, v_gate}.  The gate is written in
 // Rush-Larsen form: h_inf = 1 (tau_open) below v_gate, 0 (tau_close) at or
 // above it.
-void rates_ms(const double* y, const double* p, Rates& r) {
-  double v = y[0], h = y[1];
+template <typename Num>
+void rates_ms(const Num* y, const Num* p, Rates<Num>& r) {
+  using std::exp;
+  Num v = y[0], h = y[1];
   r.buffered = 0;
   r.is_gate[0] = 0;
   r.rate[0] = h * v * v * (1.0 - v) / p[0] - v / p[1];
@@ -237,58 +314,64 @@ const double INIT[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0,
 }  // namespace tp
 
 // Ionic currents of TP06 (pA/pF) at state y; also used by qualitative tests.
+template <typename Num>
 struct TPCurrents {
-  double INa, IK1, Ito, IKr, IKs, ICaL, INaCa, INaK, IpCa, IpK, IbNa, IbCa;
-  double Irel, Iup, Ileak, Ixfer;
-  double Iion;
+  Num INa, IK1, Ito, IKr, IKs, ICaL, INaCa, INaK, IpCa, IpK, IbNa, IbCa;
+  Num Irel, Iup, Ileak, Ixfer;
+  Num Iion;
 };
 
-void tp06_currents(const double* y, const double* p, TPCurrents& c) {
+template <typename Num>
+void tp06_currents(const Num* y, const Num* p, TPCurrents<Num>& c) {
+  using std::exp;
+  using std::expm1;
+  using std::log;
+  using std::sqrt;
   using namespace tp;
-  const double V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5],
+  const Num V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5],
                Rb = y[6];
-  const double m = y[7], h = y[8], j = y[9], xr1 = y[10], xr2 = y[11], xs = y[12];
-  const double r = y[13], s = y[14], d = y[15], f = y[16], f2 = y[17], fcass = y[18];
-  const double Ko = p[0];
-  const double RTF = R * T / F;
-  const double EK = RTF * std::log(Ko / Ki);
-  const double ENa = RTF * std::log(Nao / Nai);
-  const double ECa = 0.5 * RTF * std::log(Cao / Cai);
-  const double EKs = RTF * std::log((Ko + pKNa * Nao) / (Ki + pKNa * Nai));
+  const Num m = y[7], h = y[8], j = y[9], xr1 = y[10], xr2 = y[11], xs = y[12];
+  const Num r = y[13], s = y[14], d = y[15], f = y[16], f2 = y[17], fcass = y[18];
+  const Num Ko = p[0];
+  const Num RTF = R * T / F;
+  const Num EK = RTF * log(Ko / Ki);
+  const Num ENa = RTF * log(Nao / Nai);
+  const Num ECa = 0.5 * RTF * log(Cao / Cai);
+  const Num EKs = RTF * log((Ko + pKNa * Nao) / (Ki + pKNa * Nai));
 
   c.INa = p[1] * GNa * m * m * m * h * j * (V - ENa);
 
-  const double aK1 = 0.1 / (1.0 + std::exp(0.06 * (V - EK - 200.0)));
-  const double bK1 = (3.0 * std::exp(0.0002 * (V - EK + 100.0)) + std::exp(0.1 * (V - EK - 10.0))) /
-                     (1.0 + std::exp(-0.5 * (V - EK)));
-  const double xK1 = aK1 / (aK1 + bK1);
-  c.IK1 = p[5] * GK1 * std::sqrt(Ko / 5.4) * xK1 * (V - EK);
+  const Num aK1 = 0.1 / (1.0 + exp(0.06 * (V - EK - 200.0)));
+  const Num bK1 = (3.0 * exp(0.0002 * (V - EK + 100.0)) + exp(0.1 * (V - EK - 10.0))) /
+                     (1.0 + exp(-0.5 * (V - EK)));
+  const Num xK1 = aK1 / (aK1 + bK1);
+  c.IK1 = p[5] * GK1 * sqrt(Ko / 5.4) * xK1 * (V - EK);
 
   c.Ito = Gto * r * s * (V - EK);
-  c.IKr = p[3] * GKr * std::sqrt(Ko / 5.4) * xr1 * xr2 * (V - EK);
+  c.IKr = p[3] * GKr * sqrt(Ko / 5.4) * xr1 * xr2 * (V - EK);
   c.IKs = p[4] * GKs * xs * xs * (V - EKs);
 
   // L-type current; x/(e^x - 1) -> 1 at x = 0 (removable singularity at V=15)
-  const double x = 2.0 * (V - 15.0) * F / (R * T);
-  const double xe = (x == 0.0) ? 1.0 : x / std::expm1(x);
+  const Num x = 2.0 * (V - 15.0) * F / (R * T);
+  const Num xe = (x == 0.0) ? 1.0 : x / expm1(x);
   // 4 (V-15) F^2/(RT) (0.25 Cass e^x - Cao)/(e^x - 1) = 2 F (x/(e^x-1)) (0.25 Cass e^x - Cao)
-  c.ICaL = p[2] * GCaL * d * f * f2 * fcass * 2.0 * F * xe * (0.25 * Cass * std::exp(x) - Cao);
+  c.ICaL = p[2] * GCaL * d * f * f2 * fcass * 2.0 * F * xe * (0.25 * Cass * exp(x) - Cao);
 
-  const double eg = std::exp(gam * V * F / (R * T));
-  const double eg1 = std::exp((gam - 1.0) * V * F / (R * T));
+  const Num eg = exp(gam * V * F / (R * T));
+  const Num eg1 = exp((gam - 1.0) * V * F / (R * T));
   c.INaCa = kNaCa * (eg * Nai * Nai * Nai * Cao - eg1 * Nao * Nao * Nao * Cai * alf) /
             ((KmNai * KmNai * KmNai + Nao * Nao * Nao) * (KmCa + Cao) * (1.0 + ksat * eg1));
   c.INaK = PNaK * Ko * Nai /
            ((Ko + KmK) * (Nai + KmNa) *
-            (1.0 + 0.1245 * std::exp(-0.1 * V * F / (R * T)) + 0.0353 * std::exp(-V * F / (R * T))));
+            (1.0 + 0.1245 * exp(-0.1 * V * F / (R * T)) + 0.0353 * exp(-V * F / (R * T))));
   c.IpCa = GpCa * Cai / (KpCa + Cai);
-  c.IpK = GpK * (V - EK) / (1.0 + std::exp((25.0 - V) / 5.98));
+  c.IpK = GpK * (V - EK) / (1.0 + exp((25.0 - V) / 5.98));
   c.IbNa = GbNa * (V - ENa);
   c.IbCa = GbCa * (V - ECa);
 
-  const double kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
-  const double k1 = k1p / kcasr;
-  const double O = k1 * Cass * Cass * Rb / (k3 + k1 * Cass * Cass);
+  const Num kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
+  const Num k1 = k1p / kcasr;
+  const Num O = k1 * Cass * Cass * Rb / (k3 + k1 * Cass * Cass);
   c.Irel = Vrel * O * (CaSR - Cass);
   c.Iup = Vmaxup / (1.0 + Kup * Kup / (Cai * Cai));
   c.Ileak = Vleak * (CaSR - Cai);
@@ -298,11 +381,14 @@ void tp06_currents(const double* y, const double* p, TPCurrents& c) {
            c.IbNa + c.IbCa;
 }
 
-void rates_tp06(const double* y, const double* p, Rates& r) {
+template <typename Num>
+void rates_tp06(const Num* y, const Num* p, Rates<Num>& r) {
+  using std::exp;
+  using std::sqrt;
   using namespace tp;
-  TPCurrents c;
+  TPCurrents<Num> c;
   tp06_currents(y, p, c);
-  const double V = y[0], Cass = y[4], CaSR = y[5], Rb = y[6];
+  const Num V = y[0], Cass = y[4], CaSR = y[5], Rb = y[6];
 
   for (int i = 0; i < 7; ++i) r.is_gate[i] = 0;
   for (int i = 7; i < 19; ++i) r.is_gate[i] = 1;
@@ -316,86 +402,86 @@ void rates_tp06(const double* y, const double* p, Rates& r) {
               (Vsr / Vc) * (c.Ileak - c.Iup) + c.Ixfer;
   r.rate[4] = -c.ICaL * Cm / (2.0 * Vss * F) + (Vsr / Vss) * c.Irel - (Vc / Vss) * c.Ixfer;
   r.rate[5] = c.Iup - c.Ileak - c.Irel;
-  const double kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
-  const double k2 = k2p * kcasr;
+  const Num kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
+  const Num k2 = k2p * kcasr;
   r.rate[6] = -k2 * Cass * Rb + k4 * (1.0 - Rb);
 
   // m
   {
-    double e = 1.0 / (1.0 + std::exp((-56.86 - V) / 9.03));
+    Num e = 1.0 / (1.0 + exp((-56.86 - V) / 9.03));
     r.inf[7] = e * e;
-    double am = 1.0 / (1.0 + std::exp((-60.0 - V) / 5.0));
-    double bm = 0.1 / (1.0 + std::exp((V + 35.0) / 5.0)) + 0.10 / (1.0 + std::exp((V - 50.0) / 200.0));
+    Num am = 1.0 / (1.0 + exp((-60.0 - V) / 5.0));
+    Num bm = 0.1 / (1.0 + exp((V + 35.0) / 5.0)) + 0.10 / (1.0 + exp((V - 50.0) / 200.0));
     r.tau[7] = am * bm;
   }
   // h, j
   {
-    double e = 1.0 / (1.0 + std::exp((V + 71.55) / 7.43));
+    Num e = 1.0 / (1.0 + exp((V + 71.55) / 7.43));
     r.inf[8] = e * e;
     r.inf[9] = e * e;
-    double ah, bh, aj, bj;
+    Num ah, bh, aj, bj;
     if (V >= -40.0) {
       ah = 0.0;
-      bh = 0.77 / (0.13 * (1.0 + std::exp(-(V + 10.66) / 11.1)));
+      bh = 0.77 / (0.13 * (1.0 + exp(-(V + 10.66) / 11.1)));
       aj = 0.0;
-      bj = 0.6 * std::exp(0.057 * V) / (1.0 + std::exp(-0.1 * (V + 32.0)));
+      bj = 0.6 * exp(0.057 * V) / (1.0 + exp(-0.1 * (V + 32.0)));
     } else {
-      ah = 0.057 * std::exp(-(V + 80.0) / 6.8);
-      bh = 2.7 * std::exp(0.079 * V) + 3.1e5 * std::exp(0.3485 * V);
-      aj = (-2.5428e4 * std::exp(0.2444 * V) - 6.948e-6 * std::exp(-0.04391 * V)) * (V + 37.78) /
-           (1.0 + std::exp(0.311 * (V + 79.23)));
-      bj = 0.02424 * std::exp(-0.01052 * V) / (1.0 + std::exp(-0.1378 * (V + 40.14)));
+      ah = 0.057 * exp(-(V + 80.0) / 6.8);
+      bh = 2.7 * exp(0.079 * V) + 3.1e5 * exp(0.3485 * V);
+      aj = (-2.5428e4 * exp(0.2444 * V) - 6.948e-6 * exp(-0.04391 * V)) * (V + 37.78) /
+           (1.0 + exp(0.311 * (V + 79.23)));
+      bj = 0.02424 * exp(-0.01052 * V) / (1.0 + exp(-0.1378 * (V + 40.14)));
     }
     r.tau[8] = 1.0 / (ah + bh);
     r.tau[9] = 1.0 / (aj + bj);
   }
   // xr1, xr2
   {
-    r.inf[10] = 1.0 / (1.0 + std::exp((-26.0 - V) / 7.0));
-    double a = 450.0 / (1.0 + std::exp((-45.0 - V) / 10.0));
-    double b = 6.0 / (1.0 + std::exp((V + 30.0) / 11.5));
+    r.inf[10] = 1.0 / (1.0 + exp((-26.0 - V) / 7.0));
+    Num a = 450.0 / (1.0 + exp((-45.0 - V) / 10.0));
+    Num b = 6.0 / (1.0 + exp((V + 30.0) / 11.5));
     r.tau[10] = a * b;
-    r.inf[11] = 1.0 / (1.0 + std::exp((V + 88.0) / 24.0));
-    a = 3.0 / (1.0 + std::exp((-60.0 - V) / 20.0));
-    b = 1.12 / (1.0 + std::exp((V - 60.0) / 20.0));
+    r.inf[11] = 1.0 / (1.0 + exp((V + 88.0) / 24.0));
+    a = 3.0 / (1.0 + exp((-60.0 - V) / 20.0));
+    b = 1.12 / (1.0 + exp((V - 60.0) / 20.0));
     r.tau[11] = a * b;
   }
   // xs
   {
-    r.inf[12] = 1.0 / (1.0 + std::exp((-5.0 - V) / 14.0));
-    double a = 1400.0 / std::sqrt(1.0 + std::exp((5.0 - V) / 6.0));
-    double b = 1.0 / (1.0 + std::exp((V - 35.0) / 15.0));
+    r.inf[12] = 1.0 / (1.0 + exp((-5.0 - V) / 14.0));
+    Num a = 1400.0 / sqrt(1.0 + exp((5.0 - V) / 6.0));
+    Num b = 1.0 / (1.0 + exp((V - 35.0) / 15.0));
     r.tau[12] = a * b + 80.0;
   }
   // r, s (epicardial)
   {
-    r.inf[13] = 1.0 / (1.0 + std::exp((20.0 - V) / 6.0));
-    r.tau[13] = 9.5 * std::exp(-(V + 40.0) * (V + 40.0) / 1800.0) + 0.8;
-    r.inf[14] = 1.0 / (1.0 + std::exp((V + 20.0) / 5.0));
-    r.tau[14] = 85.0 * std::exp(-(V + 45.0) * (V + 45.0) / 320.0) +
-                5.0 / (1.0 + std::exp((V - 20.0) / 5.0)) + 3.0;
+    r.inf[13] = 1.0 / (1.0 + exp((20.0 - V) / 6.0));
+    r.tau[13] = 9.5 * exp(-(V + 40.0) * (V + 40.0) / 1800.0) + 0.8;
+    r.inf[14] = 1.0 / (1.0 + exp((V + 20.0) / 5.0));
+    r.tau[14] = 85.0 * exp(-(V + 45.0) * (V + 45.0) / 320.0) +
+                5.0 / (1.0 + exp((V - 20.0) / 5.0)) + 3.0;
   }
   // d, f, f2, fCass
   {
-    r.inf[15] = 1.0 / (1.0 + std::exp((-8.0 - V) / 7.5));
-    double a = 1.4 / (1.0 + std::exp((-35.0 - V) / 13.0)) + 0.25;
-    double b = 1.4 / (1.0 + std::exp((V + 5.0) / 5.0));
-    double g = 1.0 / (1.0 + std::exp((50.0 - V) / 20.0));
+    r.inf[15] = 1.0 / (1.0 + exp((-8.0 - V) / 7.5));
+    Num a = 1.4 / (1.0 + exp((-35.0 - V) / 13.0)) + 0.25;
+    Num b = 1.4 / (1.0 + exp((V + 5.0) / 5.0));
+    Num g = 1.0 / (1.0 + exp((50.0 - V) / 20.0));
     r.tau[15] = a * b + g;
 
-    r.inf[16] = 1.0 / (1.0 + std::exp((V + 20.0) / 7.0));
-    a = 1102.5 * std::exp(-(V + 27.0) * (V + 27.0) / 225.0);
-    b = 200.0 / (1.0 + std::exp((13.0 - V) / 10.0));
-    g = 180.0 / (1.0 + std::exp((V + 30.0) / 10.0)) + 20.0;
+    r.inf[16] = 1.0 / (1.0 + exp((V + 20.0) / 7.0));
+    a = 1102.5 * exp(-(V + 27.0) * (V + 27.0) / 225.0);
+    b = 200.0 / (1.0 + exp((13.0 - V) / 10.0));
+    g = 180.0 / (1.0 + exp((V + 30.0) / 10.0)) + 20.0;
     r.tau[16] = a + b + g;
 
-    r.inf[17] = 0.67 / (1.0 + std::exp((V + 35.0) / 7.0)) + 0.33;
-    a = 600.0 * std::exp(-(V + 25.0) * (V + 25.0) / 170.0);
-    b = 31.0 / (1.0 + std::exp((25.0 - V) / 10.0));
-    g = 16.0 / (1.0 + std::exp((V + 30.0) / 10.0));
+    r.inf[17] = 0.67 / (1.0 + exp((V + 35.0) / 7.0)) + 0.33;
+    a = 600.0 * exp(-(V + 25.0) * (V + 25.0) / 170.0);
+    b = 31.0 / (1.0 + exp((25.0 - V) / 10.0));
+    g = 16.0 / (1.0 + exp((V + 30.0) / 10.0));
     r.tau[17] = a + b + g;
 
-    double q = (Cass / 0.05) * (Cass / 0.05);
+    Num q = (Cass / 0.05) * (Cass / 0.05);
     r.inf[18] = 0.6 / (1.0 + q) + 0.4;
     r.tau[18] = 80.0 / (1.0 + q) + 2.0;
   }
@@ -403,13 +489,17 @@ void rates_tp06(const double* y, const double* p, Rates& r) {
 
 // Free concentration c >= 0 whose total c + B c/(c + K) equals `total`:
 // the positive root of c^2 + (B + K - total) c - K total = 0.
-double free_from_total(double total, double B, double K) {
-  double b = B + K - total;
-  return 0.5 * (-b + std::sqrt(b * b + 4.0 * K * total));
+template <typename Num>
+Num free_from_total(Num total, double B, double K) {
+  using std::sqrt;
+  Num b = B + K - total;
+  return 0.5 * (-b + sqrt(b * b + 4.0 * K * total));
 }
-double total_from_free(double c, double B, double K) { return c + B * c / (c + K); }
+template <typename Num>
+Num total_from_free(Num c, double B, double K) { return c + B * c / (c + K); }
 
-void model_rates(int model, const double* y, const double* p, Rates& r) {
+template <typename Num>
+void model_rates(int model, const Num* y, const Num* p, Rates<Num>& r) {
   if (model == M_LINEAR)
     rates_linear(y, p, r);
   else if (model == M_MS)
@@ -421,14 +511,16 @@ void model_rates(int model, const double* y, const double* p, Rates& r) {
 // One substep of length h from y (all rates taken at the substep start):
 // Rush-Larsen for gates, forward Euler for the rest (TP06 calcium through its
 // buffered totals).  If vclamp, V is held.
-void cell_substep(int model, double* y, const double* p, double h, int vclamp) {
-  Rates r;
+template <typename Num>
+void cell_substep(int model, Num* y, const Num* p, double h, int vclamp) {
+  using std::exp;
+  Rates<Num> r;
   model_rates(model, y, p, r);
   const int S = model_nstates(model);
-  double yn[19];
+  Num yn[19];
   for (int i = 0; i < S; ++i) {
     if (r.is_gate[i]) {
-      yn[i] = r.inf[i] + (y[i] - r.inf[i]) * std::exp(-h / r.tau[i]);
+      yn[i] = r.inf[i] + (y[i] - r.inf[i]) * exp(-h / r.tau[i]);
     } else if (r.buffered && i == 3) {
       yn[i] = free_from_total(total_from_free(y[i], tp::Bufc, tp::Kbufc) + h * r.rate[i], tp::Bufc,
                               tp::Kbufc);
@@ -518,6 +610,16 @@ struct Sim {
   double* sensor_buf = nullptr;
   int64_t sensor_steps = 0;
   std::vector<double> vtmp;
+  // adjoint: unscaled stiffness, loss target and the taped forward run
+  std::vector<double> val0;        // K before the per-node conductivity scaling
+  std::vector<int32_t> tsens;      // loss sensors
+  std::vector<double> target;      // n_steps x sensors
+  int64_t target_steps = 0;
+  bool taped = false;
+  int64_t tape_step0 = 0, tape_steps = 0;
+  std::vector<double> tape_vsub;   // per step: 2*lmax substep inputs of n values
+  std::vector<double> tape_entry;  // per step: S*n reaction-entry states
+  std::vector<uint8_t> tape_k;     // per step: n
 };
 
 int prepare(Sim* s, double dt) {
@@ -582,12 +684,13 @@ double diffusion_row(const Sim* s, const double* V, int64_t i, int m, double t0,
 // One diffusion half step B(dt/2) at time t0: l forward Euler substeps of
 // V <- V + dt_ad (-M^-1 K V + s(tau)), tau = t0 + m dt_ad (Jacobi: every row
 // reads the V of the previous substep).
-void diffusion_half(Sim* s, double t0) {
+void diffusion_half(Sim* s, double t0, double* store = nullptr) {
   const int64_t n = s->n;
   double* V = s->state.data();
   int lmax = 0;
   for (int x : s->l) lmax = std::max(lmax, x);
   for (int m = 0; m < lmax; ++m) {
+    if (store) std::memcpy(store + (int64_t)m * n, V, sizeof(double) * n);
     // stimulus rate per node at this substep
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) s->stim_rate[i] = 0.0;
@@ -617,7 +720,7 @@ int react_node(const Sim* s, int64_t nstep, int64_t i, double* y, const double* 
   if (s->dvdt_src == 0) {
     d = (nstep == 0) ? 0.0 : (Vb - vprev) / dt;
   } else {
-    Rates r;
+    Rates<double> r;
     model_rates(s->model, y, p, r);
     d = r.rate[0];
   }
@@ -659,6 +762,80 @@ void reaction(Sim* s, int64_t nstep) {
     s->lastk[i] = react_node(s, nstep, i, y, p, s->vprev[i], s->lat[i]);
     for (int a = 0; a < S; ++a) s->state[a * n + i] = y[a];
   }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the split step (gradient of a sensor-mismatch loss)
+// ---------------------------------------------------------------------------
+// Jacobian of one substep at (y, p): J[i][j] = d y'_i / d (y_j for j < S,
+// p_{j-S} for j >= S), by forward-mode derivatives through the model code.
+constexpr int kJac = 25;   // 19 states + 6 parameters (TP06), the largest model
+void substep_jacobian(int model, const double* y, const double* p, double h, int S, int P,
+                      double* J) {
+  DualN<kJac> yd[19], pd[8];
+  for (int a = 0; a < S; ++a) {
+    yd[a] = DualN<kJac>(y[a]);
+    yd[a].d[a] = 1.0;
+  }
+  for (int b = 0; b < P; ++b) {
+    pd[b] = DualN<kJac>(p[b]);
+    pd[b].d[S + b] = 1.0;
+  }
+  cell_substep(model, yd, pd, h, 0);
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S + P; ++j) J[i * (S + P) + j] = yd[i].d[j];
+}
+
+// One taped outer step: stores the inputs of every diffusion substep and the
+// reaction-entry state, and adds the loss at reaction entry.
+double taped_step(Sim* s, int64_t t) {
+  const int64_t n = s->n, nstep = s->step;
+  int lmax = 0;
+  for (int x : s->l) lmax = std::max(lmax, x);
+  double* vs = s->tape_vsub.data() + t * 2 * lmax * n;
+  const double tn = nstep * s->dt;
+  diffusion_half(s, tn, vs);
+  std::memcpy(s->tape_entry.data() + t * s->S * n, s->state.data(), sizeof(double) * s->S * n);
+  double loss = 0.0;
+  const int64_t ns = (int64_t)s->tsens.size();
+  if (nstep < s->target_steps)
+    for (int64_t q = 0; q < ns; ++q) {
+      const double e = s->state[s->tsens[q]] - s->target[nstep * ns + q];
+      loss += e * e;
+    }
+  reaction(s, nstep);
+  for (int64_t i = 0; i < n; ++i) s->tape_k[t * n + i] = (uint8_t)s->lastk[i];
+  diffusion_half(s, tn + 0.5 * s->dt, vs + (int64_t)lmax * n);
+  s->step = nstep + 1;
+  return loss;
+}
+
+// Reverse of diffusion substep m (input potential Vin): lam_V <- (I - dt_ad K
+// M^-1) lam_V, and the conductivity gradient of lam^T V' through K(sigma).
+void adjoint_diffusion(Sim* s, int m, const double* Vin, double* lamV, double* gsig) {
+  const int64_t n = s->n;
+  std::vector<double> u(n), out(n);
+  for (int64_t i = 0; i < n; ++i) u[i] = lamV[i] / s->mass[i];
+  for (int64_t i = 0; i < n; ++i) {
+    const int q = s->inst_of[i];
+    if (m >= s->l[q]) {
+      out[i] = lamV[i];
+      continue;
+    }
+    double ku = 0.0;
+    for (int64_t p = s->rowptr[i]; p < s->rowptr[i + 1]; ++p) ku += s->val[p] * u[s->col[p]];
+    out[i] = lamV[i] - s->dt_ad[q] * ku;
+    // d/dsigma of -dt_ad u^T K V, with K_ij = k0_ij (sigma_i + sigma_j)/2 off
+    // the diagonal and K_ii = -sum_j K_ij
+    for (int64_t p = s->rowptr[i]; p < s->rowptr[i + 1]; ++p) {
+      const int32_t j = s->col[p];
+      if (j == i) continue;
+      const double c = -s->dt_ad[q] * u[i] * 0.5 * s->val0[p] * (Vin[j] - Vin[i]);
+      gsig[i] += c;
+      gsig[j] += c;
+    }
+  }
+  std::memcpy(lamV, out.data(), sizeof(double) * n);
 }
 
 }  // namespace
@@ -728,6 +905,7 @@ void* orc_create(int dim, int64_t n_nodes, const double* xyz, int etype, int64_t
   }
   s->col.resize(s->rowptr[n_nodes]);
   s->val.resize(s->rowptr[n_nodes]);
+  s->val0.resize(s->rowptr[n_nodes]);
   for (int64_t i = 0; i < n_nodes; ++i) {
     int64_t p = s->rowptr[i];
     double offsum = 0.0;
@@ -735,6 +913,7 @@ void* orc_create(int dim, int64_t n_nodes, const double* xyz, int etype, int64_t
     for (auto& pr : rows[i]) {
       s->col[p] = pr.first;
       double v = pr.second;
+      s->val0[p] = v;
       if (pr.first == i) {
         pdiag = p;
       } else if (sigma) {
@@ -931,6 +1110,104 @@ int orc_set_vclamp(void* h, int on) {
   return 0;
 }
 
+// --- adjoint ------------------------------------------------------------------
+// Loss = sum over steps n and sensors q of (V_q at reaction entry of step n -
+// target[n][q])^2.
+int orc_set_target(void* h, int32_t n, const int32_t* nodes, const double* target,
+                   int64_t n_steps) {
+  Sim* s = (Sim*)h;
+  for (int32_t q = 0; q < n; ++q)
+    if (nodes[q] < 0 || nodes[q] >= s->n) return fail("sensor out of range");
+  s->tsens.assign(nodes, nodes + n);
+  s->target.assign(target, target + (int64_t)n * n_steps);
+  s->target_steps = n_steps;
+  return 0;
+}
+
+int orc_forward_taped(void* h, int64_t n_steps, double dt, double* loss) {
+  Sim* s = (Sim*)h;
+  if (s->model < 0) return fail("no cell model");
+  if (s->dt != dt && prepare(s, dt) != 0) return -1;
+  int lmax = 0;
+  for (int x : s->l) lmax = std::max(lmax, x);
+  const int64_t n = s->n;
+  s->tape_step0 = s->step;
+  s->tape_steps = n_steps;
+  s->tape_vsub.assign((size_t)n_steps * 2 * lmax * n, 0.0);
+  s->tape_entry.assign((size_t)n_steps * s->S * n, 0.0);
+  s->tape_k.assign((size_t)n_steps * n, 0);
+  double L = 0.0;
+  for (int64_t t = 0; t < n_steps; ++t) L += taped_step(s, t);
+  s->taped = true;
+  *loss = L;
+  return 0;
+}
+
+// grad_sigma[n]: dL/dsigma_i.  grad_params[P]: derivative with respect to a
+// common multiplier of each parameter row at 1, sum_i p_i[a] dL/dp_i[a].
+int orc_backward(void* h, double* grad_sigma, double* grad_params) {
+  Sim* s = (Sim*)h;
+  if (!s->taped) return fail("no taped forward run");
+  const int64_t n = s->n;
+  const int S = s->S, P = s->P;
+  int lmax = 0;
+  for (int x : s->l) lmax = std::max(lmax, x);
+  std::vector<double> lam((size_t)S * n, 0.0), gp((size_t)P * n, 0.0);
+  for (int64_t i = 0; i < n; ++i) grad_sigma[i] = 0.0;
+  const int64_t ns = (int64_t)s->tsens.size();
+  for (int64_t t = s->tape_steps - 1; t >= 0; --t) {
+    const int64_t nstep = s->tape_step0 + t;
+    const double* vs = s->tape_vsub.data() + t * 2 * lmax * n;
+    for (int m = lmax - 1; m >= 0; --m)
+      adjoint_diffusion(s, m, vs + (int64_t)(lmax + m) * n, lam.data(), grad_sigma);
+    // reaction: replay the k substeps from the entry state, then reverse them
+    const double* entry = s->tape_entry.data() + t * S * n;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      const int k = s->tape_k[t * n + i];
+      const double hsub = s->dt / k;
+      double p[8], J[19 * 25], li[19];
+      std::vector<double> ys((size_t)k * S);   // substep start states
+      for (int b = 0; b < P; ++b) p[b] = s->params[(int64_t)b * n + i];
+      for (int a = 0; a < S; ++a) ys[a] = entry[(int64_t)a * n + i];
+      for (int q = 1; q < k; ++q) {
+        for (int a = 0; a < S; ++a) ys[(size_t)q * S + a] = ys[(size_t)(q - 1) * S + a];
+        cell_substep(s->model, &ys[(size_t)q * S], p, hsub, 0);
+      }
+      for (int a = 0; a < S; ++a) li[a] = lam[(int64_t)a * n + i];
+      for (int q = k - 1; q >= 0; --q) {
+        substep_jacobian(s->model, &ys[(size_t)q * S], p, hsub, S, P, J);
+        double lo[19];
+        for (int j = 0; j < S; ++j) {
+          double acc = 0.0;
+          for (int a = 0; a < S; ++a) acc += J[a * (S + P) + j] * li[a];
+          lo[j] = acc;
+        }
+        for (int b = 0; b < P; ++b) {
+          double acc = 0.0;
+          for (int a = 0; a < S; ++a) acc += J[a * (S + P) + S + b] * li[a];
+          gp[(int64_t)b * n + i] += acc;
+        }
+        for (int a = 0; a < S; ++a) li[a] = lo[a];
+      }
+      for (int a = 0; a < S; ++a) lam[(int64_t)a * n + i] = li[a];
+    }
+    // loss at reaction entry of this step
+    if (nstep < s->target_steps)
+      for (int64_t q = 0; q < ns; ++q) {
+        const int32_t i = s->tsens[q];
+        lam[i] += 2.0 * (entry[i] - s->target[nstep * ns + q]);
+      }
+    for (int m = lmax - 1; m >= 0; --m) adjoint_diffusion(s, m, vs + (int64_t)m * n, lam.data(), grad_sigma);
+  }
+  for (int b = 0; b < P; ++b) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += s->params[(int64_t)b * n + i] * gp[(int64_t)b * n + i];
+    grad_params[b] = acc;
+  }
+  return 0;
+}
+
 // --- sampled evaluation (rows of one full-size launch) -----------------------
 // Substep m of the half step that starts at t0, applied to V_in (all n
 // values), evaluated only on `rows`.
@@ -987,7 +1264,7 @@ int orc_cell_advance(int model, const double* p, double* y, int k, double dt, in
 // Rates at a state: out_rate[S], out_inf[S], out_tau[S], out_gate[S]
 int orc_cell_rates(int model, const double* p, const double* y, double* rate, double* inf,
                    double* tau, int32_t* gate) {
-  Rates r;
+  Rates<double> r;
   model_rates(model, y, p, r);
   const int S = model_nstates(model);
   for (int a = 0; a < S; ++a) {
@@ -1001,7 +1278,7 @@ int orc_cell_rates(int model, const double* p, const double* y, double* rate, do
 
 // TP06 currents: INa IK1 Ito IKr IKs ICaL INaCa INaK IpCa IpK IbNa IbCa Irel Iup Ileak Ixfer Iion
 int orc_tp06_currents(const double* p, const double* y, double* out) {
-  TPCurrents c;
+  TPCurrents<double> c;
   tp06_currents(y, p, c);
   const double v[17] = {c.INa,  c.IK1,  c.Ito,  c.IKr,  c.IKs, c.ICaL, c.INaCa, c.INaK, c.IpCa,
                         c.IpK,  c.IbNa, c.IbCa, c.Irel, c.Iup, c.Ileak, c.Ixfer, c.Iion};

@@ -64,6 +64,9 @@ def lib():
         L.orc_tp06_currents.argtypes = [_dp, _dp, _dp]
         L.orc_diffusion_rows.argtypes = [vp, _dp, C.c_double, C.c_int, C.c_int64, _lp, _dp]
         L.orc_reaction_nodes.argtypes = [vp, C.c_int64, C.c_int64, _lp, _dp, _dp, _dp, _ip]
+        L.orc_set_target.argtypes = [vp, C.c_int32, _ip, _dp, C.c_int64]
+        L.orc_forward_taped.argtypes = [vp, C.c_int64, C.c_double, _dp]
+        L.orc_backward.argtypes = [vp, _dp, _dp]
         L.orc_k_rule.argtypes = [C.c_double, C.c_int]
         L.orc_l_rule.argtypes = [C.c_double, C.c_double, C.c_int]
         _lib = L
@@ -230,6 +233,26 @@ class Oracle:
         k = np.zeros(len(rows), np.int32)
         _check(lib().orc_reaction_nodes(self.h, int(nstep), len(rows), rows, y, vp, la, k))
         return y, vp, la, k
+
+    # -- adjoint ----------------------------------------------------------------
+    def set_target(self, nodes, target):
+        """Loss sensors and targets (n_steps x len(nodes)), sampled at reaction entry."""
+        nodes = _i32(nodes)
+        t = _f64(target)
+        self._target = (nodes, t)
+        _check(lib().orc_set_target(self.h, len(nodes), nodes, t.reshape(-1), t.shape[0]))
+
+    def forward_taped(self, n_steps, dt):
+        out = np.zeros(1)
+        _check(lib().orc_forward_taped(self.h, int(n_steps), float(dt), out))
+        return float(out[0])
+
+    def backward(self):
+        """(dL/dsigma per node, dL/d(common multiplier of each parameter row))."""
+        gs = np.zeros(self.n)
+        gp = np.zeros(self.P)
+        _check(lib().orc_backward(self.h, gs, gp))
+        return gs, gp
 
     def record_sensors(self, nodes, n_steps):
         nodes = _i32(nodes)

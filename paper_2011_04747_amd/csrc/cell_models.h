@@ -203,6 +203,83 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   c.Ixfer = T(kVxfer) * (Cass - Cai);
 }
 
+// Steady states and rates (1/tau) of the eleven V-driven TP06 gates, in the
+// state order m, h, j, xr1, xr2, xs, r, s, d, f, f2.
+template <typename T>
+__host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) {
+  {
+    const T e = sig((T(-56.86) - V) * T(1.0 / 9.03));
+    const T am = sig((T(-60) - V) * T(0.2));
+    const T bm = T(0.1) * sig((V + T(35)) * T(0.2)) + T(0.1) * sig((V - T(50)) * T(0.005));
+    inf[0] = e * e;
+    rate[0] = xrcp(am * bm);
+  }
+  {
+    const T e = sig((V + T(71.55)) * T(1.0 / 7.43));
+    inf[1] = e * e;
+    inf[2] = e * e;
+    if (V >= T(-40)) {
+      rate[1] = T(0.77 / 0.13) * sig(-(V + T(10.66)) * T(1.0 / 11.1));
+      rate[2] = T(0.6) * xexp(T(0.057) * V) * sig(T(-0.1) * (V + T(32)));
+    } else {
+      rate[1] = T(0.057) * xexp(-(V + T(80)) * T(1.0 / 6.8)) + T(2.7) * xexp(T(0.079) * V) +
+                T(3.1e5) * xexp(T(0.3485) * V);
+      rate[2] = (T(-2.5428e4) * xexp(T(0.2444) * V) - T(6.948e-6) * xexp(T(-0.04391) * V)) *
+                    (V + T(37.78)) * sig(T(0.311) * (V + T(79.23))) +
+                T(0.02424) * xexp(T(-0.01052) * V) * sig(T(-0.1378) * (V + T(40.14)));
+    }
+  }
+  const T s30 = sig((V + T(30)) * T(0.1));    // shared by f and f2
+  {
+    const T a1 = T(450) * sig((T(-45) - V) * T(0.1));
+    const T b1 = T(6) * sig((V + T(30)) * T(1.0 / 11.5));
+    inf[3] = sig((T(-26) - V) * T(1.0 / 7.0));
+    rate[3] = xrcp(a1 * b1);
+    const T a2 = T(3) * sig((T(-60) - V) * T(0.05));
+    const T b2 = T(1.12) * sig((V - T(60)) * T(0.05));
+    inf[4] = sig((V + T(88)) * T(1.0 / 24.0));
+    rate[4] = xrcp(a2 * b2);
+  }
+  {
+    const T a = T(1400) * xrcp(xsqrt(T(1) + xexp((T(5) - V) * T(1.0 / 6.0))));
+    const T b = sig((V - T(35)) * T(1.0 / 15.0));
+    inf[5] = sig((T(-5) - V) * T(1.0 / 14.0));
+    rate[5] = xrcp(a * b + T(80));
+  }
+  {
+    const T vr = V + T(40), vs = V + T(45);
+    inf[6] = sig((T(20) - V) * T(1.0 / 6.0));
+    rate[6] = xrcp(T(9.5) * xexp(-vr * vr * T(1.0 / 1800.0)) + T(0.8));
+    inf[7] = sig((V + T(20)) * T(0.2));
+    rate[7] = xrcp(T(85) * xexp(-vs * vs * T(1.0 / 320.0)) + T(5) * sig((V - T(20)) * T(0.2)) +
+                   T(3));
+  }
+  {
+    const T ad = T(1.4) * sig((T(-35) - V) * T(1.0 / 13.0)) + T(0.25);
+    const T bd = T(1.4) * sig((V + T(5)) * T(0.2));
+    const T gd = sig((T(50) - V) * T(0.05));
+    inf[8] = sig((T(-8) - V) * T(1.0 / 7.5));
+    rate[8] = xrcp(ad * bd + gd);
+    const T vf = V + T(27);
+    inf[9] = sig((V + T(20)) * T(1.0 / 7.0));
+    rate[9] = xrcp(T(1102.5) * xexp(-vf * vf * T(1.0 / 225.0)) +
+                   T(200) * sig((T(13) - V) * T(0.1)) + T(180) * s30 + T(20));
+    const T vf2 = V + T(25);
+    inf[10] = T(0.67) * sig((V + T(35)) * T(1.0 / 7.0)) + T(0.33);
+    rate[10] = xrcp(T(600) * xexp(-vf2 * vf2 * T(1.0 / 170.0)) +
+                    T(31) * sig((T(25) - V) * T(0.1)) + T(16) * s30);
+  }
+}
+
+// fCass gate: steady state and rate from the subspace calcium
+template <typename T>
+__host__ __device__ __forceinline__ void tp06_fcass_params(T Cass, T& inf, T& rate) {
+  const T q = (Cass * T(20)) * (Cass * T(20));
+  const T r1q = xrcp(T(1) + q);
+  inf = T(0.6) * r1q + T(0.4);
+  rate = xrcp(T(80) * r1q + T(2));
+}
+
 struct TP06Model {
   static constexpr int S = 19, P = 6;
   template <typename T>
@@ -230,72 +307,12 @@ struct TP06Model {
     const T kcasr = T(kMaxSR) - T(kMaxSR - kMinSR) * xrcp(T(1) + r_sr * r_sr);
     const T dRb = -T(kK2p) * kcasr * y[4] * y[6] + T(kK4) * (T(1) - y[6]);
 
-    // gates from the substep-start V (and Ca_ss for fCass); rates 1/tau are
-    // formed directly where tau = 1/(alpha + beta)
+    // gates from the substep-start V (and Ca_ss for fCass)
+    T inf[12], rate[12];
+    tp06_gate_params(V, inf, rate);
+    tp06_fcass_params(y[4], inf[11], rate[11]);
     T g[12];
-    {
-      const T e = sig((T(-56.86) - V) * T(1.0 / 9.03));
-      const T am = sig((T(-60) - V) * T(0.2));
-      const T bm = T(0.1) * sig((V + T(35)) * T(0.2)) + T(0.1) * sig((V - T(50)) * T(0.005));
-      g[0] = rush_larsen(y[7], e * e, am * bm, h);
-    }
-    {
-      const T e = sig((V + T(71.55)) * T(1.0 / 7.43));
-      const T inf = e * e;
-      T rh, rj;
-      if (V >= T(-40)) {
-        rh = T(0.77 / 0.13) * sig(-(V + T(10.66)) * T(1.0 / 11.1));
-        rj = T(0.6) * xexp(T(0.057) * V) * sig(T(-0.1) * (V + T(32)));
-      } else {
-        rh = T(0.057) * xexp(-(V + T(80)) * T(1.0 / 6.8)) + T(2.7) * xexp(T(0.079) * V) +
-             T(3.1e5) * xexp(T(0.3485) * V);
-        rj = (T(-2.5428e4) * xexp(T(0.2444) * V) - T(6.948e-6) * xexp(T(-0.04391) * V)) *
-                 (V + T(37.78)) * sig(T(0.311) * (V + T(79.23))) +
-             T(0.02424) * xexp(T(-0.01052) * V) * sig(T(-0.1378) * (V + T(40.14)));
-      }
-      g[1] = rl_rate(y[8], inf, rh, h);
-      g[2] = rl_rate(y[9], inf, rj, h);
-    }
-    const T s30 = sig((V + T(30)) * T(0.1));    // shared by f and f2
-    {
-      const T a1 = T(450) * sig((T(-45) - V) * T(0.1));
-      const T b1 = T(6) * sig((V + T(30)) * T(1.0 / 11.5));
-      g[3] = rush_larsen(y[10], sig((T(-26) - V) * T(1.0 / 7.0)), a1 * b1, h);
-      const T a2 = T(3) * sig((T(-60) - V) * T(0.05));
-      const T b2 = T(1.12) * sig((V - T(60)) * T(0.05));
-      g[4] = rush_larsen(y[11], sig((V + T(88)) * T(1.0 / 24.0)), a2 * b2, h);
-    }
-    {
-      const T a = T(1400) * xrcp(xsqrt(T(1) + xexp((T(5) - V) * T(1.0 / 6.0))));
-      const T b = sig((V - T(35)) * T(1.0 / 15.0));
-      g[5] = rush_larsen(y[12], sig((T(-5) - V) * T(1.0 / 14.0)), a * b + T(80), h);
-    }
-    {
-      const T vr = V + T(40), vs = V + T(45);
-      g[6] = rush_larsen(y[13], sig((T(20) - V) * T(1.0 / 6.0)),
-                         T(9.5) * xexp(-vr * vr * T(1.0 / 1800.0)) + T(0.8), h);
-      g[7] = rush_larsen(y[14], sig((V + T(20)) * T(0.2)),
-                         T(85) * xexp(-vs * vs * T(1.0 / 320.0)) + T(5) * sig((V - T(20)) * T(0.2)) +
-                             T(3),
-                         h);
-    }
-    {
-      const T ad = T(1.4) * sig((T(-35) - V) * T(1.0 / 13.0)) + T(0.25);
-      const T bd = T(1.4) * sig((V + T(5)) * T(0.2));
-      const T gd = sig((T(50) - V) * T(0.05));
-      g[8] = rush_larsen(y[15], sig((T(-8) - V) * T(1.0 / 7.5)), ad * bd + gd, h);
-      const T vf = V + T(27);
-      const T tf = T(1102.5) * xexp(-vf * vf * T(1.0 / 225.0)) +
-                   T(200) * sig((T(13) - V) * T(0.1)) + T(180) * s30 + T(20);
-      g[9] = rush_larsen(y[16], sig((V + T(20)) * T(1.0 / 7.0)), tf, h);
-      const T vf2 = V + T(25);
-      const T tf2 = T(600) * xexp(-vf2 * vf2 * T(1.0 / 170.0)) +
-                    T(31) * sig((T(25) - V) * T(0.1)) + T(16) * s30;
-      g[10] = rush_larsen(y[17], T(0.67) * sig((V + T(35)) * T(1.0 / 7.0)) + T(0.33), tf2, h);
-      const T q = (y[4] * T(20)) * (y[4] * T(20));
-      const T r1q = xrcp(T(1) + q);
-      g[11] = rush_larsen(y[18], T(0.6) * r1q + T(0.4), T(80) * r1q + T(2), h);
-    }
+    for (int a = 0; a < 12; ++a) g[a] = rl_rate(y[7 + a], inf[a], rate[a], h);
 
     // commit
     y[3] = free_from_total(total_from_free(y[3], T(kBufc), T(kKbufc)) + h * dCai, T(kBufc),

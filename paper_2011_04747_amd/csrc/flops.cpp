@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "cell_models.h"
+#include "cell_models_adjoint.h"
 #include "mono_internal.h"
 
 namespace {
@@ -67,5 +68,34 @@ extern "C" mono_status mono_model_flops(int32_t model, const double* state, cons
     return MONO_EINVAL;
   const long long v[7] = {c.add, c.mul, c.div, c.exp, c.log, c.sqrt, c.cmp};
   for (int a = 0; a < 7; ++a) out[a] = v[a];
+  return MONO_OK;
+}
+
+// Host evaluation of the kernel's model code in FP64 (diagnostics and tests).
+extern "C" mono_status mono_model_substep_host(int32_t model, double* y, const double* p,
+                                               double h, int32_t clamp) {
+  if (!y || !p || !(h > 0.0)) return MONO_EINVAL;
+  if (model == MONO_MODEL_LINEAR)
+    mono::LinearModel::substep(y, p, h, clamp != 0);
+  else if (model == MONO_MODEL_MS)
+    mono::MSModel::substep(y, p, h, clamp != 0);
+  else if (model == MONO_MODEL_TP06_EPI)
+    mono::TP06Model::substep(y, p, h, clamp != 0);
+  else
+    return MONO_EINVAL;
+  return MONO_OK;
+}
+
+extern "C" mono_status mono_model_vjp_host(int32_t model, const double* y, const double* p,
+                                           double h, int32_t clamp, double* lam, double* gp) {
+  if (!y || !p || !lam || !gp || !(h > 0.0)) return MONO_EINVAL;
+  if (model == MONO_MODEL_LINEAR)
+    mono::linear_substep_vjp(y, p, h, clamp != 0, lam, gp);
+  else if (model == MONO_MODEL_MS)
+    mono::ms_substep_vjp(y, p, h, clamp != 0, lam, gp);
+  else if (model == MONO_MODEL_TP06_EPI)
+    mono::tp06_substep_vjp(y, p, h, clamp != 0, lam, gp);
+  else
+    return MONO_EINVAL;
   return MONO_OK;
 }

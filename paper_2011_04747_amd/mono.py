@@ -33,7 +33,8 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_get_state_device_async", "mono_set_state", "mono_set_time_level",
            "mono_prepare", "mono_get_info", "mono_estimate_lambda", "mono_set_stream",
            "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
-           "mono_model_flops", "mono_set_launch", "mono_get_launch")
+           "mono_model_flops", "mono_set_launch", "mono_get_launch",
+           "mono_model_substep_host", "mono_model_vjp_host")
 
 
 class MonoError(RuntimeError):
@@ -100,6 +101,8 @@ def lib():
             "mono_apply_phase": [vp, i32, i64, i32],
             "mono_debug": [vp, i32, vp],
             "mono_model_flops": [i32, vp, vp, vp],
+            "mono_model_substep_host": [i32, vp, vp, dbl, i32],
+            "mono_model_vjp_host": [i32, vp, vp, dbl, i32, vp, vp],
             "mono_set_launch": [vp, C.POINTER(Launch)],
             "mono_get_launch": [vp, C.POINTER(Launch)],
         }
@@ -132,6 +135,26 @@ def model_flops(model, state, params):
     out = np.zeros(7, np.int64)
     _check(lib().mono_model_flops(int(model), y.ctypes.data, p.ctypes.data, out.ctypes.data))
     return dict(zip(("add", "mul", "div", "exp", "log", "sqrt", "cmp"), (int(v) for v in out)))
+
+
+def model_substep_host(model, state, params, h, clamp=False):
+    """One substep of the kernel's model code, evaluated on the host in FP64."""
+    y = np.array(state, dtype=np.float64)
+    p = _c(params, np.float64)
+    _check(lib().mono_model_substep_host(int(model), y.ctypes.data, p.ctypes.data, float(h),
+                                         int(clamp)))
+    return y
+
+
+def model_vjp_host(model, state, params, h, lam, clamp=False):
+    """(dF/dy)^T lam and (dF/dp)^T lam of one substep, host FP64."""
+    y = _c(state, np.float64)
+    p = _c(params, np.float64)
+    l = np.array(lam, dtype=np.float64)
+    gp = np.zeros(len(p), np.float64)
+    _check(lib().mono_model_vjp_host(int(model), y.ctypes.data, p.ctypes.data, float(h),
+                                     int(clamp), l.ctypes.data, gp.ctypes.data))
+    return l, gp
 
 
 class Sim:
