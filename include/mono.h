@@ -240,6 +240,32 @@ mono_status mono_model_vjp_host(int32_t model, const double *state, const double
  * half step.  Synchronising. */
 mono_status mono_apply_phase(mono_sim *sim, int32_t phase, int64_t step, int32_t m);
 
+/* --- adjoint ---------------------------------------------------------------
+ * Loss L = sum over outer steps n < n_steps and sensors q of
+ * (V[nodes[q]] at reaction entry of step n - target[n * n + q])^2, with the
+ * step index n absolute (time level n*dt); targets are copied.  Sensor nodes
+ * must be distinct. */
+mono_status mono_set_sensors(mono_sim *sim, int32_t n, const int32_t *nodes, const double *target,
+                             int64_t n_steps);
+
+/* Advance n_steps outer steps from the current time level like mono_step,
+ * keeping a snapshot of the state every ckpt_every steps (uniform
+ * checkpointing: memory ~ (n_steps/ckpt_every) states plus a ckpt_every-step
+ * tape), and return the loss (FP64).  Synchronising.  Needs k_max <= 16.
+ * EUNSUPPORTED with a clamped potential. */
+mono_status mono_forward_taped(mono_sim *sim, int64_t n_steps, double dt, int32_t ckpt_every,
+                               double *loss);
+
+/* Gradient of the last taped run's loss by a reverse sweep that recomputes
+ * each segment from its checkpoint (the k each node took and l are held
+ * fixed: the loss is piecewise smooth in the parameters).  grad_sigma[n_nodes]:
+ * dL/dsigma_i of the per-node conductivity scales (of 1 where the mesh had
+ * none); grad_params[n_params]: for each parameter row a, the derivative
+ * with respect to a common multiplier of that row at 1,
+ * sum_i p_i[a] dL/dp_i[a].  Either pointer may be NULL.  Leaves the state
+ * where the taped run ended.  FP64 accumulation of both gradients. */
+mono_status mono_backward(mono_sim *sim, double *grad_sigma, double *grad_params);
+
 /* Test hooks.  `what`:
  *  MONO_DEBUG_KTRACE: arg -> mono_ktrace (device buffers n_steps x n_nodes,
  *      uint8, row = step - base_step): record the k each node picks and/or

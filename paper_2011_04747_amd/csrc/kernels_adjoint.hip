@@ -1,0 +1,229 @@
+// Adjoint kernels of the split step: the gradient of a sensor-mismatch loss
+// with respect to per-node conductivity scales and the cell-model parameter
+// rows, by reverse sweeps over a taped forward run.
+//
+// Diffusion substep (forward, difference form):
+//   V'_i = V_i + dt_ad ( (1/m_i) sum_j e_ij (V_j - V_i) + s_i ),  e = -K.
+// Its reverse with u = lam'/m:
+//   lam_i = lam'_i + dt_ad sum_j e_ij (u_j - u_i)              (K symmetric)
+//   dL/dsigma_i += dt_ad sum_j e_ij/(sigma_i + sigma_j) (u_i - u_j)(V_j - V_i)
+// because e_ij = e0_ij (sigma_i + sigma_j)/2 off the diagonal.
+// Reaction: every node replays its k substeps from the taped entry state into
+// private memory and applies the hand-written reverse substep backwards.
+#include "cell_models.h"
+#include "cell_models_adjoint.h"
+#include "mono_internal.h"
+
+namespace mono {
+
+// --- loss at reaction entry -------------------------------------------------
+// out = sum_q (V[sensor_q] - target_q)^2 in FP64 (one workgroup)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sensor_loss(const T* V, const int32_t* sens, int ns,
+                                                     const double* target, double* out) {
+  __shared__ double part[4];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < ns; q += 256) {
+    const double e = (double)V[sens[q]] - target[q];
+    acc += e * e;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
+}
+
+// lam_V[sensor_q] += 2 (V_entry[sensor_q] - target_q)   (sensors are distinct)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sensor_inject(T* lamV, const T* V, const int32_t* sens,
+                                                       int ns, const double* target) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= ns) return;
+  const int32_t i = sens[q];
+  lamV[i] = (T)((double)lamV[i] + 2.0 * ((double)V[i] - target[q]));
+}
+
+// --- adjoint diffusion substep ------------------------------------------------
+template <typename T, bool BATCHED>
+__global__ __launch_bounds__(256) void k_adj_diff_stencil(AdjDiffArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const int q = BATCHED ? a.inst[i] : 0;
+  const T li = a.lam_in[i];
+  if (BATCHED && a.m >= a.l[q]) {
+    a.lam_out[i] = li;
+    return;
+  }
+  const int np = a.P;
+  const int64_t last = a.n - 1;
+  const int64_t first = BATCHED ? a.inst_off[q] : 0;
+  const T ui = li * a.minv[i];
+  const T vi = a.V[i];
+  const T si = a.sigma[i];
+  T acc = T(0), gs = T(0);
+  for (int p = 0; p < np; ++p) {
+    const int64_t o = a.off[(int64_t)q * np + p];
+    const int64_t jf = i + o;
+    const int64_t jb = i - o;
+    const int64_t jfc = jf <= last ? jf : last;
+    const int64_t jbc = jb >= first ? jb : first;
+    const T wf = a.e[(int64_t)p * a.Np + i];
+    const T wb = (jb >= first) ? a.e[(int64_t)p * a.Np + jbc] : T(0);
+    const T uf = a.lam_in[jfc] * a.minv[jfc];
+    const T ub = a.lam_in[jbc] * a.minv[jbc];
+    acc += wf * (uf - ui) + wb * (ub - ui);
+    gs += wf * xrcp(si + a.sigma[jfc]) * (ui - uf) * (a.V[jfc] - vi);
+    gs += wb * xrcp(si + a.sigma[jbc]) * (ui - ub) * (a.V[jbc] - vi);
+  }
+  const double dt_ad = a.dt_ad[q];
+  a.lam_out[i] = li + (T)dt_ad * acc;
+  a.gsig[i] += dt_ad * (double)gs;
+}
+
+// ELL stores a_ij = e_ij / m_i, so e_ij = a_ij / (1/m_i).
+template <typename T, bool BATCHED>
+__global__ __launch_bounds__(256) void k_adj_diff_ell(AdjDiffArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const int q = BATCHED ? a.inst[i] : 0;
+  const T li = a.lam_in[i];
+  if (BATCHED && a.m >= a.l[q]) {
+    a.lam_out[i] = li;
+    return;
+  }
+  const T mi = a.minv[i];
+  const T ui = li * mi;
+  const T vi = a.V[i];
+  const T si = a.sigma[i];
+  const T rm = xrcp(mi);
+  T acc = T(0), gs = T(0);
+  for (int s = 0; s < a.W; ++s) {
+    const int64_t k = (int64_t)s * a.Np + i;
+    const int32_t j = a.col[k];
+    const T e = a.val[k] * rm;
+    const T uj = a.lam_in[j] * a.minv[j];
+    acc += e * (uj - ui);
+    gs += e * xrcp(si + a.sigma[j]) * (ui - uj) * (a.V[j] - vi);
+  }
+  const double dt_ad = a.dt_ad[q];
+  a.lam_out[i] = li + (T)dt_ad * acc;
+  a.gsig[i] += dt_ad * (double)gs;
+}
+
+template <typename T>
+void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (layout == MONO_LAYOUT_ELL) {
+    if (a.inst)
+      hipLaunchKernelGGL((k_adj_diff_ell<T, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_diff_ell<T, false>), grid, dim3(256), 0, s, a);
+  } else {
+    if (a.inst)
+      hipLaunchKernelGGL((k_adj_diff_stencil<T, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_diff_stencil<T, false>), grid, dim3(256), 0, s, a);
+  }
+}
+
+// --- adjoint reaction step ------------------------------------------------------
+struct LinearAdj {
+  template <typename T>
+  __device__ static void vjp(const T* y, const T* p, T h, T* lam, T* gp) {
+    linear_substep_vjp(y, p, h, false, lam, gp);
+  }
+};
+struct MSAdj {
+  template <typename T>
+  __device__ static void vjp(const T* y, const T* p, T h, T* lam, T* gp) {
+    ms_substep_vjp(y, p, h, false, lam, gp);
+  }
+};
+struct TP06Adj {
+  template <typename T>
+  __device__ static void vjp(const T* y, const T* p, T h, T* lam, T* gp) {
+    tp06_substep_vjp(y, p, h, false, lam, gp);
+  }
+};
+
+template <typename T, class M, class A>
+__global__ __launch_bounds__(256) void k_adj_ionic(AdjIonArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = i < a.n;
+  double gpd[M::P];
+  for (int b = 0; b < M::P; ++b) gpd[b] = 0.0;
+  if (live) {
+    T p[M::P];
+    for (int b = 0; b < M::P; ++b)
+      p[b] = (a.par_pernode >> b & 1u) ? a.par[(int64_t)b * a.Np + i] : a.par_uniform[b];
+    const int k = a.k[i];
+    const T h = (T)(a.dt / (double)k);
+    T ys[kAdjMaxK][M::S];
+    for (int s = 0; s < M::S; ++s) ys[0][s] = a.entry[(int64_t)s * a.Np + i];
+    for (int q = 1; q < k; ++q) {
+      for (int s = 0; s < M::S; ++s) ys[q][s] = ys[q - 1][s];
+      M::substep(ys[q], p, h, false);
+    }
+    T lam[M::S];
+    for (int s = 0; s < M::S; ++s) lam[s] = a.lam[(int64_t)s * a.Np + i];
+    T gp[M::P];
+    for (int b = 0; b < M::P; ++b) gp[b] = T(0);
+    for (int q = k - 1; q >= 0; --q) A::vjp(ys[q], p, h, lam, gp);
+    for (int s = 0; s < M::S; ++s) a.lam[(int64_t)s * a.Np + i] = lam[s];
+    // derivative with respect to a common multiplier of each parameter row
+    for (int b = 0; b < M::P; ++b) gpd[b] = (double)p[b] * (double)gp[b];
+  }
+  // workgroup sum into this workgroup's own FP64 slot (no atomics)
+  __shared__ double part[4][M::P];
+  for (int b = 0; b < M::P; ++b) {
+    double v = gpd[b];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][b] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < M::P) {
+    const int b = threadIdx.x;
+    a.gpart[(int64_t)blockIdx.x * kMaxParams + b] += part[0][b] + part[1][b] + part[2][b] + part[3][b];
+  }
+}
+
+template <typename T>
+void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (model == MONO_MODEL_LINEAR)
+    hipLaunchKernelGGL((k_adj_ionic<T, LinearModel, LinearAdj>), grid, dim3(256), 0, s, a);
+  else if (model == MONO_MODEL_MS)
+    hipLaunchKernelGGL((k_adj_ionic<T, MSModel, MSAdj>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06Model, TP06Adj>), grid, dim3(256), 0, s, a);
+}
+
+template <typename T>
+void launch_sensor_loss(const T* V, const int32_t* sens, int ns, const double* target,
+                        double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_sensor_loss<T>), dim3(1), dim3(256), 0, s, V, sens, ns, target, out);
+}
+template <typename T>
+void launch_sensor_inject(T* lamV, const T* V, const int32_t* sens, int ns, const double* target,
+                          hipStream_t s) {
+  if (ns <= 0) return;
+  hipLaunchKernelGGL((k_sensor_inject<T>), dim3((ns + 255) / 256), dim3(256), 0, s, lamV, V, sens,
+                     ns, target);
+}
+
+template void launch_adj_diffusion<float>(int, const AdjDiffArgs<float>&, hipStream_t);
+template void launch_adj_diffusion<double>(int, const AdjDiffArgs<double>&, hipStream_t);
+template void launch_adj_ionic<float>(int, const AdjIonArgs<float>&, hipStream_t);
+template void launch_adj_ionic<double>(int, const AdjIonArgs<double>&, hipStream_t);
+template void launch_sensor_loss<float>(const float*, const int32_t*, int, const double*, double*,
+                                        hipStream_t);
+template void launch_sensor_loss<double>(const double*, const int32_t*, int, const double*,
+                                         double*, hipStream_t);
+template void launch_sensor_inject<float>(float*, const float*, const int32_t*, int,
+                                          const double*, hipStream_t);
+template void launch_sensor_inject<double>(double*, const double*, const int32_t*, int,
+                                           const double*, hipStream_t);
+
+}  // namespace mono

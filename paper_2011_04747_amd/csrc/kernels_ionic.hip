@@ -63,13 +63,13 @@ __global__ __launch_bounds__(BLOCK) void k_ionic(IonArgs<T> a) {
     // k = min(k0 + floor|d|, k_max), k0 = 5 for d > 0 else 1
     const T kd = (d > T(0) ? T(5) : T(1)) + xfloor(fabs(d));
     k = (kd <= (T)a.k_max) ? (int)kd : a.k_max;
-    if (a.kt.mode) {
-      const int64_t r = step - a.kt.base;
-      if (r >= 0 && r < a.kt.steps) {
-        const int64_t at = r * a.n + i;
-        if (a.kt.mode & 1) a.kt.rec[at] = (uint8_t)k;
-        if (a.kt.mode & 2) k = a.kt.rep[at];
-      }
+    if (a.kt.mode & 1) {
+      const int64_t r = step - a.kt.rec_base;
+      if (r >= 0 && r < a.kt.rec_steps) a.kt.rec[r * a.n + i] = (uint8_t)k;
+    }
+    if (a.kt.mode & 2) {
+      const int64_t r = step - a.kt.rep_base;
+      if (r >= 0 && r < a.kt.rep_steps) k = a.kt.rep[r * a.n + i];
     }
     a.lastk[i] = (uint8_t)k;
   }

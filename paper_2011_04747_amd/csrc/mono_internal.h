@@ -105,9 +105,10 @@ struct DiffArgs {
 
 struct KTraceArgs {
   int mode;                  // bit 0 record, bit 1 replay
-  uint8_t* rec;
-  const uint8_t* rep;
-  int64_t base, steps;
+  uint8_t* rec;              // row (step - rec_base), n values per row
+  const uint8_t* rep;        // row (step - rep_base)
+  int64_t rec_base, rec_steps;
+  int64_t rep_base, rep_steps;
 };
 
 template <typename T>
@@ -134,6 +135,52 @@ struct IonArgs {
 // ---------------------------------------------------------------------------
 // launchers (kernels_*.hip)
 // ---------------------------------------------------------------------------
+// adjoint of one diffusion substep (kernels_adjoint.hip)
+constexpr int kAdjMaxK = 16;   // largest k the adjoint reaction kernel replays
+template <typename T>
+struct AdjDiffArgs {
+  int64_t n, Np;
+  const T* lam_in;           // adjoint of the substep output
+  T* lam_out;                // adjoint of the substep input
+  const T* V;                // forward input of the substep
+  const T* minv;
+  const T* sigma;
+  int W;
+  const int32_t* col;
+  const T* val;
+  int P;
+  const T* e;
+  const int32_t* off;
+  const int32_t* inst;
+  const int64_t* inst_off;
+  const int32_t* l;
+  const double* dt_ad;
+  int m;
+  double* gsig;              // += dL/dsigma (FP64)
+};
+template <typename T>
+struct AdjIonArgs {
+  int64_t n, Np;
+  const T* entry;            // S x Np reaction-entry state
+  const uint8_t* k;          // n substep counts
+  T* lam;                    // S x Np adjoint (V first)
+  const T* par;
+  T par_uniform[kMaxParams];
+  uint32_t par_pernode;
+  double dt;
+  double* gpart;             // per workgroup kMaxParams FP64 partial sums
+};
+template <typename T>
+void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s);
+template <typename T>
+void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s);
+template <typename T>
+void launch_sensor_loss(const T* V, const int32_t* sens, int ns, const double* target,
+                        double* out, hipStream_t s);
+template <typename T>
+void launch_sensor_inject(T* lamV, const T* V, const int32_t* sens, int ns, const double* target,
+                          hipStream_t s);
+
 template <typename T>
 void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s);
 

@@ -122,6 +122,25 @@ struct mono_sim {
   std::vector<hipEvent_t> ev_pool;
   double ktime_ms[2] = {0.0, 0.0};
   int64_t klaunches[2] = {0, 0};
+  // adjoint: conductivity scales, loss sensors, checkpoints and segment tape
+  void* d_sigma = nullptr;         // Np, simulation precision
+  int32_t* d_sens = nullptr;
+  int ns = 0;
+  double* d_target = nullptr;      // target_steps x ns
+  int64_t target_steps = 0;
+  bool taped = false;
+  int64_t tape_step0 = 0, tape_steps = 0;
+  int ckpt_every = 0;
+  std::vector<void*> d_ckpt;       // state snapshots at segment starts
+  void* d_final = nullptr;         // state after the taped run
+  void* d_seg_vsub = nullptr;      // ckpt_every x 2 l_max x Np
+  void* d_seg_entry = nullptr;     // ckpt_every x S x Np
+  uint8_t* d_seg_k = nullptr;      // ckpt_every x n
+  void* d_lam = nullptr;           // S x Np adjoint of the state
+  void* d_lamV2 = nullptr;         // Np, ping-pong partner of the V adjoint
+  double* d_gsig = nullptr;        // Np
+  double* d_gpart = nullptr;       // workgroups x kMaxParams
+  double* d_loss_steps = nullptr;  // tape_steps
 };
 
 namespace {
@@ -386,6 +405,203 @@ void free_model(mono_sim* s) {
   dfree(s->d_par);
 }
 
+void free_tape(mono_sim* s) {
+  for (void*& p : s->d_ckpt) dfree(p);
+  s->d_ckpt.clear();
+  dfree(s->d_final);
+  dfree(s->d_seg_vsub);
+  dfree(s->d_seg_entry);
+  dfree(s->d_seg_k);
+  dfree(s->d_lam);
+  dfree(s->d_lamV2);
+  dfree(s->d_gsig);
+  dfree(s->d_gpart);
+  dfree(s->d_loss_steps);
+  s->taped = false;
+}
+
+// snapshot layout: V, the other S-1 states, V_prev (all Np, precision T),
+// then the activation times (Np doubles)
+size_t snapshot_bytes(const mono_sim* s) { return (size_t)(s->S + 1) * s->Np * s->es + s->Np * 8; }
+
+hipError_t save_state(mono_sim* s, void* dst) {
+  const size_t b = s->Np * s->es;
+  char* d = (char*)dst;
+  hipError_t e = hipMemcpyAsync(d, s->d_V[0], b, hipMemcpyDeviceToDevice, s->stream);
+  if (!e && s->S > 1)
+    e = hipMemcpyAsync(d + b, s->d_st, (size_t)(s->S - 1) * b, hipMemcpyDeviceToDevice, s->stream);
+  if (!e) e = hipMemcpyAsync(d + (size_t)s->S * b, s->d_vprev, b, hipMemcpyDeviceToDevice, s->stream);
+  if (!e)
+    e = hipMemcpyAsync(d + (size_t)(s->S + 1) * b, s->d_lat, s->Np * 8, hipMemcpyDeviceToDevice,
+                       s->stream);
+  return e;
+}
+
+hipError_t load_state(mono_sim* s, const void* src) {
+  const size_t b = s->Np * s->es;
+  const char* d = (const char*)src;
+  hipError_t e = hipMemcpyAsync(s->d_V[0], d, b, hipMemcpyDeviceToDevice, s->stream);
+  if (!e && s->S > 1)
+    e = hipMemcpyAsync(s->d_st, d + b, (size_t)(s->S - 1) * b, hipMemcpyDeviceToDevice, s->stream);
+  if (!e) e = hipMemcpyAsync(s->d_vprev, d + (size_t)s->S * b, b, hipMemcpyDeviceToDevice, s->stream);
+  if (!e)
+    e = hipMemcpyAsync(s->d_lat, d + (size_t)(s->S + 1) * b, s->Np * 8, hipMemcpyDeviceToDevice,
+                       s->stream);
+  return e;
+}
+
+// One outer step with clock offset g, optionally taping: the inputs of the
+// 2 l_max diffusion substeps (vsub), the reaction-entry state (entry), the k
+// each node takes (krec, row step - krec_base), and the loss at reaction
+// entry (loss_slot).
+template <typename T>
+void enqueue_taped_step(mono_sim* s, int64_t g, int64_t step, T* vsub, T* entry, uint8_t* krec,
+                        int64_t krec_base, int64_t krec_steps, double* loss_slot) {
+  const int L = s->l_max;
+  const size_t b = s->Np * s->es;
+  for (int m = 0; m < L; ++m) {
+    if (vsub)
+      (void)hipMemcpyAsync(vsub + (size_t)m * s->Np, s->d_V[m & 1], b, hipMemcpyDeviceToDevice,
+                           s->stream);
+    launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->lc, s->stream);
+  }
+  T* Vmid = (T*)s->d_V[L & 1];
+  if (entry) {
+    (void)hipMemcpyAsync(entry, Vmid, b, hipMemcpyDeviceToDevice, s->stream);
+    if (s->S > 1)
+      (void)hipMemcpyAsync(entry + s->Np, s->d_st, (size_t)(s->S - 1) * b,
+                           hipMemcpyDeviceToDevice, s->stream);
+  }
+  if (loss_slot && s->ns > 0 && step < s->target_steps)
+    launch_sensor_loss<T>(Vmid, s->d_sens, s->ns, s->d_target + step * s->ns, loss_slot,
+                          s->stream);
+  IonArgs<T> ia = ion_args<T>(s, Vmid, g);
+  if (krec) {
+    ia.kt.mode |= 1;
+    ia.kt.rec = krec;
+    ia.kt.rec_base = krec_base;
+    ia.kt.rec_steps = krec_steps;
+  }
+  launch_ionic<T>(s->model, ia, s->lc, s->stream);
+  for (int m = 0; m < L; ++m) {
+    if (vsub)
+      (void)hipMemcpyAsync(vsub + (size_t)(L + m) * s->Np, s->d_V[(L + m) & 1], b,
+                           hipMemcpyDeviceToDevice, s->stream);
+    launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
+  }
+}
+
+template <typename T>
+AdjDiffArgs<T> adj_diff_args(mono_sim* s, const T* lam_in, T* lam_out, const T* V, int m) {
+  AdjDiffArgs<T> a{};
+  a.n = s->n;
+  a.Np = s->Np;
+  a.lam_in = lam_in;
+  a.lam_out = lam_out;
+  a.V = V;
+  a.minv = (const T*)s->d_minv;
+  a.sigma = (const T*)s->d_sigma;
+  a.W = s->W;
+  a.col = s->d_col;
+  a.val = (const T*)s->d_val;
+  a.P = s->P;
+  a.e = (const T*)s->d_e;
+  a.off = s->d_off;
+  a.inst = s->n_inst > 1 ? s->d_inst : nullptr;
+  a.inst_off = s->d_inst_off;
+  a.l = s->d_l;
+  a.dt_ad = s->d_dtad;
+  a.m = m;
+  a.gsig = s->d_gsig;
+  return a;
+}
+
+template <typename T>
+mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
+  const int64_t C = s->ckpt_every;
+  const int64_t nck = (n_steps + C - 1) / C;
+  for (int64_t c = 0; c < nck; ++c) {
+    HIP_TRY(save_state(s, s->d_ckpt[c]));
+    const int64_t t0 = c * C, cn = std::min(C, n_steps - t0);
+    for (int64_t t = 0; t < cn; ++t)
+      enqueue_taped_step<T>(s, t, s->step + t, nullptr, nullptr, nullptr, 0, 0,
+                            s->d_loss_steps + t0 + t);
+    launch_advance_clock(s->d_base, cn, s->stream);
+    HIP_TRY(hipGetLastError());
+    s->step += cn;
+  }
+  HIP_TRY(save_state(s, s->d_final));
+  std::vector<double> ls(n_steps);
+  HIP_TRY(hipMemcpyAsync(ls.data(), s->d_loss_steps, n_steps * 8, hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  double L = 0.0;
+  for (double v : ls) L += v;
+  *loss = L;
+  return MONO_OK;
+}
+
+template <typename T>
+mono_status backward_t(mono_sim* s) {
+  const int64_t C = s->ckpt_every, N = s->tape_steps;
+  const int64_t nck = (N + C - 1) / C;
+  const int L = s->l_max, S = s->S;
+  const size_t b = s->Np * s->es;
+  T* lamV = (T*)s->d_lam;
+  T* lamV2 = (T*)s->d_lamV2;
+  for (int64_t c = nck - 1; c >= 0; --c) {
+    const int64_t t0 = c * C, cn = std::min(C, N - t0);
+    const int64_t step0 = s->tape_step0 + t0;
+    // recompute the segment from its checkpoint, taping what the reverse needs
+    HIP_TRY(load_state(s, s->d_ckpt[c]));
+    HIP_TRY(hipMemcpyAsync(s->d_base, &step0, 8, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int64_t t = 0; t < cn; ++t)
+      enqueue_taped_step<T>(s, t, step0 + t, (T*)s->d_seg_vsub + (size_t)t * 2 * L * s->Np,
+                            (T*)s->d_seg_entry + (size_t)t * S * s->Np, s->d_seg_k, step0, cn,
+                            nullptr);
+    // reverse the segment
+    for (int64_t t = cn - 1; t >= 0; --t) {
+      const int64_t step = step0 + t;
+      const T* vs = (const T*)s->d_seg_vsub + (size_t)t * 2 * L * s->Np;
+      const T* entry = (const T*)s->d_seg_entry + (size_t)t * S * s->Np;
+      for (int m = L - 1; m >= 0; --m) {
+        launch_adj_diffusion<T>(s->layout, adj_diff_args<T>(s, lamV, lamV2, vs + (size_t)(L + m) * s->Np, m),
+                                s->stream);
+        HIP_TRY(hipMemcpyAsync(lamV, lamV2, b, hipMemcpyDeviceToDevice, s->stream));
+      }
+      AdjIonArgs<T> ai{};
+      ai.n = s->n;
+      ai.Np = s->Np;
+      ai.entry = entry;
+      ai.k = s->d_seg_k + (size_t)t * s->n;
+      ai.lam = lamV;
+      ai.par = (const T*)s->d_par;
+      for (int q = 0; q < kMaxParams; ++q) ai.par_uniform[q] = (T)s->par_uniform[q];
+      ai.par_pernode = s->par_pernode;
+      ai.dt = s->dt;
+      ai.gpart = s->d_gpart;
+      launch_adj_ionic<T>(s->model, ai, s->stream);
+      if (s->ns > 0 && step < s->target_steps)
+        launch_sensor_inject<T>(lamV, entry, s->d_sens, s->ns, s->d_target + step * s->ns,
+                                s->stream);
+      for (int m = L - 1; m >= 0; --m) {
+        launch_adj_diffusion<T>(s->layout, adj_diff_args<T>(s, lamV, lamV2, vs + (size_t)m * s->Np, m),
+                                s->stream);
+        HIP_TRY(hipMemcpyAsync(lamV, lamV2, b, hipMemcpyDeviceToDevice, s->stream));
+      }
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  // leave the simulation where the taped forward run ended
+  HIP_TRY(load_state(s, s->d_final));
+  const int64_t endstep = s->tape_step0 + N;
+  HIP_TRY(hipMemcpyAsync(s->d_base, &endstep, 8, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->step = endstep;
+  return MONO_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -507,6 +723,15 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
       s->dt_s[q] = 0.9 * hr[q];
     }
   }
+  // conductivity scales (adjoint) and 1/m in both layouts
+  {
+    std::vector<double> sg(s->Np, 1.0);
+    if (d->sigma_node) std::copy(d->sigma_node, d->sigma_node + s->n, sg.begin());
+    if (dalloc((char**)&s->d_sigma, s->Np * s->es))
+      return bail(fail(MONO_ENOMEM, "device allocation failed"));
+    mono_status st = upload_real(s, s->d_sigma, sg.data(), sg.size());
+    if (st != MONO_OK) return bail(st);
+  }
   // operator layout
   int layout = d->layout;
   StencilHost sh;
@@ -530,8 +755,15 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
     EllHost eh;
     build_ell(s->K, s->Np, eh);
     s->W = eh.width;
-    if (dalloc(&s->d_col, eh.col.size()) || dalloc((char**)&s->d_val, eh.val.size() * s->es))
+    if (dalloc(&s->d_col, eh.col.size()) || dalloc((char**)&s->d_val, eh.val.size() * s->es) ||
+        dalloc((char**)&s->d_minv, s->Np * s->es))
       return bail(fail(MONO_ENOMEM, "device allocation failed"));
+    {
+      std::vector<double> mi(s->Np, 0.0);
+      for (int64_t i = 0; i < s->n; ++i) mi[i] = 1.0 / s->K.mass[i];
+      mono_status st = upload_real(s, s->d_minv, mi.data(), mi.size());
+      if (st != MONO_OK) return bail(st);
+    }
     if (hipMemcpy(s->d_col, eh.col.data(), eh.col.size() * 4, hipMemcpyHostToDevice))
       return bail(fail(MONO_EDEVICE, "upload failed"));
     mono_status st = upload_real(s, s->d_val, eh.val.data(), eh.val.size());
@@ -559,6 +791,10 @@ void mono_destroy(mono_sim* s) {
   dfree(s->d_base);
   dfree(s->d_flag);
   dfree(s->d_stats);
+  free_tape(s);
+  dfree(s->d_sigma);
+  dfree(s->d_sens);
+  dfree(s->d_target);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -900,6 +1136,100 @@ mono_status mono_estimate_lambda(mono_sim* s, int32_t iters) {
   return MONO_OK;
 }
 
+mono_status mono_set_sensors(mono_sim* s, int32_t n, const int32_t* nodes, const double* target,
+                             int64_t n_steps) {
+  if (!s || n < 0 || (n > 0 && (!nodes || !target)) || n_steps < 0)
+    return fail(MONO_EINVAL, "bad argument");
+  std::vector<int32_t> v(nodes, nodes + n);
+  for (int32_t i : v)
+    if (i < 0 || i >= s->n) return fail(MONO_EINVAL, "sensor node out of range");
+  std::vector<int32_t> u = v;
+  std::sort(u.begin(), u.end());
+  if (std::adjacent_find(u.begin(), u.end()) != u.end())
+    return fail(MONO_EINVAL, "sensor nodes must be distinct");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  dfree(s->d_sens);
+  dfree(s->d_target);
+  s->ns = n;
+  s->target_steps = n_steps;
+  if (n > 0) {
+    if (dalloc(&s->d_sens, n) || dalloc(&s->d_target, (size_t)n * std::max<int64_t>(n_steps, 1)))
+      return fail(MONO_ENOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpy(s->d_sens, v.data(), n * 4, hipMemcpyHostToDevice));
+    if (n_steps > 0)
+      HIP_TRY(hipMemcpy(s->d_target, target, (size_t)n * n_steps * 8, hipMemcpyHostToDevice));
+  }
+  return MONO_OK;
+}
+
+mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t ckpt_every,
+                               double* loss) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (n_steps < 1 || ckpt_every < 1 || !loss) return fail(MONO_EINVAL, "bad argument");
+  if (s->latched) return fail(MONO_ESTATE, "simulation latched after a non-finite potential");
+  st = prepare(s, dt);
+  if (st != MONO_OK) return st;
+  if (s->k_max > kAdjMaxK) return fail(MONO_EUNSUPPORTED, "adjoint needs k_max <= 16");
+  if (s->vclamp) return fail(MONO_EUNSUPPORTED, "adjoint with a clamped potential");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  free_tape(s);
+  const int64_t C = std::min<int64_t>(ckpt_every, n_steps);
+  const int64_t nck = (n_steps + C - 1) / C;
+  const size_t snap = snapshot_bytes(s);
+  const size_t nblk = (size_t)((s->n + 255) / 256);
+  s->d_ckpt.assign(nck, nullptr);
+  bool ok = true;
+  for (int64_t c = 0; c < nck && ok; ++c) ok = !dalloc((char**)&s->d_ckpt[c], snap);
+  ok = ok && !dalloc((char**)&s->d_final, snap) &&
+       !dalloc((char**)&s->d_seg_vsub, (size_t)C * 2 * s->l_max * s->Np * s->es) &&
+       !dalloc((char**)&s->d_seg_entry, (size_t)C * s->S * s->Np * s->es) &&
+       !dalloc(&s->d_seg_k, (size_t)C * s->n) &&
+       !dalloc((char**)&s->d_lam, (size_t)s->S * s->Np * s->es) &&
+       !dalloc((char**)&s->d_lamV2, s->Np * s->es) && !dalloc(&s->d_gsig, s->Np) &&
+       !dalloc(&s->d_gpart, nblk * kMaxParams) && !dalloc(&s->d_loss_steps, n_steps);
+  if (!ok) {
+    free_tape(s);
+    return fail(MONO_ENOMEM, "not enough device memory for the checkpoints and tape");
+  }
+  HIP_TRY(hipMemsetAsync(s->d_loss_steps, 0, n_steps * 8, s->stream));
+  s->ckpt_every = (int)C;
+  s->tape_step0 = s->step;
+  s->tape_steps = n_steps;
+  st = s->prec == MONO_F64 ? forward_taped_t<double>(s, n_steps, loss)
+                           : forward_taped_t<float>(s, n_steps, loss);
+  if (st != MONO_OK) return st;
+  s->taped = true;
+  return check_flag(s);
+}
+
+mono_status mono_backward(mono_sim* s, double* grad_sigma, double* grad_params) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (!s->taped) return fail(MONO_ESTATE, "call mono_forward_taped first");
+  if (s->step != s->tape_step0 + s->tape_steps)
+    return fail(MONO_ESTATE, "the simulation moved since the taped run");
+  const size_t nblk = (size_t)((s->n + 255) / 256);
+  HIP_TRY(hipMemsetAsync(s->d_lam, 0, (size_t)s->S * s->Np * s->es, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_lamV2, 0, s->Np * s->es, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_gsig, 0, s->Np * 8, s->stream));
+  HIP_TRY(hipMemsetAsync(s->d_gpart, 0, nblk * kMaxParams * 8, s->stream));
+  st = s->prec == MONO_F64 ? backward_t<double>(s) : backward_t<float>(s);
+  if (st != MONO_OK) return st;
+  if (grad_sigma)
+    HIP_TRY(hipMemcpy(grad_sigma, s->d_gsig, s->n * 8, hipMemcpyDeviceToHost));
+  if (grad_params) {
+    std::vector<double> gp(nblk * kMaxParams);
+    HIP_TRY(hipMemcpy(gp.data(), s->d_gpart, gp.size() * 8, hipMemcpyDeviceToHost));
+    for (int b = 0; b < s->Pm; ++b) {
+      double acc = 0.0;
+      for (size_t q = 0; q < nblk; ++q) acc += gp[q * kMaxParams + b];
+      grad_params[b] = acc;
+    }
+  }
+  return check_flag(s);
+}
+
 mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
   if (!s || !c) return fail(MONO_EINVAL, "NULL argument");
   auto okb = [](int b) { return b == 128 || b == 256 || b == 512; };
@@ -959,8 +1289,8 @@ mono_status mono_debug(mono_sim* s, int32_t what, void* arg) {
       s->kt.mode = k->mode;
       s->kt.rec = k->record;
       s->kt.rep = k->replay;
-      s->kt.base = k->base_step;
-      s->kt.steps = k->mode ? k->n_steps : 0;
+      s->kt.rec_base = s->kt.rep_base = k->base_step;
+      s->kt.rec_steps = s->kt.rep_steps = k->mode ? k->n_steps : 0;
       drop_graph(s);
       return MONO_OK;
     }

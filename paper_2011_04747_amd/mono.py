@@ -34,7 +34,8 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_prepare", "mono_get_info", "mono_estimate_lambda", "mono_set_stream",
            "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
            "mono_model_flops", "mono_set_launch", "mono_get_launch",
-           "mono_model_substep_host", "mono_model_vjp_host")
+           "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
+           "mono_forward_taped", "mono_backward")
 
 
 class MonoError(RuntimeError):
@@ -103,6 +104,9 @@ def lib():
             "mono_model_flops": [i32, vp, vp, vp],
             "mono_model_substep_host": [i32, vp, vp, dbl, i32],
             "mono_model_vjp_host": [i32, vp, vp, dbl, i32, vp, vp],
+            "mono_set_sensors": [vp, i32, vp, vp, i64],
+            "mono_forward_taped": [vp, i64, dbl, i32, vp],
+            "mono_backward": [vp, vp, vp],
             "mono_set_launch": [vp, C.POINTER(Launch)],
             "mono_get_launch": [vp, C.POINTER(Launch)],
         }
@@ -276,6 +280,28 @@ class Sim:
 
     def set_stream(self, stream):
         _check(lib().mono_set_stream(self.h, C.c_void_p(int(stream))))
+
+    # -- adjoint -----------------------------------------------------------------
+    def set_sensors(self, nodes, target):
+        """Loss sensors and targets (n_steps x len(nodes)) sampled at reaction entry."""
+        nodes = _c(nodes, np.int32)
+        t = _c(target, np.float64)
+        _check(lib().mono_set_sensors(self.h, len(nodes), nodes.ctypes.data, t.ctypes.data,
+                                      t.shape[0]))
+
+    def forward_taped(self, n_steps, dt, ckpt_every=50):
+        out = np.zeros(1)
+        _check(lib().mono_forward_taped(self.h, int(n_steps), float(dt), int(ckpt_every),
+                                        out.ctypes.data))
+        return float(out[0])
+
+    def backward(self, n_params=None):
+        """(dL/dsigma per node, derivative for a common multiplier of each parameter row)."""
+        gs = np.zeros(self.n)
+        gp = np.zeros(8)
+        _check(lib().mono_backward(self.h, gs.ctypes.data, gp.ctypes.data))
+        P = n_params if n_params is not None else {0: 2, 1: 5, 2: 6}[self.model]
+        return gs, gp[:P]
 
     # -- test hooks --------------------------------------------------------------
     def ktrace(self, mode, record_ptr=None, replay_ptr=None, n_steps=0, base_step=0):

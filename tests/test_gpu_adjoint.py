@@ -1,0 +1,134 @@
+"""GPU adjoint (mono_forward_taped / mono_backward) against the FP64 oracle
+adjoint, which is itself pinned by finite differences (test_adjoint_cpu.py).
+
+The GPU replays the oracle's k-trace so both differentiate the same
+piecewise-smooth map.  Tolerances: FP64 loss 1e-10 relative; gradients
+1e-8 of their largest magnitude.  FP32 against the FP64 oracle: cosine
+similarity >= 0.999 and relative L2 error <= 1e-2 (the stated reporting
+targets for the FP32 adjoint).
+"""
+import numpy as np
+import pytest
+
+from paper_2011_04747_amd import mono
+from paper_2011_04747_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    T.cuda.set_device(0)
+    return T
+
+
+def _problem(kind):
+    rng = np.random.default_rng(3)
+    if kind == "ms":
+        w = W.cable_ms(n_nodes=301, length=3.0, t_end=40.0)
+        w.sensors = np.sort(rng.choice(w.mesh.n_nodes, 40, replace=False)).astype(np.int32)
+        base = 0.0
+    elif kind == "tp06":
+        w = W.adjoint_slab(shape=(23, 19, 7), t_end=12.0, n_sensors=64)
+        base = -80.0
+    else:
+        w = W.batched_sheets(n_inst=4, side_lo=15, side_hi=33, t_end=10.0)
+        w.sensors = np.sort(rng.choice(w.mesh.n_nodes, 60, replace=False)).astype(np.int32)
+        base = -80.0
+    n = w.mesh.n_nodes
+    if w.mesh.sigma is None:
+        w.mesh.sigma = np.exp(0.1 * rng.standard_normal(n))
+    target = base + rng.uniform(-0.2, 0.2, (w.n_steps, len(w.sensors)))
+    return w, target
+
+
+def _oracle_grad(w, target):
+    from oracle.oracle import Oracle
+    o = Oracle.from_workload(w)
+    kt, _ = o.record_k(w.n_steps)
+    o.set_target(w.sensors, target)
+    L = o.forward_taped(w.n_steps, w.dt)
+    gs, gp = o.backward()
+    return L, gs, gp, kt
+
+
+def _gpu_grad(torch, w, target, kt, prec, ckpt):
+    s = mono.Sim.from_workload(w, prec)
+    rep = torch.from_numpy(np.ascontiguousarray(kt)).cuda()
+    s.ktrace(2, None, rep.data_ptr(), kt.shape[0], 0)
+    s.set_sensors(w.sensors, target)
+    L = s.forward_taped(w.n_steps, w.dt, ckpt)
+    gs, gp = s.backward()
+    torch.cuda.synchronize()
+    return L, gs, gp, s
+
+
+@pytest.mark.parametrize("kind", ["ms", "tp06", "batched"])
+def test_adjoint_fp64_matches_oracle(torch, kind):
+    w, target = _problem(kind)
+    Lo, gso, gpo, kt = _oracle_grad(w, target)
+    Lg, gsg, gpg, s = _gpu_grad(torch, w, target, kt, "f64", 7)
+    assert Lg == pytest.approx(Lo, rel=1e-10)
+    assert np.abs(gsg - gso).max() <= 1e-8 * np.abs(gso).max()
+    assert np.abs(gpg - gpo).max() <= 1e-8 * np.abs(gpo).max()
+    # the state after backward is the state after the taped run
+    o_end = s.get(mono.FIELD_V)
+    s2 = mono.Sim.from_workload(w, "f64")
+    rep = torch.from_numpy(np.ascontiguousarray(kt)).cuda()
+    s2.ktrace(2, None, rep.data_ptr(), kt.shape[0], 0)
+    s2.step(w.n_steps, w.dt)
+    assert (s2.get(mono.FIELD_V) == o_end).all()
+
+
+def test_adjoint_checkpoint_interval_does_not_change_gradients(torch):
+    w, target = _problem("tp06")
+    from oracle.oracle import Oracle
+    o = Oracle.from_workload(w)
+    kt, _ = o.record_k(w.n_steps)
+    o.step(w.n_steps, w.dt)
+    ref = None
+    for ck in (1, 7, 50, 1000):
+        L, gs, gp, _ = _gpu_grad(torch, w, target, kt, "f32", ck)
+        if ref is None:
+            ref = (L, gs, gp)
+        else:
+            assert L == ref[0] and (gs == ref[1]).all() and (gp == ref[2]).all()
+
+
+@pytest.mark.parametrize("kind", ["tp06", "batched"])
+def test_adjoint_fp32_against_fp64_oracle(torch, kind):
+    w, target = _problem(kind)
+    Lo, gso, gpo, kt = _oracle_grad(w, target)
+    Lg, gsg, gpg, _ = _gpu_grad(torch, w, target, kt, "f32", 50)
+    cos = np.dot(gsg, gso) / (np.linalg.norm(gsg) * np.linalg.norm(gso))
+    rel = np.linalg.norm(gsg - gso) / np.linalg.norm(gso)
+    assert cos >= 0.999 and rel <= 1e-2, (cos, rel)
+    relp = np.abs(gpg[1:] - gpo[1:]) / np.abs(gpo[1:]).max()
+    assert relp.max() <= 1e-2, relp
+    assert Lg == pytest.approx(Lo, rel=1e-3)
+
+
+def test_autograd_function(torch):
+    from paper_2011_04747_amd.adjoint import TP06_SCALING_ROWS, AdjointProblem, mono_adjoint_fn
+    w, target = _problem("tp06")
+    c = np.array([1.0, 1.1, 0.9, 1.0, 1.05])
+    # the oracle on the same problem with the conductance rows scaled by c
+    wo, _ = _problem("tp06")
+    for r, cr in zip(TP06_SCALING_ROWS, c):
+        wo.params[r] *= cr
+    Lo, gso, gpo, kt = _oracle_grad(wo, target)
+    rep = torch.from_numpy(np.ascontiguousarray(kt)).cuda()
+    prob = AdjointProblem(w, target, w.n_steps, ckpt_every=10, precision="f64", replay_k=rep)
+    sigma = torch.tensor(w.mesh.sigma, dtype=torch.float64, device="cuda", requires_grad=True)
+    scal = torch.tensor(c, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = mono_adjoint_fn().apply(sigma, scal, prob)
+    assert loss.item() == pytest.approx(Lo, rel=1e-10)
+    loss.backward()
+    gs = sigma.grad.cpu().numpy()
+    assert np.abs(gs - gso).max() <= 1e-8 * np.abs(gso).max()
+    want = np.array([gpo[r] / cr for r, cr in zip(TP06_SCALING_ROWS, c)])
+    got = scal.grad.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
