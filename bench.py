@@ -70,6 +70,75 @@ def cpu_baseline(w, steps):
                       f"from t=0 (assembly excluded), {el:.1f} s"}
 
 
+def adjoint_leg(stream, with_accuracy):
+    """Adjoint/forward wall-time ratio on the 3D adjoint slab (101x101x26,
+    512 sensors, loss over 300 ms, checkpoints every 50 steps, FP32)."""
+    import torch
+    from paper_2011_04747_amd import mono
+    from paper_2011_04747_amd import workloads as W
+    w = W.adjoint_slab(precision="f32")
+    n_steps = w.n_steps
+    ns = len(w.sensors)
+    ck = w.extra["ckpt_every"]
+    # synthetic measurements: the same tissue with the perturbed conductivity
+    mt = W.Mesh(w.mesh.dim, w.mesh.xyz, w.mesh.etype, w.mesh.conn, w.mesh.D_elem,
+                w.extra["sigma_target"])
+    wt = W.Workload(w.name, mt, w.model, w.params, w.stimuli, w.dt, w.t_end, w.dt0, "f32",
+                    w.lat_threshold)
+    st = mono.Sim.from_workload(wt, "f32", stream=stream.cuda_stream)
+    st.set_sensors(w.sensors, np.zeros((0, ns)))
+    target = st.sample_sensors(n_steps, w.dt, ns)
+    st.close()
+
+    def run(prec, taped, ktrace=None):
+        s = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream)
+        s.set_sensors(w.sensors, target)
+        if ktrace is not None:
+            mode, buf = ktrace
+            if mode == 1:
+                s.ktrace(1, buf.data_ptr(), None, n_steps, 0)
+            else:
+                s.ktrace(2, None, buf.data_ptr(), n_steps, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if not taped:
+            s.step(n_steps, w.dt)
+            s.sync()
+            out = (time.perf_counter() - t0, None)
+        else:
+            loss = s.forward_taped(n_steps, w.dt, ck)
+            t1 = time.perf_counter()
+            gs, gp = s.backward()
+            t2 = time.perf_counter()
+            out = (t1 - t0, t2 - t1, loss, gs, gp)
+        s.close()
+        return out
+
+    run("f32", False)                      # warm-up (graph capture, code load)
+    t_fwd = run("f32", False)[0]
+    t_tf, t_bw, loss, gs, gp = run("f32", True)
+    res = {"workload": f"adjoint_tp06_3d 101x101x26 ({w.mesh.n_nodes} nodes), {ns} sensors, "
+                       f"{n_steps} steps, checkpoint every {ck}, FP32",
+           "forward_s": t_fwd, "taped_forward_s": t_tf, "backward_s": t_bw,
+           "adjoint_over_forward": (t_tf + t_bw) / t_fwd, "loss": loss,
+           "grad_sigma_l2": float(np.linalg.norm(gs)),
+           "grad_scalings": {k: float(gp[i]) for i, k in
+                             enumerate(("gNa", "gCaL", "gKr", "gKs", "gK1"), start=1)}}
+    if with_accuracy:
+        # same k decisions in both precisions: record the FP32 run's, replay in FP64
+        kt = torch.zeros((n_steps, w.mesh.n_nodes), dtype=torch.uint8, device="cuda")
+        _, _, loss, gs, gp = run("f32", True, (1, kt))
+        _, _, loss64, gs64, gp64 = run("f64", True, (2, kt))
+        del kt
+        res["fp32_vs_fp64"] = {
+            "note": "FP64 adjoint of the same kernels replaying the FP32 run's k decisions",
+            "grad_sigma_cosine": float(np.dot(gs, gs64) / (np.linalg.norm(gs) * np.linalg.norm(gs64))),
+            "grad_sigma_rel_l2": float(np.linalg.norm(gs - gs64) / np.linalg.norm(gs64)),
+            "grad_scalings_max_rel": float(np.max(np.abs(gp[1:] - gp64[1:]) / np.abs(gp64[1:]).max())),
+            "loss_rel": float(abs(loss - loss64) / loss64)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +150,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -204,6 +274,10 @@ def main():
                     "lat_max_ms": float(np.abs(l32 - l64)[both].max()) if both.any() else None,
                     "activated_equal": bool(((l32 > 0) == (l64 > 0)).all())}
 
+    adjoint = None
+    if not args.no_adjoint and args.workload == "slab":
+        adjoint = adjoint_leg(stream, not args.no_accuracy)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_steps)
@@ -222,7 +296,7 @@ def main():
            "roofline": roofline,
            "kernels": {"diffusion": diff_roof, "reaction": react_roof,
                        "ms_per_step": {"diffusion": diff_total, "reaction": react_total}},
-           "accuracy": accuracy, "cpu_baseline": cpu}
+           "accuracy": accuracy, "adjoint": adjoint, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

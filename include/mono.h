@@ -248,6 +248,12 @@ mono_status mono_apply_phase(mono_sim *sim, int32_t phase, int64_t step, int32_t
 mono_status mono_set_sensors(mono_sim *sim, int32_t n, const int32_t *nodes, const double *target,
                              int64_t n_steps);
 
+/* Advance n_steps outer steps like mono_step (kernels launched one by one)
+ * and copy V at the sensors at reaction entry of every step to host out
+ * (n_steps x sensors, FP64): synthetic measurements for a loss target.
+ * Synchronising; the targets given with the sensors are not used. */
+mono_status mono_sample_sensors(mono_sim *sim, int64_t n_steps, double dt, double *out);
+
 /* Advance n_steps outer steps from the current time level like mono_step,
  * keeping a snapshot of the state every ckpt_every steps (uniform
  * checkpointing: memory ~ (n_steps/ckpt_every) states plus a ckpt_every-step

@@ -33,6 +33,14 @@ __global__ __launch_bounds__(256) void k_sensor_loss(const T* V, const int32_t* 
   if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
 }
 
+// out[q] = V[sensor_q] (FP64)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sensor_sample(const T* V, const int32_t* sens, int ns,
+                                                       double* out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q < ns) out[q] = (double)V[sens[q]];
+}
+
 // lam_V[sensor_q] += 2 (V_entry[sensor_q] - target_q)   (sensors are distinct)
 template <typename T>
 __global__ __launch_bounds__(256) void k_sensor_inject(T* lamV, const T* V, const int32_t* sens,
@@ -213,6 +221,15 @@ void launch_sensor_inject(T* lamV, const T* V, const int32_t* sens, int ns, cons
                      ns, target);
 }
 
+template <typename T>
+void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, hipStream_t s) {
+  if (ns <= 0) return;
+  hipLaunchKernelGGL((k_sensor_sample<T>), dim3((ns + 255) / 256), dim3(256), 0, s, V, sens, ns,
+                     out);
+}
+template void launch_sensor_sample<float>(const float*, const int32_t*, int, double*, hipStream_t);
+template void launch_sensor_sample<double>(const double*, const int32_t*, int, double*,
+                                           hipStream_t);
 template void launch_adj_diffusion<float>(int, const AdjDiffArgs<float>&, hipStream_t);
 template void launch_adj_diffusion<double>(int, const AdjDiffArgs<double>&, hipStream_t);
 template void launch_adj_ionic<float>(int, const AdjIonArgs<float>&, hipStream_t);

@@ -178,6 +178,8 @@ template <typename T>
 void launch_sensor_loss(const T* V, const int32_t* sens, int ns, const double* target,
                         double* out, hipStream_t s);
 template <typename T>
+void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, hipStream_t s);
+template <typename T>
 void launch_sensor_inject(T* lamV, const T* V, const int32_t* sens, int ns, const double* target,
                           hipStream_t s);
 

@@ -456,7 +456,8 @@ hipError_t load_state(mono_sim* s, const void* src) {
 // entry (loss_slot).
 template <typename T>
 void enqueue_taped_step(mono_sim* s, int64_t g, int64_t step, T* vsub, T* entry, uint8_t* krec,
-                        int64_t krec_base, int64_t krec_steps, double* loss_slot) {
+                        int64_t krec_base, int64_t krec_steps, double* loss_slot,
+                        double* sample = nullptr) {
   const int L = s->l_max;
   const size_t b = s->Np * s->es;
   for (int m = 0; m < L; ++m) {
@@ -475,6 +476,7 @@ void enqueue_taped_step(mono_sim* s, int64_t g, int64_t step, T* vsub, T* entry,
   if (loss_slot && s->ns > 0 && step < s->target_steps)
     launch_sensor_loss<T>(Vmid, s->d_sens, s->ns, s->d_target + step * s->ns, loss_slot,
                           s->stream);
+  if (sample) launch_sensor_sample<T>(Vmid, s->d_sens, s->ns, sample, s->stream);
   IonArgs<T> ia = ion_args<T>(s, Vmid, g);
   if (krec) {
     ia.kt.mode |= 1;
@@ -600,6 +602,14 @@ mono_status backward_t(mono_sim* s) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->step = endstep;
   return MONO_OK;
+}
+
+template <typename T>
+void sample_steps(mono_sim* s, int64_t n_steps, double* dbuf) {
+  for (int64_t t = 0; t < n_steps; ++t)
+    enqueue_taped_step<T>(s, t, s->step + t, nullptr, nullptr, nullptr, 0, 0, nullptr,
+                          dbuf + t * s->ns);
+  launch_advance_clock(s->d_base, n_steps, s->stream);
 }
 
 }  // namespace
@@ -1160,6 +1170,30 @@ mono_status mono_set_sensors(mono_sim* s, int32_t n, const int32_t* nodes, const
       HIP_TRY(hipMemcpy(s->d_target, target, (size_t)n * n_steps * 8, hipMemcpyHostToDevice));
   }
   return MONO_OK;
+}
+
+mono_status mono_sample_sensors(mono_sim* s, int64_t n_steps, double dt, double* out) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (n_steps < 0 || (n_steps > 0 && !out)) return fail(MONO_EINVAL, "bad argument");
+  if (s->ns <= 0) return fail(MONO_ESTATE, "no sensors set");
+  if (s->latched) return fail(MONO_ESTATE, "simulation latched after a non-finite potential");
+  st = prepare(s, dt);
+  if (st != MONO_OK) return st;
+  double* dbuf = nullptr;
+  if (dalloc(&dbuf, (size_t)std::max<int64_t>(n_steps, 1) * s->ns))
+    return fail(MONO_ENOMEM, "device allocation failed");
+  if (s->prec == MONO_F64)
+    sample_steps<double>(s, n_steps, dbuf);
+  else
+    sample_steps<float>(s, n_steps, dbuf);
+  hipError_t e = hipGetLastError();
+  if (!e) e = hipMemcpyAsync(out, dbuf, (size_t)n_steps * s->ns * 8, hipMemcpyDeviceToHost, s->stream);
+  if (!e) e = hipStreamSynchronize(s->stream);
+  dfree(dbuf);
+  if (e) return fail(MONO_EDEVICE, hipGetErrorString(e));
+  s->step += n_steps;
+  return check_flag(s);
 }
 
 mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t ckpt_every,

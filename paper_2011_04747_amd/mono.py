@@ -35,7 +35,7 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
            "mono_model_flops", "mono_set_launch", "mono_get_launch",
            "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
-           "mono_forward_taped", "mono_backward")
+           "mono_forward_taped", "mono_backward", "mono_sample_sensors")
 
 
 class MonoError(RuntimeError):
@@ -107,6 +107,7 @@ def lib():
             "mono_set_sensors": [vp, i32, vp, vp, i64],
             "mono_forward_taped": [vp, i64, dbl, i32, vp],
             "mono_backward": [vp, vp, vp],
+            "mono_sample_sensors": [vp, i64, dbl, vp],
             "mono_set_launch": [vp, C.POINTER(Launch)],
             "mono_get_launch": [vp, C.POINTER(Launch)],
         }
@@ -288,6 +289,12 @@ class Sim:
         t = _c(target, np.float64)
         _check(lib().mono_set_sensors(self.h, len(nodes), nodes.ctypes.data, t.ctypes.data,
                                       t.shape[0]))
+
+    def sample_sensors(self, n_steps, dt, n_sensors):
+        """Step and return V at the sensors at reaction entry (n_steps x n_sensors)."""
+        out = np.zeros((int(n_steps), int(n_sensors)))
+        _check(lib().mono_sample_sensors(self.h, int(n_steps), float(dt), out.ctypes.data))
+        return out
 
     def forward_taped(self, n_steps, dt, ckpt_every=50):
         out = np.zeros(1)
