@@ -127,6 +127,8 @@ typedef struct {
   int32_t n_instances;
   int32_t n_states;
   int32_t ell_width;  /* ELL slots per row, or stencil offsets per instance    */
+  int32_t row_classes; /* distinct stencil rows of a single instance when the
+                          diffusion can read rows by class, else 0             */
 } mono_info;
 
 /* Assemble K and the row-sum lumped mass M_L of the FE diffusion problem
@@ -192,18 +194,27 @@ mono_status mono_get_info(mono_sim *sim, int32_t inst, mono_info *out);
  * and check dt_ad < 2/lambda_est for the last prepared dt. */
 mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
 
-/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32).  Block sizes
- * 128, 256 or 512 lanes; rows per lane of the stencil diffusion kernel 1, 2
- * or 4 (FP64: 1 or 2; ignored by the ELL layout); XCD remap 0/1 (deal
+/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32, 0, 1).  Block
+ * sizes 128, 256 or 512 lanes (the FP32 reaction also 1024); rows per lane of the stencil diffusion kernel
+ * 1, 2 or 4 (FP64: 1 or 2; ignored by the ELL layout); XCD remap 0/1 (deal
  * contiguous row ranges to each of the 8 XCDs); graph_steps 1..8192 outer
- * steps per captured HIP graph (a whole run can be one graph).  Results do
- * not depend on the shape (bitwise). */
+ * steps per captured HIP graph (a whole run can be one graph); react_sort
+ * 0/1: every reaction workgroup first decides the k of all its nodes and
+ * orders them by k in LDS, so that a wavefront runs one substep count where
+ * it can; diff_classes 0/1 (default 1): where mono_info.row_classes > 0 the
+ * stencil diffusion reads each row's weights and 1/m from a table of the
+ * distinct rows through a 2-byte class id instead of per-row arrays, and
+ * rows per lane (1, 2, 4, 8 or 16, any precision) count the rows each lane
+ * sweeps in turn.
+ * Results do not depend on the shape (bitwise). */
 typedef struct {
   int32_t diff_block;
   int32_t diff_rows_per_lane;
   int32_t diff_xcd_remap;
   int32_t react_block;
   int32_t graph_steps;
+  int32_t react_sort;
+  int32_t diff_classes;
 } mono_launch;
 mono_status mono_set_launch(mono_sim *sim, const mono_launch *cfg);
 mono_status mono_get_launch(mono_sim *sim, mono_launch *out);

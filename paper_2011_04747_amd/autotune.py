@@ -2,8 +2,10 @@
 
 Searches, on the simulation it is given and at its current state:
   * diffusion kernel: workgroup size (128/256/512), stencil rows per lane
-    (1/2/4; vector loads of the streamed arrays) and the XCD row remap;
-  * reaction kernel: workgroup size;
+    (1/2/4; vector loads of the streamed arrays) or rows read by class, and
+    the XCD row remap;
+  * reaction kernel: workgroup size, and whether each workgroup orders its
+    nodes by substep count k before advancing them;
   * outer steps per captured HIP graph.
 Kernel candidates are timed with the library's per-kernel HIP events
 (MONO_STEP_TIMED), graph sizes by the wall time of whole steps.  The state is
@@ -84,24 +86,39 @@ def tune(sim: mono.Sim, dt: float, steps: int = 8, use_cache: bool = True,
     best_d, best_r = None, None
     _restore(sim, snap)
     _time_kernels(sim, dt, steps)            # warm caches and clocks first
+    # stencil rows by class (one RPL) or per-row arrays (RPL 1/2/4)
+    shapes = [(0, rpl) for rpl in rpls]
+    if info["row_classes"] > 0:
+        shapes.append((1, 1))
     for blk in (128, 256, 512):
-        for rpl in rpls:
+        for cls, rpl in shapes:
             for xcd in (0, 1):
                 sim.set_launch(diff_block=blk, diff_rows_per_lane=rpl, diff_xcd_remap=xcd,
-                               react_block=blk)
+                               diff_classes=cls, react_block=blk, react_sort=0)
                 _restore(sim, snap)
                 d, r = _time_kernels(sim, dt, steps)
-                trials.append({"diff_block": blk, "rpl": rpl, "xcd": xcd, "diff_ms": d,
-                               "react_block": blk, "react_ms": r})
+                trials.append({"diff_block": blk, "classes": cls, "rpl": rpl, "xcd": xcd,
+                               "diff_ms": d, "react_block": blk, "react_ms": r})
                 if verbose:
                     print("tune", trials[-1], flush=True)
                 if best_d is None or d < best_d[0]:
-                    best_d = (d, blk, rpl, xcd)
+                    best_d = (d, blk, rpl, xcd, cls)
                 if best_r is None or r < best_r[0]:
                     best_r = (r, blk)
     best = dict(base)
     best.update(diff_block=best_d[1], diff_rows_per_lane=best_d[2], diff_xcd_remap=best_d[3],
-                react_block=best_r[1])
+                diff_classes=best_d[4], react_block=best_r[1], react_sort=0)
+    sort_blocks = (256, 512, 1024) if sim.precision == "f32" else (256, 512)
+    for blk in sort_blocks:
+        sim.set_launch(**dict(best, react_block=blk, react_sort=1))
+        _restore(sim, snap)
+        _, r = _time_kernels(sim, dt, steps)
+        trials.append({"react_block": blk, "react_sort": 1, "react_ms": r})
+        if verbose:
+            print("tune", trials[-1], flush=True)
+        if r < best_r[0]:
+            best_r = (r, blk)
+            best.update(react_block=blk, react_sort=1)
     # graph size: wall time of the same steps from the same state (the cost of
     # a step depends on the simulation phase, so every candidate runs the
     # same window)

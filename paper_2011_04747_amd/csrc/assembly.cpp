@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <unordered_map>
 
 #include "mono_internal.h"
 
@@ -151,11 +153,17 @@ int assemble_fe(const mono_mesh_desc* d, HostCSR& K, std::string& err) {
     double Ke[8][8] = {{0}};
     double me[8] = {0};
     for (int q = 0; q < t.nq; ++q) {
+      // Jacobian from coordinates relative to the element's first node (the
+      // shape-function derivatives sum to zero, so J is unchanged): elements
+      // of the same shape then give bitwise the same matrices wherever they
+      // sit, which lets the stencil rows of structured meshes repeat exactly.
       double J[3][3] = {{0}};
       for (int k = 0; k < dim; ++k)
         for (int c = 0; c < dim; ++c) {
+          const double x0 = d->xyz[(int64_t)en[0] * dim + c];
           double s = 0.0;
-          for (int a = 0; a < nen; ++a) s += t.dN[q][a][k] * d->xyz[(int64_t)en[a] * dim + c];
+          for (int a = 1; a < nen; ++a)
+            s += t.dN[q][a][k] * (d->xyz[(int64_t)en[a] * dim + c] - x0);
           J[k][c] = s;
         }
       double B[3][8];
@@ -276,6 +284,46 @@ bool build_stencil(const HostCSR& K, const std::vector<int64_t>& inst_off, int64
       }
     }
   }
+  return true;
+}
+
+bool build_row_classes(const StencilHost& sh, int64_t n, int64_t Np, bool fp32,
+                       int max_classes, RowClasses& out) {
+  if ((int64_t)sh.off.size() != (int64_t)sh.P) return false;   // one instance only
+  const int P = sh.P;
+  const int tw = (2 * P + 1 + 1) & ~1;
+  std::unordered_map<std::string, int> ids;
+  std::vector<uint16_t> cls(Np, 0);
+  std::vector<double> table;
+  std::vector<double> row(tw);
+  std::string key(tw * sizeof(double), '\0');
+  const int64_t cap = std::min<int64_t>(max_classes, std::max<int64_t>(Np / 8, 1));
+  for (int64_t i = 0; i < Np; ++i) {
+    std::fill(row.begin(), row.end(), 0.0);
+    for (int p = 0; p < P; ++p) {
+      const int64_t jb = i - sh.off[p];
+      row[p] = sh.e[(size_t)p * Np + i];
+      row[P + p] = (jb >= 0 && i < n) ? sh.e[(size_t)p * Np + jb] : 0.0;
+    }
+    row[2 * P] = sh.minv[i];
+    if (fp32)
+      for (double& v : row) v = (double)(float)v;
+    std::memcpy(&key[0], row.data(), key.size());
+    auto it = ids.find(key);
+    if (it == ids.end()) {
+      const int id = (int)ids.size();
+      if (id >= cap) return false;
+      ids.emplace(key, id);
+      table.insert(table.end(), row.begin(), row.end());
+      cls[i] = (uint16_t)id;
+    } else {
+      cls[i] = (uint16_t)it->second;
+    }
+  }
+  out.tw = tw;
+  out.n_classes = (int)ids.size();
+  out.cls.swap(cls);
+  out.table.swap(table);
   return true;
 }
 

@@ -13,6 +13,8 @@
 // receive workgroups round-robin) works on one contiguous slice of rows: the
 // neighbour rows a stencil reaches (up to one plane away) then stay in that
 // XCD's L2.
+#include <type_traits>
+
 #include "mono_internal.h"
 
 namespace mono {
@@ -63,8 +65,8 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[R]) {
   }
 }
 
-__device__ __forceinline__ double tmul(double a, double b) { return __dmul_rn(a, b); }
-__device__ __forceinline__ double tadd(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ double tmul(double a, double b) { return rn_mul(a, b); }
+__device__ __forceinline__ double tadd(double a, double b) { return rn_add(a, b); }
 
 // Start time of this substep, evaluated exactly as t_n (+ dt/2) + m dt_ad
 // with one rounding per operation (no contraction), so that stimulus windows
@@ -183,6 +185,114 @@ __global__ __launch_bounds__(BLOCK) void k_diff_stencil(DiffArgs<T> a) {
   vstore<RPL>(a.Vout + i0, out);
 }
 
+// The stencil sweep of a single instance whose rows are stored by class:
+// row i reads only V, its class id and (through the class) a table row that
+// the rows of a wavefront usually share, so HBM carries V in, V out and 2
+// bytes per row.  Where every lane of a wavefront has the same class the
+// table row is read through scalar loads.  Same arithmetic, in the same order,
+// as k_diff_stencil with RPL = 1.
+template <typename T>
+__device__ __forceinline__ T ld_bytes(const T* base, uint32_t byte_off) {
+  return *(const T*)((const char*)base + byte_off);
+}
+
+// Workgroup w sweeps ITER chunks of BLOCK consecutive rows, so the uniform
+// work of a wavefront (arguments, substep time, open stimulus windows) is paid
+// once per ITER rows.
+template <typename T, int P, int BLOCK, int ITER>
+__global__ __launch_bounds__(BLOCK) void k_diff_classes(DiffArgs<T> a) {
+  constexpr int ES = (int)sizeof(T);
+  const int64_t nb = (a.n + (int64_t)BLOCK * ITER - 1) / ((int64_t)BLOCK * ITER);
+  const int64_t r0 = row_block(nb, a.xcd) * BLOCK * ITER;
+  const int np = P > 0 ? P : a.P;
+  const int n = (int)a.n;
+  const int blast = (n - 1) * ES;
+  const int maxo = a.off[np - 1];
+  const T* V = a.Vin;
+  const double dt_ad = a.dt_ad[0];
+  const T hT = (T)dt_ad;
+  const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
+  uint32_t active = 0;
+  if (a.stim_mask)
+    for (int q = 0; q < a.stim.n; ++q)
+      if (a.stim.t_on[q] <= tau && tau < a.stim.t_end[q]) active |= 1u << q;
+  using Clamp = std::integral_constant<bool, true>;
+  using NoClamp = std::integral_constant<bool, false>;
+  for (int it = 0; it < ITER; ++it) {
+    // rows addressed by 32-bit byte offsets from uniform bases (the host
+    // takes this kernel only when n * sizeof(T) < 2^31)
+    const int i = (int)(r0 + it * BLOCK) + (int)threadIdx.x;
+    if (i >= n) break;
+    const int bi = i * ES;
+    const T vi = ld_bytes(V, (uint32_t)bi);
+    const int c = a.cls[(uint32_t)i];
+    const int c0 = __builtin_amdgcn_readfirstlane(c);
+    // a wavefront whose rows all have every neighbour in range skips the clamps
+    const bool inner = __ballot(i < maxo || i > n - 1 - maxo) == 0ull;
+    T acc = T(0), mv;
+    auto sweep = [&](const T* w, auto clamp) {
+      auto edge = [&](int p) {
+        const int bo = a.off[p] * ES;
+        int bf = bi + bo, bb = bi - bo;
+        if constexpr (decltype(clamp)::value) {
+          bf = min(bf, blast);
+          bb = max(bb, 0);
+        }
+        const T vf = ld_bytes(V, (uint32_t)bf);
+        const T vb = ld_bytes(V, (uint32_t)bb);
+        acc += w[p] * (vf - vi);
+        acc += w[np + p] * (vb - vi);
+      };
+      if constexpr (P > 0) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) edge(p);
+      } else {
+        for (int p = 0; p < np; ++p) edge(p);
+      }
+      mv = w[2 * np];
+    };
+    if (__ballot(c != c0) == 0ull) {
+      const T* w = a.ctab + (uint32_t)(c0 * a.tw);
+      if (inner)
+        sweep(w, NoClamp{});
+      else
+        sweep(w, Clamp{});
+    } else {
+      sweep(a.ctab + (uint32_t)(c * a.tw), Clamp{});
+    }
+    T sr = T(0);
+    if (active) {
+      const uint32_t mask = a.stim_mask[(uint32_t)i] & active;
+      for (int q = 0; q < a.stim.n; ++q)
+        if (mask & (1u << q)) sr += (T)a.stim.amp[q];
+    }
+    *(T*)((char*)a.Vout + (uint32_t)bi) = vi + hT * (mv * acc + sr);
+  }
+}
+
+template <typename T, int P, int BLOCK, int ITER>
+static void launch_classes_k(const DiffArgs<T>& a, hipStream_t s) {
+  const int64_t per = (int64_t)BLOCK * ITER;
+  const dim3 grid((unsigned)((a.n + per - 1) / per));
+  hipLaunchKernelGGL((k_diff_classes<T, P, BLOCK, ITER>), grid, dim3(BLOCK), 0, s, a);
+}
+template <typename T, int P, int BLOCK>
+static void launch_classes_i(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  switch (c.diff_rpl) {
+    case 2: return launch_classes_k<T, P, BLOCK, 2>(a, s);
+    case 4: return launch_classes_k<T, P, BLOCK, 4>(a, s);
+    case 8: return launch_classes_k<T, P, BLOCK, 8>(a, s);
+    case 16: return launch_classes_k<T, P, BLOCK, 16>(a, s);
+    default: return launch_classes_k<T, P, BLOCK, 1>(a, s);
+  }
+}
+template <typename T, int P>
+static void launch_classes_b(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (c.diff_block == 128) return launch_classes_i<T, P, 128>(a, c, s);
+  if (c.diff_block == 512) return launch_classes_i<T, P, 512>(a, c, s);
+  launch_classes_i<T, P, 256>(a, c, s);
+}
+
 template <typename T, int P, bool BATCHED, int BLOCK, int RPL>
 static void launch_stencil_k(const DiffArgs<T>& a, hipStream_t s) {
   const int64_t nlanes = (a.n + RPL - 1) / RPL;
@@ -234,6 +344,15 @@ void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipS
       launch_ell_b<T, true>(a, c, s);
     else
       launch_ell_b<T, false>(a, c, s);
+    return;
+  }
+  if (a.cls && !a.inst && c.diff_classes && a.n * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+    switch (a.P) {
+      case 1: launch_classes_b<T, 1>(a, c, s); break;
+      case 4: launch_classes_b<T, 4>(a, c, s); break;
+      case 13: launch_classes_b<T, 13>(a, c, s); break;
+      default: launch_classes_b<T, 0>(a, c, s); break;
+    }
     return;
   }
   switch (a.P) {

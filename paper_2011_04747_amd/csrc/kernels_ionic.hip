@@ -6,8 +6,9 @@
 //
 // One node per lane with the whole cell state in registers; states,
 // parameters and V are structure-of-arrays so every load and store of a
-// wavefront is one contiguous 256 B (FP32) or 512 B (FP64) segment.  A
-// wavefront runs as many substeps as its largest k.  The activation time of
+// wavefront is one contiguous 256 B (FP32) or 512 B (FP64) segment (or, with
+// the nodes of a workgroup ordered by k, falls inside the workgroup's own
+// segment).  The activation time of
 // a node (first upward crossing of a threshold between the V samples taken at
 // reaction entry, linearly interpolated) is kept in FP64 in every precision.
 #include "cell_models.h"
@@ -27,51 +28,86 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-template <typename T, class M, int BLOCK>
+// The substep count of node i at outer step `step`, with the bookkeeping that
+// goes with reaction entry: non-finite check, activation time, V_prev, k-trace
+// record/replay and the stored k.  y/p are needed only for dvdt_src = 1.
+template <typename T, class M>
+__device__ __forceinline__ int decide_k(const IonArgs<T>& a, int64_t i, int64_t step, T Vb,
+                                        const T* y, const T* p) {
+  const double dt = a.clk.dt;
+  if (!isfinite(Vb)) atomicOr(a.flag, 1);
+  const T vp = a.vprev[i];
+  // dV/dt that drives the substep count
+  T d;
+  if (a.dvdt_src == 0)
+    d = (step == 0) ? T(0) : (Vb - vp) / (T)dt;
+  else
+    d = M::vrate(y, p);
+  // activation time: first upward crossing between reaction-entry samples
+  if (step > 0) {
+    const double thr = a.lat_thr, v0 = (double)vp, v1 = (double)Vb;
+    if (v0 < thr && v1 >= thr && a.lat[i] < 0.0) {
+      const double w = (thr - v0) / (v1 - v0);
+      const double tA = rn_add(rn_mul((double)step, dt), rn_mul(0.5, dt));
+      a.lat[i] = rn_add(rn_add(tA, -dt), rn_mul(w, dt));
+    }
+  }
+  a.vprev[i] = Vb;
+  // k = min(k0 + floor|d|, k_max), k0 = 5 for d > 0 else 1
+  const T kd = (d > T(0) ? T(5) : T(1)) + xfloor(fabs(d));
+  int k = (kd <= (T)a.k_max) ? (int)kd : a.k_max;
+  if (a.kt.mode & 1) {
+    const int64_t r = step - a.kt.rec_base;
+    if (r >= 0 && r < a.kt.rec_steps) a.kt.rec[r * a.n + i] = (uint8_t)k;
+  }
+  if (a.kt.mode & 2) {
+    const int64_t r = step - a.kt.rep_base;
+    if (r >= 0 && r < a.kt.rep_steps) k = a.kt.rep[r * a.n + i];
+  }
+  a.lastk[i] = (uint8_t)k;
+  return k;
+}
+
+template <typename T, class M>
+__device__ __forceinline__ void load_cell(const IonArgs<T>& a, int64_t i, T* y, T* p) {
+  y[0] = a.V[i];
+  for (int s = 1; s < M::S; ++s) y[s] = a.st[(int64_t)(s - 1) * a.Np + i];
+  for (int q = 0; q < M::P; ++q)
+    p[q] = (a.par_pernode >> q & 1u) ? a.par[(int64_t)q * a.Np + i] : a.par_uniform[q];
+}
+
+template <typename T, class M>
+__device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t i, T* y, const T* p,
+                                             int k) {
+  const T h = (T)(a.clk.dt / (double)k);
+  const bool clamp = a.vclamp != 0;
+  for (int s = 0; s < k; ++s) M::substep(y, p, h, clamp);
+  a.V[i] = y[0];
+  for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
+}
+
+// One node per lane.  SORT = false: the lane that decides node i's k advances
+// node i, so a wavefront runs as many substeps as its largest k.  SORT = true:
+// the workgroup first decides the k of all its nodes, orders them by k in LDS
+// (a stable counting sort over k = 0..kSortMaxK, larger k sharing the last
+// key), and lane t then advances the t-th node of that order, so a wavefront
+// mixes substep counts only where two keys meet.  Each node's arithmetic is
+// the same either way, so both give the same bits.
+template <typename T, class M, int BLOCK, bool SORT>
 __global__ __launch_bounds__(BLOCK) void k_ionic(IonArgs<T> a) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool live = i < a.n;
   const int64_t step = *a.clk.base + a.clk.g;
-  const double dt = a.clk.dt;
   int k = 0;
   T y[M::S];
   T p[M::P];
   if (live) {
-    y[0] = a.V[i];
-    for (int s = 1; s < M::S; ++s) y[s] = a.st[(int64_t)(s - 1) * a.Np + i];
-    for (int q = 0; q < M::P; ++q)
-      p[q] = (a.par_pernode >> q & 1u) ? a.par[(int64_t)q * a.Np + i] : a.par_uniform[q];
-    const T Vb = y[0];
-    if (!isfinite(Vb)) atomicOr(a.flag, 1);
-    const T vp = a.vprev[i];
-    // dV/dt that drives the substep count
-    T d;
-    if (a.dvdt_src == 0)
-      d = (step == 0) ? T(0) : (Vb - vp) / (T)dt;
-    else
-      d = M::vrate(y, p);
-    // activation time: first upward crossing between reaction-entry samples
-    if (step > 0) {
-      const double thr = a.lat_thr, v0 = (double)vp, v1 = (double)Vb;
-      if (v0 < thr && v1 >= thr && a.lat[i] < 0.0) {
-        const double w = (thr - v0) / (v1 - v0);
-        const double tA = __dadd_rn(__dmul_rn((double)step, dt), __dmul_rn(0.5, dt));
-        a.lat[i] = __dadd_rn(__dadd_rn(tA, -dt), __dmul_rn(w, dt));
-      }
+    if (!SORT || a.dvdt_src != 0) {
+      load_cell<T, M>(a, i, y, p);
+      k = decide_k<T, M>(a, i, step, y[0], y, p);
+    } else {
+      k = decide_k<T, M>(a, i, step, a.V[i], y, p);
     }
-    a.vprev[i] = Vb;
-    // k = min(k0 + floor|d|, k_max), k0 = 5 for d > 0 else 1
-    const T kd = (d > T(0) ? T(5) : T(1)) + xfloor(fabs(d));
-    k = (kd <= (T)a.k_max) ? (int)kd : a.k_max;
-    if (a.kt.mode & 1) {
-      const int64_t r = step - a.kt.rec_base;
-      if (r >= 0 && r < a.kt.rec_steps) a.kt.rec[r * a.n + i] = (uint8_t)k;
-    }
-    if (a.kt.mode & 2) {
-      const int64_t r = step - a.kt.rep_base;
-      if (r >= 0 && r < a.kt.rep_steps) k = a.kt.rep[r * a.n + i];
-    }
-    a.lastk[i] = (uint8_t)k;
   }
   if (a.stats) {
     // k statistics: wavefront reductions, then one atomic per workgroup and
@@ -95,24 +131,77 @@ __global__ __launch_bounds__(BLOCK) void k_ionic(IonArgs<T> a) {
       atomicAdd(&a.stats[threadIdx.x * 16], v);   // one 128-byte line per counter
     }
   }
-  if (!live) return;
-  const T h = (T)(dt / (double)k);
-  const bool clamp = a.vclamp != 0;
-  for (int s = 0; s < k; ++s) M::substep(y, p, h, clamp);
-  a.V[i] = y[0];
-  for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
+  if constexpr (SORT) {
+    constexpr int W = BLOCK / 64;
+    constexpr int NK = kSortMaxK + 1;
+    __shared__ int wcount[NK][W];   // nodes of key q in wavefront w, then their start
+    __shared__ int slot_node[BLOCK];
+    __shared__ unsigned char slot_k[BLOCK];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = live ? min(k, kSortMaxK) : -1;
+    unsigned long long mine = 0ull;
+    for (int kk = 0; kk < NK; ++kk) {
+      const unsigned long long m = __ballot(q == kk);
+      if (q == kk) mine = m;
+      if (lane == 0) wcount[kk][w] = __popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int kk = 0; kk < NK; ++kk)
+        for (int v = 0; v < W; ++v) {
+          const int c = wcount[kk][v];
+          wcount[kk][v] = run;
+          run += c;
+        }
+    }
+    __syncthreads();
+    if (live) {
+      const int pos = wcount[q][w] + __popcll(mine & ((1ull << lane) - 1ull));
+      slot_node[pos] = (int)threadIdx.x;
+      slot_k[pos] = (unsigned char)k;   // k <= 255 (k_max is capped there)
+    }
+    __syncthreads();
+    const int64_t n_here = min((int64_t)BLOCK, a.n - (int64_t)blockIdx.x * BLOCK);
+    if ((int64_t)threadIdx.x >= n_here) return;
+    // the node's rows addressed from the workgroup's (uniform) first node by
+    // a 32-bit lane offset
+    const int64_t b0 = (int64_t)blockIdx.x * BLOCK;
+    const uint32_t j = (uint32_t)slot_node[threadIdx.x];
+    const int kn = slot_k[threadIdx.x];
+    y[0] = (a.V + b0)[j];
+    for (int s = 1; s < M::S; ++s) y[s] = (a.st + (int64_t)(s - 1) * a.Np + b0)[j];
+    for (int c = 0; c < M::P; ++c)
+      p[c] = (a.par_pernode >> c & 1u) ? (a.par + (int64_t)c * a.Np + b0)[j] : a.par_uniform[c];
+    const T h = (T)(a.clk.dt / (double)kn);
+    const bool clamp = a.vclamp != 0;
+    for (int s = 0; s < kn; ++s) M::substep(y, p, h, clamp);
+    (a.V + b0)[j] = y[0];
+    for (int s = 1; s < M::S; ++s) (a.st + (int64_t)(s - 1) * a.Np + b0)[j] = y[s];
+  } else {
+    if (!live) return;
+    advance_cell<T, M>(a, i, y, p, k);
+  }
 }
 
 template <typename T, class M, int BLOCK>
-static void launch_ionic_k(const IonArgs<T>& a, hipStream_t s) {
+static void launch_ionic_k(const IonArgs<T>& a, bool sort, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + BLOCK - 1) / BLOCK));
-  hipLaunchKernelGGL((k_ionic<T, M, BLOCK>), grid, dim3(BLOCK), 0, s, a);
+  if (sort)
+    hipLaunchKernelGGL((k_ionic<T, M, BLOCK, true>), grid, dim3(BLOCK), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_ionic<T, M, BLOCK, false>), grid, dim3(BLOCK), 0, s, a);
 }
 template <typename T, class M>
 static void launch_ionic_m(const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
-  if (c.react_block == 128) return launch_ionic_k<T, M, 128>(a, s);
-  if (c.react_block == 512) return launch_ionic_k<T, M, 512>(a, s);
-  launch_ionic_k<T, M, 256>(a, s);
+  const bool sort = c.react_sort != 0;
+  if (c.react_block == 128) return launch_ionic_k<T, M, 128>(a, sort, s);
+  if (c.react_block == 512) return launch_ionic_k<T, M, 512>(a, sort, s);
+  if constexpr (sizeof(T) == 4) {
+    // 16 wavefronts per workgroup fit the register file only in FP32
+    if (c.react_block == 1024) return launch_ionic_k<T, M, 1024>(a, sort, s);
+  }
+  launch_ionic_k<T, M, 256>(a, sort, s);
 }
 
 template <typename T>

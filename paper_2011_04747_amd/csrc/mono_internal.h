@@ -11,6 +11,17 @@
 
 namespace mono {
 
+// FP64 product and sum with one rounding each: never fused into an FMA (HIP
+// compiles with contraction on, and the _rn intrinsics are plain operators).
+__host__ __device__ __forceinline__ double rn_mul(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__host__ __device__ __forceinline__ double rn_add(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxStim = 8;        // stimuli per simulation
 constexpr int kMaxOffsets = 13;    // positive stencil offsets (27-point hex stencil)
@@ -49,6 +60,22 @@ struct StencilHost {
 bool build_stencil(const HostCSR& K, const std::vector<int64_t>& inst_off, int64_t Np,
                    StencilHost& out);
 
+// Rows of a single-instance stencil that repeat exactly: row i is represented
+// by class cls[i], a table row holding its P forward weights e[p][i], its P
+// backward weights e[p][i - off_p] (0 where that neighbour is absent) and 1/m_i,
+// compared after rounding to the simulation precision.  Structured meshes with
+// piecewise-uniform conductivity have few classes (boundary type x material).
+struct RowClasses {
+  int tw = 0;                    // table row width: 2P + 1, padded to even
+  int n_classes = 0;
+  std::vector<uint16_t> cls;     // Np
+  std::vector<double> table;     // n_classes * tw, values exact in the precision
+};
+// Returns false (no compression) for several instances or when the rows do not
+// repeat enough: more than max_classes classes or more than Np / 8.
+bool build_row_classes(const StencilHost& sh, int64_t n, int64_t Np, bool fp32,
+                       int max_classes, RowClasses& out);
+
 // ---------------------------------------------------------------------------
 // kernel argument blocks
 // ---------------------------------------------------------------------------
@@ -59,7 +86,13 @@ struct LaunchCfg {
   int diff_xcd = 1;       // deal row ranges to XCDs
   int react_block = 256;  // 128, 256 or 512
   int graph_steps = 32;   // outer steps per captured HIP graph
+  int react_sort = 0;     // reaction nodes ordered by k within a workgroup
+  int diff_classes = 1;   // diffusion from row classes when the mesh has them
 };
+
+// keys of the in-workgroup ordering of the reaction by k: k = 0..kSortMaxK-1
+// each, and every k >= kSortMaxK the last key
+constexpr int kSortMaxK = 16;
 
 struct StimTable {
   int n;
@@ -88,6 +121,11 @@ struct DiffArgs {
   const T* e;
   const T* minv;
   const int32_t* off;        // n_inst * P
+  // STENCIL rows by class (single instance): table row = P forward weights,
+  // P backward weights, 1/m
+  const uint16_t* cls;       // per row, or nullptr
+  const T* ctab;
+  int tw;
   // instances
   const int32_t* inst;       // per node, or nullptr for a single instance
   const int64_t* inst_off;   // n_inst + 1 first nodes of the instances

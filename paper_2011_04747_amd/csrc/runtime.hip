@@ -77,6 +77,9 @@ struct mono_sim {
   int32_t* d_col = nullptr;
   void* d_val = nullptr;
   void* d_e = nullptr;
+  uint16_t* d_cls = nullptr;       // row classes of a single-instance stencil
+  void* d_ctab = nullptr;
+  int tw = 0, n_classes = 0;
   void* d_minv = nullptr;
   int32_t* d_off = nullptr;
   int64_t nnz = 0;
@@ -238,6 +241,9 @@ DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   a.col = s->d_col;
   a.val = (const T*)s->d_val;
   a.P = s->P;
+  a.cls = s->d_cls;
+  a.ctab = (const T*)s->d_ctab;
+  a.tw = s->tw;
   a.e = (const T*)s->d_e;
   a.minv = (const T*)s->d_minv;
   a.off = s->d_off;
@@ -761,6 +767,18 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
     if (st != MONO_OK) return bail(st);
     if (hipMemcpy(s->d_off, sh.off.data(), sh.off.size() * 4, hipMemcpyHostToDevice))
       return bail(fail(MONO_EDEVICE, "upload failed"));
+    RowClasses rc;
+    if (build_row_classes(sh, s->n, s->Np, s->prec == MONO_F32, 65535, rc)) {
+      if (dalloc(&s->d_cls, rc.cls.size()) ||
+          dalloc((char**)&s->d_ctab, rc.table.size() * s->es))
+        return bail(fail(MONO_ENOMEM, "device allocation failed"));
+      if (hipMemcpy(s->d_cls, rc.cls.data(), rc.cls.size() * 2, hipMemcpyHostToDevice))
+        return bail(fail(MONO_EDEVICE, "upload failed"));
+      st = upload_real(s, s->d_ctab, rc.table.data(), rc.table.size());
+      if (st != MONO_OK) return bail(st);
+      s->tw = rc.tw;
+      s->n_classes = rc.n_classes;
+    }
   } else {
     EllHost eh;
     build_ell(s->K, s->Np, eh);
@@ -793,6 +811,8 @@ void mono_destroy(mono_sim* s) {
   dfree(s->d_col);
   dfree(s->d_val);
   dfree(s->d_e);
+  dfree(s->d_cls);
+  dfree(s->d_ctab);
   dfree(s->d_minv);
   dfree(s->d_off);
   dfree(s->d_mask);
@@ -834,6 +854,7 @@ mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
   HIP_TRY(hipMemsetAsync(s->d_st, 0, (size_t)std::max(S - 1, 1) * Np * es, s->stream));
   HIP_TRY(hipMemsetAsync(s->d_k, 0, Np, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+
   // initial state
   std::vector<double> y((size_t)S * s->n);
   if (init_state) {
@@ -1096,6 +1117,7 @@ mono_status mono_get_info(mono_sim* s, int32_t inst, mono_info* out) {
   out->n_instances = s->n_inst;
   out->n_states = s->S;
   out->ell_width = s->layout == MONO_LAYOUT_ELL ? s->W : s->P;
+  out->row_classes = s->n_classes;
   return MONO_OK;
 }
 
@@ -1268,20 +1290,30 @@ mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
   if (!s || !c) return fail(MONO_EINVAL, "NULL argument");
   auto okb = [](int b) { return b == 128 || b == 256 || b == 512; };
   const int maxr = s->prec == MONO_F32 ? 4 : 2;
-  if (!okb(c->diff_block) || !okb(c->react_block))
-    return fail(MONO_EINVAL, "block sizes must be 128, 256 or 512");
-  if (!(c->diff_rows_per_lane == 1 || c->diff_rows_per_lane == 2 ||
-        c->diff_rows_per_lane == 4) || c->diff_rows_per_lane > maxr)
+  if (!okb(c->diff_block) ||
+      !(okb(c->react_block) || (c->react_block == 1024 && s->prec == MONO_F32)))
+    return fail(MONO_EINVAL, "block sizes must be 128, 256 or 512 (FP32 reaction: also 1024)");
+  const int r = c->diff_rows_per_lane;
+  const bool by_class = s->layout == MONO_LAYOUT_STENCIL && s->n_classes > 0 && c->diff_classes;
+  if (by_class) {
+    if (!(r == 1 || r == 2 || r == 4 || r == 8 || r == 16))
+      return fail(MONO_EINVAL, "rows per lane must be 1, 2, 4, 8 or 16");
+  } else if (!(r == 1 || r == 2 || r == 4) || r > maxr) {
     return fail(MONO_EINVAL, "rows per lane must be 1, 2 or 4 (FP64: 1 or 2)");
+  }
   if (c->diff_xcd_remap < 0 || c->diff_xcd_remap > 1) return fail(MONO_EINVAL, "bad remap flag");
   if (c->graph_steps < 1 || c->graph_steps > 8192)
     return fail(MONO_EINVAL, "graph_steps must be in 1..8192");
+  if (c->react_sort < 0 || c->react_sort > 1) return fail(MONO_EINVAL, "bad sort flag");
+  if (c->diff_classes < 0 || c->diff_classes > 1) return fail(MONO_EINVAL, "bad classes flag");
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->lc.diff_block = c->diff_block;
   s->lc.diff_rpl = c->diff_rows_per_lane;
   s->lc.diff_xcd = c->diff_xcd_remap;
   s->lc.react_block = c->react_block;
   s->lc.graph_steps = c->graph_steps;
+  s->lc.react_sort = c->react_sort;
+  s->lc.diff_classes = c->diff_classes;
   drop_graph(s);
   return MONO_OK;
 }
@@ -1293,6 +1325,8 @@ mono_status mono_get_launch(mono_sim* s, mono_launch* c) {
   c->diff_xcd_remap = s->lc.diff_xcd;
   c->react_block = s->lc.react_block;
   c->graph_steps = s->lc.graph_steps;
+  c->react_sort = s->lc.react_sort;
+  c->diff_classes = s->lc.diff_classes;
   return MONO_OK;
 }
 

@@ -52,7 +52,7 @@ def _check_flips(w, k_orc, d_orc, k_gpu):
 
 
 def run_pair(torch, w, n_steps, precision="f64", layout=mono.LAYOUT_AUTO, every=None,
-             replay=True):
+             replay=True, launch=None):
     """Run the oracle (recording its k decisions), then the GPU replaying them;
     returns per-level (V_orc, V_gpu), both simulations and the flip count."""
     o = _oracle(w)
@@ -64,6 +64,8 @@ def run_pair(torch, w, n_steps, precision="f64", layout=mono.LAYOUT_AUTO, every=
         o.step(c, w.dt)
         vo.append(o.get(0))
     s = mono.Sim.from_workload(w, precision, layout=layout)
+    if launch:
+        s.set_launch(**launch)
     rep = torch.from_numpy(kt).cuda()
     rec = torch.zeros_like(rep)
     s.ktrace(3 if replay else 1, rec.data_ptr(), rep.data_ptr(), n_steps, 0)
@@ -442,18 +444,92 @@ def test_launch_shapes_do_not_change_results(torch, which):
     for cfg in ({}, dict(diff_block=128, diff_rows_per_lane=4, diff_xcd_remap=0, react_block=512,
                          graph_steps=8),
                 dict(diff_block=512, diff_rows_per_lane=2, diff_xcd_remap=1, react_block=128,
-                     graph_steps=120)):
+                     graph_steps=120, react_sort=1),
+                dict(react_sort=1, graph_steps=7),
+                dict(react_sort=1, react_block=1024, graph_steps=64),
+                dict(react_sort=0, react_block=1024, graph_steps=64, diff_classes=0),
+                dict(diff_classes=0, diff_rows_per_lane=2, diff_block=128)):
         s = mono.Sim.from_workload(w, "f32")
         if cfg:
             s.set_launch(**cfg)
         s.step(w.n_steps, w.dt)
         out = (s.get(mono.FIELD_V), s.state(min(4, s.info()["n_states"] - 1)),
-               s.get(mono.FIELD_LAT))
+               s.get(mono.FIELD_LAT), s.get(mono.FIELD_K), s.get(mono.FIELD_VPREV))
         if ref is None:
             ref = out
         else:
-            for a, b in zip(ref, out):
-                assert (a == b).all()
+            for f, (a, b) in enumerate(zip(ref, out)):
+                bad = np.flatnonzero(a != b)
+                assert bad.size == 0, (cfg, f, bad.size, bad[:5], a[bad[:5]], b[bad[:5]])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("which", ["slab", "sheet", "cable"])
+def test_row_classes_match_per_row_arrays(torch, prec, which):
+    """Diffusion reading stencil rows by class gives the bits of the per-row
+    arrays.  Grid spacings are powers of two so that the node coordinates,
+    and with them the element matrices, repeat exactly in FP64 as well."""
+    if which == "slab":
+        w = W.slab_ischemic(shape=(37, 29, 11), dx=2.0 ** -7, t_end=15.0)
+    elif which == "sheet":
+        w = W.sheet_tp06(n=61, dx=2.0 ** -5, t_end=15.0)
+    else:
+        w = W.cable_ms(n_nodes=513, length=4.0, t_end=15.0)
+    outs = []
+    for cls in (1, 0):
+        s = mono.Sim.from_workload(w, prec)
+        assert s.info()["row_classes"] > 0
+        s.set_launch(diff_classes=cls)
+        s.step(w.n_steps, w.dt)
+        outs.append((s.get(mono.FIELD_V), s.get(mono.FIELD_LAT)))
+    for a, b in zip(*outs):
+        assert (a == b).all()
+
+
+def test_row_classes_absent_where_rows_do_not_repeat(torch):
+    w = W.batched_sheets(n_inst=3, side_lo=12, side_hi=20)
+    assert mono.Sim.from_workload(w, "f32").info()["row_classes"] == 0
+    w = W.sheet_tp06(n=41)
+    w.mesh.sigma = np.exp(0.2 * np.random.default_rng(0).standard_normal(w.mesh.n_nodes))
+    assert mono.Sim.from_workload(w, "f32").info()["row_classes"] == 0
+
+
+@pytest.mark.parametrize("layout", [mono.LAYOUT_ELL, mono.LAYOUT_STENCIL])
+def test_sorted_reaction_fp64_parity(torch, layout):
+    """The reaction with the nodes of each workgroup ordered by k, against the
+    oracle replaying its k decisions, on the ischemic slab."""
+    w = W.slab_ischemic(shape=(25, 21, 9), t_end=25.0)
+    _, s, levels, _ = run_pair(torch, w, w.n_steps, "f64", layout, every=40,
+                               launch=dict(react_sort=1, graph_steps=16))
+    _assert_f64_levels(w, levels)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sorted_reaction_restarts_and_phases(torch, prec):
+    """Rewinding the clock, eager steps, single phases and the model-rate
+    dV/dt source give the same bits with and without the ordering by k."""
+    w = W.slab_ischemic(shape=(23, 19, 9), t_end=20.0)
+    outs = []
+    for srt in (0, 1):
+        s = mono.Sim.from_workload(w, prec)
+        s.set_launch(react_sort=srt, graph_steps=5)
+        s.step(30, w.dt)
+        snap = {f: s.get(f) for f in (mono.FIELD_V, mono.FIELD_VPREV, mono.FIELD_LAT)}
+        st = [s.state(j) for j in range(1, s.info()["n_states"])]
+        s.step(13, w.dt)
+        for f, v in snap.items():
+            s.set(f, v)
+        for j, v in enumerate(st, start=1):
+            s.set(mono.FIELD_STATE0 + j, v)
+        s.set_time_level(30)
+        s.step(9, w.dt, flags=mono.STEP_EAGER)
+        s.step(11, w.dt)
+        s.apply_phase(1, 50)
+        s.set_method(mono.DAETI, dvdt_source=1)
+        s.step(6, w.dt)
+        outs.append((s.get(mono.FIELD_V), s.state(3), s.get(mono.FIELD_LAT), s.get(mono.FIELD_K)))
+    for a, b in zip(*outs):
+        assert (a == b).all()
 
 
 def test_autotuner_leaves_state_unchanged(torch, tmp_path, monkeypatch):
