@@ -208,7 +208,8 @@ def main():
     sim.set_launch(**launch)
     sim.step(args.warmup, w.dt)
     sim.kernel_times(reset=True)
-    kbuf = torch.zeros(((n + 63) // 64) * 64, dtype=torch.uint8, device="cuda")
+    kbuf = torch.zeros(((n + 1023) // 1024) * 1024, dtype=torch.uint8, device="cuda")
+    rb = launch.get("react_block", 256)
     ksum = kwave = ksat = 0
     kt_steps = args.steps
     for _ in range(kt_steps):
@@ -217,7 +218,12 @@ def main():
             sim.get_device_async(mono.FIELD_K, kbuf.data_ptr())
             kk = kbuf.to(torch.int64)
             ksum += int(kk.sum())
-            kwave += 64 * int(kk.view(-1, 64).amax(dim=1).sum())
+            if launch.get("react_sort", 0):
+                # lanes take the nodes of their workgroup in order of k
+                kw = kk[:((n + rb - 1) // rb) * rb].view(-1, rb).sort(dim=1).values
+            else:
+                kw = kk
+            kwave += 64 * int(kw.reshape(-1, 64).amax(dim=1).sum())
             ksat += int((kk[:n] == info["k_max"]).sum())
     torch.cuda.synchronize()
     kt = sim.kernel_times()
@@ -227,7 +233,11 @@ def main():
 
     # algorithmic work per launch
     P = info["ell_width"]
-    if info["layout"] == mono.LAYOUT_STENCIL:
+    by_class = (info["layout"] == mono.LAYOUT_STENCIL and info["row_classes"] > 0
+                and launch.get("diff_classes", 1))
+    if by_class:
+        row_bytes = 4 + 4 + 2        # V in, V out, class id (table rows stay in cache)
+    elif info["layout"] == mono.LAYOUT_STENCIL:
         row_bytes = (P + 3) * 4      # own edges, 1/m, V in, V out
     else:
         row_bytes = P * 8 + 2 * 4    # (value, column) per slot, V in, V out
@@ -240,7 +250,9 @@ def main():
     react_flops = (ksum / kt_steps) * f_model
     diff_total = kt["diffusion_ms"] / kt_steps
     react_total = kt["reaction_ms"] / kt_steps
-    diff_roof = {"kernel": ("k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL
+    by_rows = by_class and info["grid_rows"] and launch.get("diff_wave_rows", 1)
+    diff_roof = {"kernel": ("k_diff_rows" if by_rows else "k_diff_classes" if by_class else
+                            "k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL
                             else "k_diff_ell") + f"<float,{P}>",
                  "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
@@ -291,6 +303,7 @@ def main():
                       "k_max": info["k_max"],
                       "layout": "stencil" if info["layout"] == mono.LAYOUT_STENCIL else "ell",
                       "sim_ms_per_s": w.dt * args.steps / (ms * 1e-3),
+                      "row_classes": info["row_classes"],
                       "mean_k": ksum / (n * kt_steps), "k_at_kmax_frac": ksat / (n * kt_steps),
                       "wall_s": wall},
            "roofline": roofline,

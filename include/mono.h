@@ -129,6 +129,8 @@ typedef struct {
   int32_t ell_width;  /* ELL slots per row, or stencil offsets per instance    */
   int32_t row_classes; /* distinct stencil rows of a single instance when the
                           diffusion can read rows by class, else 0             */
+  int32_t grid_rows;   /* 1 when the stencil offsets are those of a structured
+                          grid numbered x fastest (row-sharing diffusion)      */
 } mono_info;
 
 /* Assemble K and the row-sum lumped mass M_L of the FE diffusion problem
@@ -194,7 +196,7 @@ mono_status mono_get_info(mono_sim *sim, int32_t inst, mono_info *out);
  * and check dt_ad < 2/lambda_est for the last prepared dt. */
 mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
 
-/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32, 0, 1).  Block
+/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32, 0, 1, 1).  Block
  * sizes 128, 256 or 512 lanes (the FP32 reaction also 1024); rows per lane of the stencil diffusion kernel
  * 1, 2 or 4 (FP64: 1 or 2; ignored by the ELL layout); XCD remap 0/1 (deal
  * contiguous row ranges to each of the 8 XCDs); graph_steps 1..8192 outer
@@ -205,7 +207,9 @@ mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
  * stencil diffusion reads each row's weights and 1/m from a table of the
  * distinct rows through a 2-byte class id instead of per-row arrays, and
  * rows per lane (1, 2, 4, 8 or 16, any precision) count the rows each lane
- * sweeps in turn.
+ * sweeps in turn; diff_wave_rows 0/1 (default 1): with row classes on a
+ * structured grid (mono_info.grid_rows) a wavefront loads each neighbouring
+ * grid row once and passes x-neighbours between lanes.
  * Results do not depend on the shape (bitwise). */
 typedef struct {
   int32_t diff_block;
@@ -215,6 +219,7 @@ typedef struct {
   int32_t graph_steps;
   int32_t react_sort;
   int32_t diff_classes;
+  int32_t diff_wave_rows;
 } mono_launch;
 mono_status mono_set_launch(mono_sim *sim, const mono_launch *cfg);
 mono_status mono_get_launch(mono_sim *sim, mono_launch *out);

@@ -2,8 +2,9 @@
 
 Searches, on the simulation it is given and at its current state:
   * diffusion kernel: workgroup size (128/256/512), stencil rows per lane
-    (1/2/4; vector loads of the streamed arrays) or rows read by class, and
-    the XCD row remap;
+    (1/2/4; vector loads of the streamed arrays), rows read by class, rows by
+    class sharing neighbour rows across lanes (1/2/4 row groups per
+    wavefront), and the XCD row remap;
   * reaction kernel: workgroup size, and whether each workgroup orders its
     nodes by substep count k before advancing them;
   * outer steps per captured HIP graph.
@@ -86,28 +87,33 @@ def tune(sim: mono.Sim, dt: float, steps: int = 8, use_cache: bool = True,
     best_d, best_r = None, None
     _restore(sim, snap)
     _time_kernels(sim, dt, steps)            # warm caches and clocks first
-    # stencil rows by class (one RPL) or per-row arrays (RPL 1/2/4)
-    shapes = [(0, rpl) for rpl in rpls]
+    # per-row arrays (rows per lane 1/2/4), rows by class (1), or rows by
+    # class with neighbour rows shared across lanes (row groups 1/2/4)
+    shapes = [(0, 0, rpl) for rpl in rpls]
     if info["row_classes"] > 0:
-        shapes.append((1, 1))
+        shapes.append((1, 0, 1))
+        if info["grid_rows"]:
+            shapes += [(1, 1, g) for g in (1, 2, 4)]
     for blk in (128, 256, 512):
-        for cls, rpl in shapes:
+        for cls, rows, rpl in shapes:
             for xcd in (0, 1):
                 sim.set_launch(diff_block=blk, diff_rows_per_lane=rpl, diff_xcd_remap=xcd,
-                               diff_classes=cls, react_block=blk, react_sort=0)
+                               diff_classes=cls, diff_wave_rows=rows, react_block=blk,
+                               react_sort=0)
                 _restore(sim, snap)
                 d, r = _time_kernels(sim, dt, steps)
-                trials.append({"diff_block": blk, "classes": cls, "rpl": rpl, "xcd": xcd,
-                               "diff_ms": d, "react_block": blk, "react_ms": r})
+                trials.append({"diff_block": blk, "classes": cls, "wave_rows": rows, "rpl": rpl,
+                               "xcd": xcd, "diff_ms": d, "react_block": blk, "react_ms": r})
                 if verbose:
                     print("tune", trials[-1], flush=True)
                 if best_d is None or d < best_d[0]:
-                    best_d = (d, blk, rpl, xcd, cls)
+                    best_d = (d, blk, rpl, xcd, cls, rows)
                 if best_r is None or r < best_r[0]:
                     best_r = (r, blk)
     best = dict(base)
     best.update(diff_block=best_d[1], diff_rows_per_lane=best_d[2], diff_xcd_remap=best_d[3],
-                diff_classes=best_d[4], react_block=best_r[1], react_sort=0)
+                diff_classes=best_d[4], diff_wave_rows=best_d[5], react_block=best_r[1],
+                react_sort=0)
     sort_blocks = (256, 512, 1024) if sim.precision == "f32" else (256, 512)
     for blk in sort_blocks:
         sim.set_launch(**dict(best, react_block=blk, react_sort=1))

@@ -270,6 +270,176 @@ __global__ __launch_bounds__(BLOCK) void k_diff_classes(DiffArgs<T> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Stencil rows by class, neighbour rows shared across lanes
+// ---------------------------------------------------------------------------
+// On a structured grid numbered x fastest the stencil offsets come in
+// triples c-1, c, c+1 around a few "row centres" c (0 and +-nx in 2D; 0,
+// +-nx, +-(nxy-nx), +-nxy, +-(nxy+nx) in 3D).  A wavefront then loads each
+// centre row once for its 64 consecutive rows and takes the x-1 / x+1
+// neighbours from the adjacent lanes (DPP wavefront shifts); lanes 0 and 63
+// only supply those neighbours, lanes 1..62 produce rows.  The arithmetic and
+// its order are those of k_diff_classes, so the results are the same bits.
+template <int P>
+struct RowPattern;
+template <>
+struct RowPattern<1> {
+  static constexpr int NC = 1;
+  __device__ static constexpr int fk(int) { return 0; }
+  __device__ static constexpr int fd(int) { return 1; }
+  __device__ static constexpr int bk(int) { return 0; }
+  __device__ static constexpr int bd(int) { return -1; }
+};
+template <>
+struct RowPattern<4> {   // centres 0, +nx, -nx; offsets 1, nx-1, nx, nx+1
+  static constexpr int NC = 3;
+  __device__ static constexpr int fk(int p) { return p == 0 ? 0 : 1; }
+  __device__ static constexpr int fd(int p) { return p == 0 ? 1 : p - 2; }
+  __device__ static constexpr int bk(int p) { return p == 0 ? 0 : 2; }
+  __device__ static constexpr int bd(int p) { return p == 0 ? -1 : 2 - p; }
+};
+template <>
+struct RowPattern<13> {  // centres 0, nx, nxy-nx, nxy, nxy+nx, then their negatives
+  static constexpr int NC = 9;
+  __device__ static constexpr int fk(int p) { return p == 0 ? 0 : 1 + (p - 1) / 3; }
+  __device__ static constexpr int fd(int p) { return p == 0 ? 1 : (p - 1) % 3 - 1; }
+  __device__ static constexpr int bk(int p) { return p == 0 ? 0 : 5 + (p - 1) / 3; }
+  __device__ static constexpr int bd(int p) { return p == 0 ? -1 : 1 - (p - 1) % 3; }
+};
+
+// value of the next (d = 1) or previous (d = -1) lane of the wavefront
+template <int D, typename T>
+__device__ __forceinline__ T lane_shift(T v) {
+  if constexpr (D == 0) {
+    return v;
+  } else if constexpr (sizeof(T) == 4) {
+    const int x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), D > 0 ? 0x130 : 0x138, 0xf,
+                                              0xf, false);
+    return __int_as_float(x);
+  } else {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), D > 0 ? 0x130 : 0x138,
+                                               0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), D > 0 ? 0x130 : 0x138, 0xf,
+                                               0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
+// Each wavefront produces ITER consecutive groups of kWaveRows rows; the loads
+// of all groups are issued before any group is computed.
+template <typename T, int P, int BLOCK, int ITER>
+__global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __restrict__ ctab,
+                                                     const int32_t* __restrict__ wcls) {
+  using RP = RowPattern<P>;
+  constexpr int NC = RP::NC;
+  constexpr int WR = kWaveRows;
+  constexpr int WPB = BLOCK / 64;
+  constexpr int ES = (int)sizeof(T);
+  const int n = (int)a.n;
+  const int64_t ngroups = (a.n + WR - 1) / WR;
+  const int64_t nb = (ngroups + (int64_t)WPB * ITER - 1) / ((int64_t)WPB * ITER);
+  const int lane = threadIdx.x & 63;
+  // first row group of this wavefront (wave-uniform)
+  const int64_t g0 =
+      (row_block(nb, a.xcd) * WPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) *
+      ITER;
+  if (g0 >= ngroups) return;                // whole wavefront past the end
+  // row centres from the offsets (validated on the host)
+  int ctr[NC];
+  ctr[0] = 0;
+  if constexpr (P == 4) {
+    ctr[1] = a.off[2];
+    ctr[2] = -a.off[2];
+  } else if constexpr (P == 13) {
+    const int nx = a.off[2], nxy = a.off[8];
+    ctr[1] = nx;
+    ctr[2] = nxy - nx;
+    ctr[3] = nxy;
+    ctr[4] = nxy + nx;
+    for (int k = 1; k < 5; ++k) ctr[4 + k] = -ctr[k];
+  }
+  // every lane (halo lanes included) loads the centre rows of every group;
+  // all lanes stay active through the shifts
+  T vc[ITER][NC];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int i = (int)((g0 + it) * WR) + lane - 1;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int j = min(max(i + ctr[k], 0), n - 1);
+      vc[it][k] = ld_bytes(a.Vin, (uint32_t)(j * ES));
+    }
+  }
+  const double dt_ad = a.dt_ad[0];
+  const T hT = (T)dt_ad;
+  const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int64_t g = g0 + it;
+    if (g >= ngroups) break;
+    const int i = (int)(g * WR) + lane - 1;
+    const bool produce = lane >= 1 && lane <= WR && i < n;
+    T vl[NC], vr[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      vl[k] = lane_shift<1>(vc[it][k]);
+      vr[k] = lane_shift<-1>(vc[it][k]);
+    }
+    auto pick = [&](int k, int d) -> T {
+      return d > 0 ? vl[k] : (d < 0 ? vr[k] : vc[it][k]);
+    };
+    const T vi = vc[it][0];
+    T acc = T(0), mv;
+    auto sweep = [&](auto w) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const T vf = pick(RP::fk(p), RP::fd(p));
+        const T vb = pick(RP::bk(p), RP::bd(p));
+        acc += w[p] * (vf - vi);
+        acc += w[P + p] * (vb - vi);
+      }
+      mv = w[2 * P];
+    };
+    // class shared by the group's rows, or kNoClass
+    const int wc = wcls[g];
+    if (wc != kNoClass) {
+      // one table row for the whole wavefront: read through the constant
+      // address space, i.e. by scalar loads
+      using CT = const __attribute__((address_space(4))) T*;
+      sweep((CT)(ctab + (uint32_t)(wc * a.tw)));
+    } else {
+      const int ic = min(max(i, 0), n - 1);
+      sweep(ctab + (uint32_t)((int)a.cls[(uint32_t)ic] * a.tw));
+    }
+    if (produce) {
+      const T sr = stimulus_rate(a, (int64_t)i, tau);
+      *(T*)((char*)a.Vout + (uint32_t)(i * ES)) = vi + hT * (mv * acc + sr);
+    }
+  }
+}
+
+template <typename T, int P, int BLOCK, int ITER>
+static void launch_rows_k(const DiffArgs<T>& a, hipStream_t s) {
+  const int64_t ngroups = (a.n + kWaveRows - 1) / kWaveRows;
+  const int64_t per = (int64_t)(BLOCK / 64) * ITER;
+  const dim3 grid((unsigned)((ngroups + per - 1) / per));
+  hipLaunchKernelGGL((k_diff_rows<T, P, BLOCK, ITER>), grid, dim3(BLOCK), 0, s, a, a.ctab,
+                     a.wcls);
+}
+template <typename T, int P, int BLOCK>
+static void launch_rows_i(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (c.diff_rpl == 2) return launch_rows_k<T, P, BLOCK, 2>(a, s);
+  if (c.diff_rpl >= 4) return launch_rows_k<T, P, BLOCK, 4>(a, s);
+  launch_rows_k<T, P, BLOCK, 1>(a, s);
+}
+template <typename T, int P>
+static void launch_rows_b(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
+  if (c.diff_block == 128) return launch_rows_i<T, P, 128>(a, c, s);
+  if (c.diff_block == 512) return launch_rows_i<T, P, 512>(a, c, s);
+  launch_rows_i<T, P, 256>(a, c, s);
+}
+
 template <typename T, int P, int BLOCK, int ITER>
 static void launch_classes_k(const DiffArgs<T>& a, hipStream_t s) {
   const int64_t per = (int64_t)BLOCK * ITER;
@@ -347,6 +517,14 @@ void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipS
     return;
   }
   if (a.cls && !a.inst && c.diff_classes && a.n * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+    if (a.wcls && c.diff_wave_rows) {
+      switch (a.P) {
+        case 1: launch_rows_b<T, 1>(a, c, s); return;
+        case 4: launch_rows_b<T, 4>(a, c, s); return;
+        case 13: launch_rows_b<T, 13>(a, c, s); return;
+        default: break;
+      }
+    }
     switch (a.P) {
       case 1: launch_classes_b<T, 1>(a, c, s); break;
       case 4: launch_classes_b<T, 4>(a, c, s); break;

@@ -88,11 +88,17 @@ struct LaunchCfg {
   int graph_steps = 32;   // outer steps per captured HIP graph
   int react_sort = 0;     // reaction nodes ordered by k within a workgroup
   int diff_classes = 1;   // diffusion from row classes when the mesh has them
+  int diff_wave_rows = 1; // class diffusion sharing neighbour rows across lanes
 };
 
 // keys of the in-workgroup ordering of the reaction by k: k = 0..kSortMaxK-1
 // each, and every k >= kSortMaxK the last key
 constexpr int kSortMaxK = 16;
+
+// rows produced per wavefront by the row-sharing diffusion (lanes 1..62; lanes
+// 0 and 63 hold the neighbouring rows)
+constexpr int kWaveRows = 62;
+constexpr int32_t kNoClass = -1;
 
 struct StimTable {
   int n;
@@ -126,6 +132,8 @@ struct DiffArgs {
   const uint16_t* cls;       // per row, or nullptr
   const T* ctab;
   int tw;
+  const int32_t* wcls;       // grid-row stencils: class of each wavefront's
+                             // kWaveRows rows, or kNoClass; nullptr otherwise
   // instances
   const int32_t* inst;       // per node, or nullptr for a single instance
   const int64_t* inst_off;   // n_inst + 1 first nodes of the instances

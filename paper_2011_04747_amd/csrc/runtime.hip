@@ -80,6 +80,8 @@ struct mono_sim {
   uint16_t* d_cls = nullptr;       // row classes of a single-instance stencil
   void* d_ctab = nullptr;
   int tw = 0, n_classes = 0;
+  int row_pattern = 0;             // stencil offsets are grid row triples
+  int32_t* d_wcls = nullptr;       // per-wavefront class of the row-sharing diffusion
   void* d_minv = nullptr;
   int32_t* d_off = nullptr;
   int64_t nnz = 0;
@@ -157,6 +159,27 @@ void drop_graph(mono_sim* s) {
 }
 
 // upload n_host doubles into a device array of the simulation's precision
+// Offsets of a structured grid numbered x fastest: 1 (line); 1, nx-1, nx, nx+1
+// (quads); and in 3D the nine x-triples around 0, nx, nxy-nx, nxy, nxy+nx.
+bool grid_row_pattern(const std::vector<int32_t>& off) {
+  const size_t P = off.size();
+  if (P == 1) return off[0] == 1;
+  if (P == 4) {
+    const int nx = off[2];
+    return nx > 2 && off[0] == 1 && off[1] == nx - 1 && off[3] == nx + 1;
+  }
+  if (P == 13) {
+    const int64_t nx = off[2], nxy = off[8];
+    const int64_t want[13] = {1,           nx - 1,       nx,       nx + 1,  nxy - nx - 1,
+                              nxy - nx,    nxy - nx + 1, nxy - 1,  nxy,     nxy + 1,
+                              nxy + nx - 1, nxy + nx,    nxy + nx + 1};
+    for (int p = 0; p < 13; ++p)
+      if (off[p] != want[p] || (p > 0 && want[p] <= want[p - 1])) return false;
+    return true;
+  }
+  return false;
+}
+
 mono_status upload_real(mono_sim* s, void* dst, const double* src, size_t count) {
   if (count == 0) return MONO_OK;
   if (s->prec == MONO_F64) {
@@ -244,6 +267,7 @@ DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   a.cls = s->d_cls;
   a.ctab = (const T*)s->d_ctab;
   a.tw = s->tw;
+  a.wcls = s->d_wcls;
   a.e = (const T*)s->d_e;
   a.minv = (const T*)s->d_minv;
   a.off = s->d_off;
@@ -778,6 +802,22 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
       if (st != MONO_OK) return bail(st);
       s->tw = rc.tw;
       s->n_classes = rc.n_classes;
+      s->row_pattern = grid_row_pattern(sh.off) ? 1 : 0;
+      if (s->row_pattern) {
+        // class shared by all kWaveRows rows of a wavefront, else kNoClass
+        const int64_t nw = (s->n + kWaveRows - 1) / kWaveRows;
+        std::vector<int32_t> wc(nw);
+        for (int64_t w = 0; w < nw; ++w) {
+          const int64_t r0 = w * kWaveRows, r1 = std::min<int64_t>(r0 + kWaveRows, s->n);
+          int32_t c = rc.cls[r0];
+          for (int64_t r = r0 + 1; r < r1 && c != kNoClass; ++r)
+            if (rc.cls[r] != c) c = kNoClass;
+          wc[w] = c;
+        }
+        if (dalloc(&s->d_wcls, nw)) return bail(fail(MONO_ENOMEM, "device allocation failed"));
+        if (hipMemcpy(s->d_wcls, wc.data(), nw * 4, hipMemcpyHostToDevice))
+          return bail(fail(MONO_EDEVICE, "upload failed"));
+      }
     }
   } else {
     EllHost eh;
@@ -813,6 +853,7 @@ void mono_destroy(mono_sim* s) {
   dfree(s->d_e);
   dfree(s->d_cls);
   dfree(s->d_ctab);
+  dfree(s->d_wcls);
   dfree(s->d_minv);
   dfree(s->d_off);
   dfree(s->d_mask);
@@ -1118,6 +1159,7 @@ mono_status mono_get_info(mono_sim* s, int32_t inst, mono_info* out) {
   out->n_states = s->S;
   out->ell_width = s->layout == MONO_LAYOUT_ELL ? s->W : s->P;
   out->row_classes = s->n_classes;
+  out->grid_rows = s->row_pattern;
   return MONO_OK;
 }
 
@@ -1306,6 +1348,7 @@ mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
     return fail(MONO_EINVAL, "graph_steps must be in 1..8192");
   if (c->react_sort < 0 || c->react_sort > 1) return fail(MONO_EINVAL, "bad sort flag");
   if (c->diff_classes < 0 || c->diff_classes > 1) return fail(MONO_EINVAL, "bad classes flag");
+  if (c->diff_wave_rows < 0 || c->diff_wave_rows > 1) return fail(MONO_EINVAL, "bad rows flag");
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->lc.diff_block = c->diff_block;
   s->lc.diff_rpl = c->diff_rows_per_lane;
@@ -1314,6 +1357,7 @@ mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
   s->lc.graph_steps = c->graph_steps;
   s->lc.react_sort = c->react_sort;
   s->lc.diff_classes = c->diff_classes;
+  s->lc.diff_wave_rows = c->diff_wave_rows;
   drop_graph(s);
   return MONO_OK;
 }
@@ -1327,6 +1371,7 @@ mono_status mono_get_launch(mono_sim* s, mono_launch* c) {
   c->graph_steps = s->lc.graph_steps;
   c->react_sort = s->lc.react_sort;
   c->diff_classes = s->lc.diff_classes;
+  c->diff_wave_rows = s->lc.diff_wave_rows;
   return MONO_OK;
 }
 

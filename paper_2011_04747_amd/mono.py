@@ -57,14 +57,15 @@ class Info(C.Structure):
                 ("dt_ad", C.c_double), ("dt", C.c_double), ("t", C.c_double),
                 ("step", C.c_int64), ("nnz", C.c_int64), ("l", C.c_int32), ("k_max", C.c_int32),
                 ("layout", C.c_int32), ("n_instances", C.c_int32), ("n_states", C.c_int32),
-                ("ell_width", C.c_int32), ("row_classes", C.c_int32)]
+                ("ell_width", C.c_int32), ("row_classes", C.c_int32),
+                ("grid_rows", C.c_int32)]
 
 
 class Launch(C.Structure):
     _fields_ = [("diff_block", C.c_int32), ("diff_rows_per_lane", C.c_int32),
                 ("diff_xcd_remap", C.c_int32), ("react_block", C.c_int32),
                 ("graph_steps", C.c_int32), ("react_sort", C.c_int32),
-                ("diff_classes", C.c_int32)]
+                ("diff_classes", C.c_int32), ("diff_wave_rows", C.c_int32)]
 
 
 class KTrace(C.Structure):

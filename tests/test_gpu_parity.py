@@ -448,7 +448,8 @@ def test_launch_shapes_do_not_change_results(torch, which):
                 dict(react_sort=1, graph_steps=7),
                 dict(react_sort=1, react_block=1024, graph_steps=64),
                 dict(react_sort=0, react_block=1024, graph_steps=64, diff_classes=0),
-                dict(diff_classes=0, diff_rows_per_lane=2, diff_block=128)):
+                dict(diff_classes=0, diff_rows_per_lane=2, diff_block=128),
+                dict(diff_wave_rows=0, diff_rows_per_lane=4, diff_block=512)):
         s = mono.Sim.from_workload(w, "f32")
         if cfg:
             s.set_launch(**cfg)
@@ -476,14 +477,15 @@ def test_row_classes_match_per_row_arrays(torch, prec, which):
     else:
         w = W.cable_ms(n_nodes=513, length=4.0, t_end=15.0)
     outs = []
-    for cls in (1, 0):
+    for cls, rows in ((1, 1), (1, 0), (0, 0)):
         s = mono.Sim.from_workload(w, prec)
-        assert s.info()["row_classes"] > 0
-        s.set_launch(diff_classes=cls)
+        assert s.info()["row_classes"] > 0 and s.info()["grid_rows"] == 1
+        s.set_launch(diff_classes=cls, diff_wave_rows=rows)
         s.step(w.n_steps, w.dt)
         outs.append((s.get(mono.FIELD_V), s.get(mono.FIELD_LAT)))
-    for a, b in zip(*outs):
-        assert (a == b).all()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert (a == b).all()
 
 
 def test_row_classes_absent_where_rows_do_not_repeat(torch):
