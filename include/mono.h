@@ -165,11 +165,14 @@ mono_status mono_set_method(mono_sim *sim, int32_t method, int32_t dvdt_source, 
 
 /* Advance n_outer_steps steps of size dt [ms] (async).  flags: bit 0
  * (MONO_STEP_EAGER) = launch kernels one by one instead of replaying a cached
- * HIP graph of 32 outer steps; bit 1 (MONO_STEP_TIMED) = launch one by one
- * with every kernel bracketed by HIP events on the simulation's stream and
- * add their durations to the totals read by MONO_DEBUG_KTIMES (this mode
- * synchronises). */
-enum { MONO_STEP_EAGER = 1, MONO_STEP_TIMED = 2 };
+ * HIP graph of graph_steps outer steps; bit 1 (MONO_STEP_TIMED) = launch one
+ * by one, every step kernel with a start and a stop event that the command
+ * processor records at the kernel's begin and end, and add the durations to
+ * the totals read by MONO_DEBUG_KTIMES (this mode synchronises); bit 2
+ * (MONO_STEP_CAPTURE) = only capture the graphs that a graph-mode call with
+ * the same n_outer_steps and dt would replay (graph_steps steps and the
+ * remainder), so that the call itself does no capture work; nothing runs. */
+enum { MONO_STEP_EAGER = 1, MONO_STEP_TIMED = 2, MONO_STEP_CAPTURE = 4 };
 mono_status mono_step(mono_sim *sim, int64_t n_outer_steps, double dt, uint32_t flags);
 
 /* Copy `count` (= n_nodes) values of a field to host memory as FP64. */
@@ -301,14 +304,23 @@ mono_status mono_backward(mono_sim *sim, double *grad_sigma, double *grad_params
  *  MONO_DEBUG_KTIMES: arg -> double[5]; returns {diffusion kernel ms,
  *      diffusion launches, reaction kernel ms, reaction launches} of the
  *      MONO_STEP_TIMED steps so far; the totals are reset when arg[4] != 0
- *      on entry. */
+ *      on entry.
+ *  MONO_DEBUG_TIME_DIFFUSION: arg -> double[2]; arg[0] = an even number R
+ *      of repetitions on entry; runs R diffusion substeps (the first
+ *      substep of the first half step at the current time level, alternating
+ *      between the two potential buffers) captured in one HIP graph, timed
+ *      by events around the graph launch, and returns the mean ms per
+ *      substep in arg[1].  The potential is advanced by those R substeps:
+ *      for benchmarking simulations only.  Synchronising; needs
+ *      mono_prepare. */
 enum {
   MONO_DEBUG_KTRACE = 1,
   MONO_DEBUG_VCLAMP = 2,
   MONO_DEBUG_FORCE_L = 3,
   MONO_DEBUG_STATS = 4,
   MONO_DEBUG_STATS_ENABLE = 5,
-  MONO_DEBUG_KTIMES = 6
+  MONO_DEBUG_KTIMES = 6,
+  MONO_DEBUG_TIME_DIFFUSION = 7
 };
 typedef struct {
   int32_t mode;          /* bit 0 record, bit 1 replay; 0 = off          */

@@ -424,8 +424,7 @@ static void launch_rows_k(const DiffArgs<T>& a, hipStream_t s) {
   const int64_t ngroups = (a.n + kWaveRows - 1) / kWaveRows;
   const int64_t per = (int64_t)(BLOCK / 64) * ITER;
   const dim3 grid((unsigned)((ngroups + per - 1) / per));
-  hipLaunchKernelGGL((k_diff_rows<T, P, BLOCK, ITER>), grid, dim3(BLOCK), 0, s, a, a.ctab,
-                     a.wcls);
+  launch_step_kernel(k_diff_rows<T, P, BLOCK, ITER>, grid, dim3(BLOCK), s, a, a.ctab, a.wcls);
 }
 template <typename T, int P, int BLOCK>
 static void launch_rows_i(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
@@ -444,7 +443,7 @@ template <typename T, int P, int BLOCK, int ITER>
 static void launch_classes_k(const DiffArgs<T>& a, hipStream_t s) {
   const int64_t per = (int64_t)BLOCK * ITER;
   const dim3 grid((unsigned)((a.n + per - 1) / per));
-  hipLaunchKernelGGL((k_diff_classes<T, P, BLOCK, ITER>), grid, dim3(BLOCK), 0, s, a);
+  launch_step_kernel(k_diff_classes<T, P, BLOCK, ITER>, grid, dim3(BLOCK), s, a);
 }
 template <typename T, int P, int BLOCK>
 static void launch_classes_i(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
@@ -467,7 +466,7 @@ template <typename T, int P, bool BATCHED, int BLOCK, int RPL>
 static void launch_stencil_k(const DiffArgs<T>& a, hipStream_t s) {
   const int64_t nlanes = (a.n + RPL - 1) / RPL;
   const dim3 grid((unsigned)((nlanes + BLOCK - 1) / BLOCK));
-  hipLaunchKernelGGL((k_diff_stencil<T, P, BATCHED, BLOCK, RPL>), grid, dim3(BLOCK), 0, s, a);
+  launch_step_kernel(k_diff_stencil<T, P, BATCHED, BLOCK, RPL>, grid, dim3(BLOCK), s, a);
 }
 
 template <typename T, int P, bool BATCHED, int BLOCK>
@@ -497,7 +496,7 @@ static void launch_stencil_p(const DiffArgs<T>& a, const LaunchCfg& c, hipStream
 template <typename T, bool BATCHED, int BLOCK>
 static void launch_ell_k(const DiffArgs<T>& a, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + BLOCK - 1) / BLOCK));
-  hipLaunchKernelGGL((k_diff_ell<T, BATCHED, BLOCK>), grid, dim3(BLOCK), 0, s, a);
+  launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK>, grid, dim3(BLOCK), s, a);
 }
 template <typename T, bool BATCHED>
 static void launch_ell_b(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {

@@ -188,9 +188,9 @@ template <typename T, class M, int BLOCK>
 static void launch_ionic_k(const IonArgs<T>& a, bool sort, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + BLOCK - 1) / BLOCK));
   if (sort)
-    hipLaunchKernelGGL((k_ionic<T, M, BLOCK, true>), grid, dim3(BLOCK), 0, s, a);
+    launch_step_kernel(k_ionic<T, M, BLOCK, true>, grid, dim3(BLOCK), s, a);
   else
-    hipLaunchKernelGGL((k_ionic<T, M, BLOCK, false>), grid, dim3(BLOCK), 0, s, a);
+    launch_step_kernel(k_ionic<T, M, BLOCK, false>, grid, dim3(BLOCK), s, a);
 }
 template <typename T, class M>
 static void launch_ionic_m(const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s) {

@@ -1,6 +1,7 @@
 // Internal declarations of libmono (host runtime <-> HIP kernels).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -20,6 +21,24 @@ __host__ __device__ __forceinline__ double rn_mul(double a, double b) {
 __host__ __device__ __forceinline__ double rn_add(double a, double b) {
 #pragma clang fp contract(off)
   return a + b;
+}
+
+// Per-kernel timing of eager steps: when set, the next step kernel is launched
+// with a start and a stop event that the command processor records at the
+// kernel's own begin and end (no event packets between kernels), then cleared.
+struct KernelTimer {
+  hipEvent_t start, stop;
+};
+extern thread_local KernelTimer* g_ktimer;
+
+template <typename F, typename... A>
+void launch_step_kernel(F kernel, dim3 grid, dim3 block, hipStream_t s, A... args) {
+  if (KernelTimer* t = g_ktimer) {
+    g_ktimer = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t->start, t->stop, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
 }
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)

@@ -117,6 +117,11 @@ struct mono_sim {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool g_valid = false;
+  // graph of a shorter run (the remainder of a step count that graph_steps
+  // does not divide)
+  hipGraph_t graph_r = nullptr;
+  hipGraphExec_t gexec_r = nullptr;
+  int64_t g_r_steps = 0;
   LaunchCfg lc;
   // debug
   KTraceArgs kt{};
@@ -156,6 +161,11 @@ void drop_graph(mono_sim* s) {
   s->gexec = nullptr;
   s->graph = nullptr;
   s->g_valid = false;
+  if (s->gexec_r) (void)hipGraphExecDestroy(s->gexec_r);
+  if (s->graph_r) (void)hipGraphDestroy(s->graph_r);
+  s->gexec_r = nullptr;
+  s->graph_r = nullptr;
+  s->g_r_steps = 0;
 }
 
 // upload n_host doubles into a device array of the simulation's precision
@@ -313,43 +323,45 @@ IonArgs<T> ion_args(mono_sim* s, void* V, int64_t g) {
 }
 
 // Enqueue `count` outer steps with clock offsets 0..count-1 and advance the
-// device clock by count.  With `ev` non-null every kernel is bracketed by a
-// pair of events (appended as {start, stop, class}).
+// device clock by count.  With `ev` non-null every step kernel is launched
+// with a start/stop event pair (appended as {start, stop, class}).
 struct TimedPair {
   hipEvent_t a, b;
   int cls;
 };
 
+}  // namespace
+
+thread_local KernelTimer* mono::g_ktimer = nullptr;
+
+namespace {
+
 template <typename T>
 void enqueue_steps(mono_sim* s, int64_t count, std::vector<TimedPair>* ev) {
   const int L = s->l_max;
   size_t next = 0;
-  auto mark = [&](int cls, bool start) {
+  KernelTimer kt{};
+  auto mark = [&](int cls) {
     if (!ev) return;
-    if (start) {
-      TimedPair p{s->ev_pool[next], s->ev_pool[next + 1], cls};
-      next += 2;
-      ev->push_back(p);
-      (void)hipEventRecord(p.a, s->stream);
-    } else {
-      (void)hipEventRecord(ev->back().b, s->stream);
-    }
+    TimedPair p{s->ev_pool[next], s->ev_pool[next + 1], cls};
+    next += 2;
+    ev->push_back(p);
+    kt = KernelTimer{p.a, p.b};
+    g_ktimer = &kt;
   };
   for (int64_t g = 0; g < count; ++g) {
     for (int m = 0; m < L; ++m) {
-      mark(0, true);
+      mark(0);
       launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->lc, s->stream);
-      mark(0, false);
     }
-    mark(1, true);
+    mark(1);
     launch_ionic<T>(s->model, ion_args<T>(s, s->d_V[L & 1], g), s->lc, s->stream);
-    mark(1, false);
     for (int m = 0; m < L; ++m) {
-      mark(0, true);
+      mark(0);
       launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
-      mark(0, false);
     }
   }
+  g_ktimer = nullptr;
   launch_advance_clock(s->d_base, count, s->stream);
 }
 
@@ -360,8 +372,8 @@ void enqueue(mono_sim* s, int64_t count, std::vector<TimedPair>* ev = nullptr) {
     enqueue_steps<float>(s, count, ev);
 }
 
-// Eager steps with every kernel timed by HIP events on the simulation's
-// stream (synchronising); adds to the per-class totals.
+// Eager steps with every step kernel timed by its own start/stop events
+// (synchronising); adds to the per-class totals.
 mono_status enqueue_timed(mono_sim* s, int64_t count) {
   const int64_t per_step = 2 * s->l_max + 1;
   const int64_t chunk = 64;
@@ -369,8 +381,11 @@ mono_status enqueue_timed(mono_sim* s, int64_t count) {
     const int64_t c = std::min(chunk, count - done);
     const size_t need = (size_t)(2 * per_step * c);
     while (s->ev_pool.size() < need) {
+      // timing-only events: no system-scope fence (cache writeback and
+      // invalidation) around the kernels they time; the stream is synchronised
+      // before they are read
       hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       s->ev_pool.push_back(e);
     }
     std::vector<TimedPair> ev;
@@ -389,6 +404,40 @@ mono_status enqueue_timed(mono_sim* s, int64_t count) {
   return MONO_OK;
 }
 
+// R diffusion substeps (first substep of the first half, clock offset 0)
+// alternating between the potential buffers, captured in one graph and timed
+// by events around its launch (after one untimed launch).
+mono_status time_diffusion(mono_sim* s, int64_t R, double& ms_per) {
+  HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  for (int64_t r = 0; r < R; ++r) {
+    if (s->prec == MONO_F64)
+      launch_diffusion<double>(s->layout, diff_args<double>(s, (int)(r & 1), 0, 0, 0), s->lc,
+                               s->stream);
+    else
+      launch_diffusion<float>(s->layout, diff_args<float>(s, (int)(r & 1), 0, 0, 0), s->lc,
+                              s->stream);
+  }
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamEndCapture(s->stream, &g));
+  hipGraphExec_t ge = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  mono_status st = MONO_OK;
+  float ms = 0.f;
+  if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipGraphLaunch(ge, s->stream) != hipSuccess ||
+      hipEventRecord(e0, s->stream) != hipSuccess || hipGraphLaunch(ge, s->stream) != hipSuccess ||
+      hipEventRecord(e1, s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess ||
+      hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    st = fail(MONO_EDEVICE, "diffusion timing failed");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ge) (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
+  ms_per = (double)ms / (double)R;
+  return st;
+}
+
 mono_status ensure_graph(mono_sim* s) {
   if (s->g_valid) return MONO_OK;
   drop_graph(s);
@@ -399,6 +448,25 @@ mono_status ensure_graph(mono_sim* s) {
   s->graph = g;
   HIP_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
   s->g_valid = true;
+  return MONO_OK;
+}
+
+// Graph of `steps` outer steps for the remainder of a run (cached while the
+// remainder length repeats).
+mono_status ensure_rem_graph(mono_sim* s, int64_t steps) {
+  if (s->g_r_steps == steps && s->gexec_r) return MONO_OK;
+  if (s->gexec_r) (void)hipGraphExecDestroy(s->gexec_r);
+  if (s->graph_r) (void)hipGraphDestroy(s->graph_r);
+  s->gexec_r = nullptr;
+  s->graph_r = nullptr;
+  s->g_r_steps = 0;
+  HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  enqueue(s, steps);
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamEndCapture(s->stream, &g));
+  s->graph_r = g;
+  HIP_TRY(hipGraphInstantiate(&s->gexec_r, s->graph_r, nullptr, nullptr, 0));
+  s->g_r_steps = steps;
   return MONO_OK;
 }
 
@@ -1032,7 +1100,16 @@ mono_status mono_step(mono_sim* s, int64_t n_steps, double dt, uint32_t flags) {
     return MONO_OK;
   }
   const int64_t chunk = s->lc.graph_steps;
-  if (!(flags & 1u) && left >= chunk) {
+  if (flags & 4u) {
+    // capture the graphs a graph-mode call of n_steps would replay; run nothing
+    if (flags & 1u) return fail(MONO_EINVAL, "capture-only needs graph mode");
+    st = ensure_graph(s);
+    if (st == MONO_OK && n_steps % chunk) st = ensure_rem_graph(s, n_steps % chunk);
+    return st;
+  }
+  if (!(flags & 1u) && left > 0) {
+    // the first graph-mode call captures the graph of graph_steps steps, so
+    // later calls launch it without capture work
     st = ensure_graph(s);
     if (st != MONO_OK) return st;
     while (left >= chunk) {
@@ -1040,7 +1117,15 @@ mono_status mono_step(mono_sim* s, int64_t n_steps, double dt, uint32_t flags) {
       left -= chunk;
     }
   }
-  if (left > 0) enqueue(s, left);
+  if (left > 0) {
+    if (flags & 1u) {
+      enqueue(s, left);
+    } else {
+      st = ensure_rem_graph(s, left);
+      if (st != MONO_OK) return st;
+      HIP_TRY(hipGraphLaunch(s->gexec_r, s->stream));
+    }
+  }
   HIP_TRY(hipGetLastError());
   s->step += n_steps;
   return MONO_OK;
@@ -1461,6 +1546,17 @@ mono_status mono_debug(mono_sim* s, int32_t what, void* arg) {
         s->klaunches[0] = s->klaunches[1] = 0;
       }
       return MONO_OK;
+    }
+    case MONO_DEBUG_TIME_DIFFUSION: {
+      if (!arg) return fail(MONO_EINVAL, "NULL argument");
+      double* o = (double*)arg;
+      const int64_t R = (int64_t)o[0];
+      if (R < 2 || R % 2 || R > 100000) return fail(MONO_EINVAL, "R must be even, 2..100000");
+      const mono_status ms = require_model(s);
+      if (ms != MONO_OK) return ms;
+      if (s->dt <= 0.0) return fail(MONO_ESTATE, "call mono_prepare first");
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      return time_diffusion(s, R, o[1]);
     }
     default:
       return fail(MONO_EINVAL, "unknown debug request");

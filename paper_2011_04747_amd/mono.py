@@ -22,7 +22,8 @@ FIELD_V, FIELD_VPREV, FIELD_LAT, FIELD_K, FIELD_STATE0 = 0, 1, 2, 3, 16
 DAETI, OSTAR, OST = 0, 1, 2
 DEBUG_KTRACE, DEBUG_VCLAMP, DEBUG_FORCE_L, DEBUG_STATS, DEBUG_STATS_ENABLE = 1, 2, 3, 4, 5
 DEBUG_KTIMES = 6
-STEP_EAGER, STEP_TIMED = 1, 2
+DEBUG_TIME_DIFFUSION = 7
+STEP_EAGER, STEP_TIMED, STEP_CAPTURE = 1, 2, 4
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSUPPORTED",
           -6: "ENONFINITE"}
@@ -345,3 +346,11 @@ class Sim:
         _check(lib().mono_debug(self.h, DEBUG_KTIMES, out))
         return dict(diffusion_ms=out[0], diffusion_launches=int(out[1]),
                     reaction_ms=out[2], reaction_launches=int(out[3]))
+
+    def time_diffusion(self, repetitions=384):
+        """Mean ms of one diffusion substep over `repetitions` (even) substeps
+        replayed as one HIP graph; advances the potential by them."""
+        out = (C.c_double * 2)()
+        out[0] = float(repetitions)
+        _check(lib().mono_debug(self.h, DEBUG_TIME_DIFFUSION, out))
+        return out[1]

@@ -370,6 +370,25 @@ def test_full_slab_graph_equals_eager(torch, full_slab):
     assert (a.state(5) == b.state(5)).all()
 
 
+def test_graph_remainders_and_capture_only(torch):
+    """Step counts that graph_steps does not divide replay a cached remainder
+    graph; STEP_CAPTURE captures without running; all equal eager stepping."""
+    w = W.slab_ischemic(shape=(27, 21, 9), t_end=20.0)
+    a = mono.Sim.from_workload(w, "f32")
+    b = mono.Sim.from_workload(w, "f32")
+    a.set_launch(graph_steps=16)
+    a.step(5, w.dt)
+    v0 = a.get(mono.FIELD_V)
+    a.step(37, w.dt, flags=mono.STEP_CAPTURE)
+    assert a.info()["step"] == 5 and (a.get(mono.FIELD_V) == v0).all()
+    for n in (37, 37, 3, 16):
+        a.step(n, w.dt)
+    b.step(5 + 37 + 37 + 3 + 16, w.dt, flags=mono.STEP_EAGER)
+    assert a.info()["step"] == b.info()["step"]
+    for f in (mono.FIELD_V, mono.FIELD_LAT, mono.FIELD_K):
+        assert (a.get(f) == b.get(f)).all()
+
+
 # ---------------------------------------------------------------------------
 # edge cases and failure handling
 # ---------------------------------------------------------------------------
