@@ -19,18 +19,21 @@ namespace mono {
 // --- loss at reaction entry -------------------------------------------------
 // out = sum_q (V[sensor_q] - target_q)^2 in FP64 (one workgroup)
 template <typename T>
-__global__ __launch_bounds__(256) void k_sensor_loss(const T* V, const int32_t* sens, int ns,
-                                                     const double* target, double* out) {
+__global__ __launch_bounds__(256) void k_sensor_loss(const T* V, SensorArgs a) {
+  const int64_t step = *a.clk.base + a.clk.g;
+  const bool on = step < a.target_steps;
+  const double* target = a.target + step * a.ns;
   __shared__ double part[4];
   double acc = 0.0;
-  for (int q = threadIdx.x; q < ns; q += 256) {
-    const double e = (double)V[sens[q]] - target[q];
-    acc += e * e;
-  }
+  if (on)
+    for (int q = threadIdx.x; q < a.ns; q += 256) {
+      const double e = (double)V[a.sens[q]] - target[q];
+      acc += e * e;
+    }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
+  if (threadIdx.x == 0) a.out[step - a.out_base] = part[0] + part[1] + part[2] + part[3];
 }
 
 // out[q] = V[sensor_q] (FP64)
@@ -43,12 +46,12 @@ __global__ __launch_bounds__(256) void k_sensor_sample(const T* V, const int32_t
 
 // lam_V[sensor_q] += 2 (V_entry[sensor_q] - target_q)   (sensors are distinct)
 template <typename T>
-__global__ __launch_bounds__(256) void k_sensor_inject(T* lamV, const T* V, const int32_t* sens,
-                                                       int ns, const double* target) {
+__global__ __launch_bounds__(256) void k_sensor_inject(T* lamV, const T* V, SensorArgs a) {
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= ns) return;
-  const int32_t i = sens[q];
-  lamV[i] = (T)((double)lamV[i] + 2.0 * ((double)V[i] - target[q]));
+  const int64_t step = *a.clk.base + a.clk.g;
+  if (q >= a.ns || step >= a.target_steps) return;
+  const int32_t i = a.sens[q];
+  lamV[i] = (T)((double)lamV[i] + 2.0 * ((double)V[i] - a.target[step * a.ns + q]));
 }
 
 // --- adjoint diffusion substep ------------------------------------------------
@@ -174,11 +177,13 @@ __global__ __launch_bounds__(256) void k_adj_ionic(AdjIonArgs<T> a) {
       M::substep(ys[q], p, h, false);
     }
     T lam[M::S];
-    for (int s = 0; s < M::S; ++s) lam[s] = a.lam[(int64_t)s * a.Np + i];
+    lam[0] = a.lamV[i];
+    for (int s = 1; s < M::S; ++s) lam[s] = a.lam[(int64_t)s * a.Np + i];
     T gp[M::P];
     for (int b = 0; b < M::P; ++b) gp[b] = T(0);
     for (int q = k - 1; q >= 0; --q) A::vjp(ys[q], p, h, lam, gp);
-    for (int s = 0; s < M::S; ++s) a.lam[(int64_t)s * a.Np + i] = lam[s];
+    a.lamV[i] = lam[0];
+    for (int s = 1; s < M::S; ++s) a.lam[(int64_t)s * a.Np + i] = lam[s];
     // derivative with respect to a common multiplier of each parameter row
     for (int b = 0; b < M::P; ++b) gpd[b] = (double)p[b] * (double)gp[b];
   }
@@ -209,16 +214,14 @@ void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_sensor_loss(const T* V, const int32_t* sens, int ns, const double* target,
-                        double* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_sensor_loss<T>), dim3(1), dim3(256), 0, s, V, sens, ns, target, out);
+void launch_sensor_loss(const T* V, const SensorArgs& a, hipStream_t s) {
+  if (a.ns <= 0) return;
+  hipLaunchKernelGGL((k_sensor_loss<T>), dim3(1), dim3(256), 0, s, V, a);
 }
 template <typename T>
-void launch_sensor_inject(T* lamV, const T* V, const int32_t* sens, int ns, const double* target,
-                          hipStream_t s) {
-  if (ns <= 0) return;
-  hipLaunchKernelGGL((k_sensor_inject<T>), dim3((ns + 255) / 256), dim3(256), 0, s, lamV, V, sens,
-                     ns, target);
+void launch_sensor_inject(T* lamV, const T* V, const SensorArgs& a, hipStream_t s) {
+  if (a.ns <= 0) return;
+  hipLaunchKernelGGL((k_sensor_inject<T>), dim3((a.ns + 255) / 256), dim3(256), 0, s, lamV, V, a);
 }
 
 template <typename T>
@@ -234,13 +237,10 @@ template void launch_adj_diffusion<float>(int, const AdjDiffArgs<float>&, hipStr
 template void launch_adj_diffusion<double>(int, const AdjDiffArgs<double>&, hipStream_t);
 template void launch_adj_ionic<float>(int, const AdjIonArgs<float>&, hipStream_t);
 template void launch_adj_ionic<double>(int, const AdjIonArgs<double>&, hipStream_t);
-template void launch_sensor_loss<float>(const float*, const int32_t*, int, const double*, double*,
-                                        hipStream_t);
-template void launch_sensor_loss<double>(const double*, const int32_t*, int, const double*,
-                                         double*, hipStream_t);
-template void launch_sensor_inject<float>(float*, const float*, const int32_t*, int,
-                                          const double*, hipStream_t);
-template void launch_sensor_inject<double>(double*, const double*, const int32_t*, int,
-                                           const double*, hipStream_t);
+template void launch_sensor_loss<float>(const float*, const SensorArgs&, hipStream_t);
+template void launch_sensor_loss<double>(const double*, const SensorArgs&, hipStream_t);
+template void launch_sensor_inject<float>(float*, const float*, const SensorArgs&, hipStream_t);
+template void launch_sensor_inject<double>(double*, const double*, const SensorArgs&,
+                                           hipStream_t);
 
 }  // namespace mono

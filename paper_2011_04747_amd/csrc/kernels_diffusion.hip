@@ -345,14 +345,15 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
       (row_block(nb, a.xcd) * WPB + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) *
       ITER;
   if (g0 >= ngroups) return;                // whole wavefront past the end
-  // row centres from the offsets (validated on the host)
+  // row centres (kernel arguments, so the loads below need no memory
+  // round trip for their addresses; validated on the host)
   int ctr[NC];
   ctr[0] = 0;
   if constexpr (P == 4) {
-    ctr[1] = a.off[2];
-    ctr[2] = -a.off[2];
+    ctr[1] = a.nx;
+    ctr[2] = -a.nx;
   } else if constexpr (P == 13) {
-    const int nx = a.off[2], nxy = a.off[8];
+    const int nx = a.nx, nxy = a.nxy;
     ctr[1] = nx;
     ctr[2] = nxy - nx;
     ctr[3] = nxy;
@@ -549,6 +550,12 @@ __global__ void k_advance_clock(int64_t* base, int64_t by) {
 }
 void launch_advance_clock(int64_t* base, int64_t by, hipStream_t s) {
   hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(64), 0, s, base, by);
+}
+__global__ void k_set_clock(int64_t* base, int64_t to) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *base = to;
+}
+void launch_set_clock(int64_t* base, int64_t to, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, base, to);
 }
 
 // ---------------------------------------------------------------------------

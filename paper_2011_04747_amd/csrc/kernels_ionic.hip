@@ -57,7 +57,7 @@ __device__ __forceinline__ int decide_k(const IonArgs<T>& a, int64_t i, int64_t 
   const T kd = (d > T(0) ? T(5) : T(1)) + xfloor(fabs(d));
   int k = (kd <= (T)a.k_max) ? (int)kd : a.k_max;
   if (a.kt.mode & 1) {
-    const int64_t r = step - a.kt.rec_base;
+    const int64_t r = a.kt.rec_rel ? a.clk.g : step - a.kt.rec_base;
     if (r >= 0 && r < a.kt.rec_steps) a.kt.rec[r * a.n + i] = (uint8_t)k;
   }
   if (a.kt.mode & 2) {
@@ -79,10 +79,12 @@ __device__ __forceinline__ void load_cell(const IonArgs<T>& a, int64_t i, T* y, 
 template <typename T, class M>
 __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t i, T* y, const T* p,
                                              int k) {
+  if (a.tape_st)
+    for (int s = 1; s < M::S; ++s) a.tape_st[(int64_t)(s - 1) * a.Np + i] = y[s];
   const T h = (T)(a.clk.dt / (double)k);
   const bool clamp = a.vclamp != 0;
   for (int s = 0; s < k; ++s) M::substep(y, p, h, clamp);
-  a.V[i] = y[0];
+  (a.Vout ? a.Vout : a.V)[i] = y[0];
   for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
 }
 
@@ -173,10 +175,12 @@ __global__ __launch_bounds__(BLOCK) void k_ionic(IonArgs<T> a) {
     for (int s = 1; s < M::S; ++s) y[s] = (a.st + (int64_t)(s - 1) * a.Np + b0)[j];
     for (int c = 0; c < M::P; ++c)
       p[c] = (a.par_pernode >> c & 1u) ? (a.par + (int64_t)c * a.Np + b0)[j] : a.par_uniform[c];
+    if (a.tape_st)
+      for (int s = 1; s < M::S; ++s) (a.tape_st + (int64_t)(s - 1) * a.Np + b0)[j] = y[s];
     const T h = (T)(a.clk.dt / (double)kn);
     const bool clamp = a.vclamp != 0;
     for (int s = 0; s < kn; ++s) M::substep(y, p, h, clamp);
-    (a.V + b0)[j] = y[0];
+    ((a.Vout ? a.Vout : a.V) + b0)[j] = y[0];
     for (int s = 1; s < M::S; ++s) (a.st + (int64_t)(s - 1) * a.Np + b0)[j] = y[s];
   } else {
     if (!live) return;

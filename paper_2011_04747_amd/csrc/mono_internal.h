@@ -153,6 +153,7 @@ struct DiffArgs {
   int tw;
   const int32_t* wcls;       // grid-row stencils: class of each wavefront's
                              // kWaveRows rows, or kNoClass; nullptr otherwise
+  int nx, nxy;               // grid-row stencils: offsets of the y and z rows
   // instances
   const int32_t* inst;       // per node, or nullptr for a single instance
   const int64_t* inst_off;   // n_inst + 1 first nodes of the instances
@@ -170,7 +171,8 @@ struct DiffArgs {
 
 struct KTraceArgs {
   int mode;                  // bit 0 record, bit 1 replay
-  uint8_t* rec;              // row (step - rec_base), n values per row
+  uint8_t* rec;              // row (step - rec_base), or row g if rec_rel, n values per row
+  int rec_rel;               // record rows by clock offset g (graph-replayed segments)
   const uint8_t* rep;        // row (step - rep_base)
   int64_t rec_base, rec_steps;
   int64_t rep_base, rep_steps;
@@ -179,7 +181,9 @@ struct KTraceArgs {
 template <typename T>
 struct IonArgs {
   int64_t n, Np;
-  T* V;
+  T* V;                      // potential in (and out unless Vout is set)
+  T* Vout;                   // potential out, or nullptr (in place)
+  T* tape_st;                // if set: (S - 1) * Np copy of the entry states
   T* st;                     // (S - 1) * Np
   T* vprev;
   double* lat;
@@ -228,7 +232,8 @@ struct AdjIonArgs {
   int64_t n, Np;
   const T* entry;            // S x Np reaction-entry state
   const uint8_t* k;          // n substep counts
-  T* lam;                    // S x Np adjoint (V first)
+  T* lam;                    // S x Np adjoint of the states (row 0 unused)
+  T* lamV;                   // Np adjoint of V
   const T* par;
   T par_uniform[kMaxParams];
   uint32_t par_pernode;
@@ -239,14 +244,23 @@ template <typename T>
 void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s);
 template <typename T>
 void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s);
+// sensors of the adjoint loss; the target row and the output slot follow the
+// device clock (step = *clk.base + clk.g), so graphs replay them correctly
+struct SensorArgs {
+  const int32_t* sens;
+  int ns;
+  const double* target;      // target_steps x ns
+  int64_t target_steps;      // steps at or past this have no target (no loss)
+  StepClock clk;
+  double* out;               // loss of step s goes to out[s - out_base]
+  int64_t out_base;
+};
 template <typename T>
-void launch_sensor_loss(const T* V, const int32_t* sens, int ns, const double* target,
-                        double* out, hipStream_t s);
+void launch_sensor_loss(const T* V, const SensorArgs& a, hipStream_t s);
 template <typename T>
 void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, hipStream_t s);
 template <typename T>
-void launch_sensor_inject(T* lamV, const T* V, const int32_t* sens, int ns, const double* target,
-                          hipStream_t s);
+void launch_sensor_inject(T* lamV, const T* V, const SensorArgs& a, hipStream_t s);
 
 template <typename T>
 void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s);
@@ -255,6 +269,7 @@ template <typename T>
 void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s);
 
 void launch_advance_clock(int64_t* base, int64_t by, hipStream_t s);
+void launch_set_clock(int64_t* base, int64_t to, hipStream_t s);
 
 // Gershgorin rows in FP64 on CSR: r_i = m_i/(k_ii + sum|k_ij|), g_i = 1/r_i,
 // then per-instance min r and max g.

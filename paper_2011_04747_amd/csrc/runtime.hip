@@ -81,6 +81,7 @@ struct mono_sim {
   void* d_ctab = nullptr;
   int tw = 0, n_classes = 0;
   int row_pattern = 0;             // stencil offsets are grid row triples
+  int grid_nx = 0, grid_nxy = 0;   // their y-row and z-plane offsets
   int32_t* d_wcls = nullptr;       // per-wavefront class of the row-sharing diffusion
   void* d_minv = nullptr;
   int32_t* d_off = nullptr;
@@ -278,6 +279,8 @@ DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   a.ctab = (const T*)s->d_ctab;
   a.tw = s->tw;
   a.wcls = s->d_wcls;
+  a.nx = s->grid_nx;
+  a.nxy = s->grid_nxy;
   a.e = (const T*)s->d_e;
   a.minv = (const T*)s->d_minv;
   a.off = s->d_off;
@@ -535,10 +538,11 @@ hipError_t save_state(mono_sim* s, void* dst) {
   return e;
 }
 
-hipError_t load_state(mono_sim* s, const void* src) {
+// V goes to Vdst (default: the simulation's potential)
+hipError_t load_state(mono_sim* s, const void* src, void* Vdst = nullptr) {
   const size_t b = s->Np * s->es;
   const char* d = (const char*)src;
-  hipError_t e = hipMemcpyAsync(s->d_V[0], d, b, hipMemcpyDeviceToDevice, s->stream);
+  hipError_t e = hipMemcpyAsync(Vdst ? Vdst : s->d_V[0], d, b, hipMemcpyDeviceToDevice, s->stream);
   if (!e && s->S > 1)
     e = hipMemcpyAsync(s->d_st, d + b, (size_t)(s->S - 1) * b, hipMemcpyDeviceToDevice, s->stream);
   if (!e) e = hipMemcpyAsync(s->d_vprev, d + (size_t)s->S * b, b, hipMemcpyDeviceToDevice, s->stream);
@@ -548,46 +552,68 @@ hipError_t load_state(mono_sim* s, const void* src) {
   return e;
 }
 
-// One outer step with clock offset g, optionally taping: the inputs of the
-// 2 l_max diffusion substeps (vsub), the reaction-entry state (entry), the k
-// each node takes (krec, row step - krec_base), and the loss at reaction
-// entry (loss_slot).
+// Sensor arguments for clock offset g: targets by device step, losses to
+// d_loss_steps[step - tape_step0].
+SensorArgs sensor_args(mono_sim* s, int64_t g) {
+  SensorArgs a{};
+  a.sens = s->d_sens;
+  a.ns = s->ns;
+  a.target = s->d_target;
+  a.target_steps = s->target_steps;
+  a.clk.base = s->d_base;
+  a.clk.g = g;
+  a.clk.dt = s->dt;
+  a.out = s->d_loss_steps;
+  a.out_base = s->tape_step0;
+  return a;
+}
+
+// One outer step with clock offset g that also stores the loss at reaction
+// entry (loss) and/or samples the sensors there (sample).
 template <typename T>
-void enqueue_taped_step(mono_sim* s, int64_t g, int64_t step, T* vsub, T* entry, uint8_t* krec,
-                        int64_t krec_base, int64_t krec_steps, double* loss_slot,
-                        double* sample = nullptr) {
+void enqueue_loss_step(mono_sim* s, int64_t g, bool loss, double* sample = nullptr) {
   const int L = s->l_max;
-  const size_t b = s->Np * s->es;
-  for (int m = 0; m < L; ++m) {
-    if (vsub)
-      (void)hipMemcpyAsync(vsub + (size_t)m * s->Np, s->d_V[m & 1], b, hipMemcpyDeviceToDevice,
-                           s->stream);
+  for (int m = 0; m < L; ++m)
     launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->lc, s->stream);
-  }
   T* Vmid = (T*)s->d_V[L & 1];
-  if (entry) {
-    (void)hipMemcpyAsync(entry, Vmid, b, hipMemcpyDeviceToDevice, s->stream);
-    if (s->S > 1)
-      (void)hipMemcpyAsync(entry + s->Np, s->d_st, (size_t)(s->S - 1) * b,
-                           hipMemcpyDeviceToDevice, s->stream);
-  }
-  if (loss_slot && s->ns > 0 && step < s->target_steps)
-    launch_sensor_loss<T>(Vmid, s->d_sens, s->ns, s->d_target + step * s->ns, loss_slot,
-                          s->stream);
+  if (loss && s->ns > 0) launch_sensor_loss<T>(Vmid, sensor_args(s, g), s->stream);
   if (sample) launch_sensor_sample<T>(Vmid, s->d_sens, s->ns, sample, s->stream);
-  IonArgs<T> ia = ion_args<T>(s, Vmid, g);
-  if (krec) {
-    ia.kt.mode |= 1;
-    ia.kt.rec = krec;
-    ia.kt.rec_base = krec_base;
-    ia.kt.rec_steps = krec_steps;
+  launch_ionic<T>(s->model, ion_args<T>(s, Vmid, g), s->lc, s->stream);
+  for (int m = 0; m < L; ++m)
+    launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
+}
+
+// One outer step of a segment recompute writing what the reverse sweep needs
+// straight into the segment tape: vs holds the inputs of the 2 l_max diffusion
+// substeps (vs[0], the step's starting potential, is already there; every
+// substep writes the next slot), entry the reaction-entry state (its V row
+// written by the last first-half substep, the other rows by the reaction
+// kernel as it loads them), krec the substep counts (row g); the last
+// substep writes vnext.
+template <typename T>
+void enqueue_tape_step(mono_sim* s, int64_t g, T* vs, T* entry, uint8_t* krec, int64_t krec_steps,
+                       T* vnext) {
+  const int L = s->l_max;
+  const size_t Np = s->Np;
+  for (int m = 0; m < L; ++m) {
+    DiffArgs<T> a = diff_args<T>(s, m, 0, m, g);
+    a.Vin = vs + (size_t)m * Np;
+    a.Vout = (m + 1 < L) ? vs + (size_t)(m + 1) * Np : entry;
+    launch_diffusion<T>(s->layout, a, s->lc, s->stream);
   }
+  IonArgs<T> ia = ion_args<T>(s, entry, g);
+  ia.Vout = vs + (size_t)L * Np;
+  ia.tape_st = entry + Np;
+  ia.kt.mode |= 1;
+  ia.kt.rec = krec;
+  ia.kt.rec_rel = 1;
+  ia.kt.rec_steps = krec_steps;
   launch_ionic<T>(s->model, ia, s->lc, s->stream);
   for (int m = 0; m < L; ++m) {
-    if (vsub)
-      (void)hipMemcpyAsync(vsub + (size_t)(L + m) * s->Np, s->d_V[(L + m) & 1], b,
-                           hipMemcpyDeviceToDevice, s->stream);
-    launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
+    DiffArgs<T> a = diff_args<T>(s, L + m, 1, m, g);
+    a.Vin = vs + (size_t)(L + m) * Np;
+    a.Vout = (m + 1 < L) ? vs + (size_t)(L + m + 1) * Np : vnext;
+    launch_diffusion<T>(s->layout, a, s->lc, s->stream);
   }
 }
 
@@ -616,18 +642,50 @@ AdjDiffArgs<T> adj_diff_args(mono_sim* s, const T* lam_in, T* lam_out, const T* 
   return a;
 }
 
+// Capture the work `body` enqueues on the simulation's stream as a graph.
+template <class F>
+mono_status capture_graph(mono_sim* s, F body, hipGraphExec_t* out) {
+  HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  body();
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamEndCapture(s->stream, &g));
+  const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(MONO_EDEVICE, "graph instantiation failed");
+  return MONO_OK;
+}
+
+struct GraphPair {
+  hipGraphExec_t full = nullptr, rest = nullptr;
+  ~GraphPair() {
+    if (full) (void)hipGraphExecDestroy(full);
+    if (rest) (void)hipGraphExecDestroy(rest);
+  }
+};
+
+// Taped forward run: the state at every segment start goes to a checkpoint,
+// then the segment's steps (with the loss at each reaction entry) replay as
+// one graph; the clock advances on the device.
 template <typename T>
 mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
   const int64_t C = s->ckpt_every;
   const int64_t nck = (n_steps + C - 1) / C;
+  const int64_t rest = n_steps % C;
+  GraphPair gp;
+  auto segment = [s](int64_t cn) {
+    return [s, cn]() {
+      for (int64_t t = 0; t < cn; ++t) enqueue_loss_step<T>(s, t, true);
+      launch_advance_clock(s->d_base, cn, s->stream);
+    };
+  };
+  mono_status st = MONO_OK;
+  if (n_steps >= C) st = capture_graph(s, segment(C), &gp.full);
+  if (st == MONO_OK && rest) st = capture_graph(s, segment(rest), &gp.rest);
+  if (st != MONO_OK) return st;
   for (int64_t c = 0; c < nck; ++c) {
     HIP_TRY(save_state(s, s->d_ckpt[c]));
-    const int64_t t0 = c * C, cn = std::min(C, n_steps - t0);
-    for (int64_t t = 0; t < cn; ++t)
-      enqueue_taped_step<T>(s, t, s->step + t, nullptr, nullptr, nullptr, 0, 0,
-                            s->d_loss_steps + t0 + t);
-    launch_advance_clock(s->d_base, cn, s->stream);
-    HIP_TRY(hipGetLastError());
+    const int64_t cn = std::min(C, n_steps - c * C);
+    HIP_TRY(hipGraphLaunch(cn == C ? gp.full : gp.rest, s->stream));
     s->step += cn;
   }
   HIP_TRY(save_state(s, s->d_final));
@@ -641,72 +699,84 @@ mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
   return MONO_OK;
 }
 
+// Reverse sweep.  Per segment, from the last: load its checkpoint (the
+// potential straight into the tape's first slot) and set the clock, then one
+// graph recomputes the segment, taping what the reverse needs, and runs the
+// reverse steps: adjoint diffusion substeps (the V adjoint ping-pongs between
+// two rows, an even number of times per step), adjoint reaction, sensor
+// injection.  Every segment of ckpt_every steps replays the same graph.
 template <typename T>
 mono_status backward_t(mono_sim* s) {
   const int64_t C = s->ckpt_every, N = s->tape_steps;
   const int64_t nck = (N + C - 1) / C;
+  const int64_t rest = N % C;
   const int L = s->l_max, S = s->S;
-  const size_t b = s->Np * s->es;
-  T* lamV = (T*)s->d_lam;
-  T* lamV2 = (T*)s->d_lamV2;
+  const size_t Np = s->Np;
+  T* const vsub = (T*)s->d_seg_vsub;
+  T* const ent = (T*)s->d_seg_entry;
+  auto segment = [=](int64_t cn) {
+    return [=]() {
+      for (int64_t t = 0; t < cn; ++t) {
+        T* vs = vsub + (size_t)t * 2 * L * Np;
+        T* vnext = (t + 1 < cn) ? vs + 2 * (size_t)L * Np : (T*)s->d_V[0];
+        enqueue_tape_step<T>(s, t, vs, ent + (size_t)t * S * Np, s->d_seg_k, cn, vnext);
+      }
+      T* lamV = (T*)s->d_lam;
+      T* lamW = (T*)s->d_lamV2;
+      for (int64_t t = cn - 1; t >= 0; --t) {
+        const T* vs = vsub + (size_t)t * 2 * L * Np;
+        const T* entry = ent + (size_t)t * S * Np;
+        for (int m = L - 1; m >= 0; --m) {
+          launch_adj_diffusion<T>(
+              s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)(L + m) * Np, m), s->stream);
+          std::swap(lamV, lamW);
+        }
+        AdjIonArgs<T> ai{};
+        ai.n = s->n;
+        ai.Np = s->Np;
+        ai.entry = entry;
+        ai.k = s->d_seg_k + (size_t)t * s->n;
+        ai.lam = (T*)s->d_lam;
+        ai.lamV = lamV;
+        ai.par = (const T*)s->d_par;
+        for (int q = 0; q < kMaxParams; ++q) ai.par_uniform[q] = (T)s->par_uniform[q];
+        ai.par_pernode = s->par_pernode;
+        ai.dt = s->dt;
+        ai.gpart = s->d_gpart;
+        launch_adj_ionic<T>(s->model, ai, s->stream);
+        if (s->ns > 0) launch_sensor_inject<T>(lamV, entry, sensor_args(s, t), s->stream);
+        for (int m = L - 1; m >= 0; --m) {
+          launch_adj_diffusion<T>(
+              s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)m * Np, m), s->stream);
+          std::swap(lamV, lamW);
+        }
+      }
+    };
+  };
+  GraphPair gp;
+  mono_status st = MONO_OK;
+  if (N >= C) st = capture_graph(s, segment(C), &gp.full);
+  if (st == MONO_OK && rest) st = capture_graph(s, segment(rest), &gp.rest);
+  if (st != MONO_OK) return st;
   for (int64_t c = nck - 1; c >= 0; --c) {
     const int64_t t0 = c * C, cn = std::min(C, N - t0);
-    const int64_t step0 = s->tape_step0 + t0;
-    // recompute the segment from its checkpoint, taping what the reverse needs
-    HIP_TRY(load_state(s, s->d_ckpt[c]));
-    HIP_TRY(hipMemcpyAsync(s->d_base, &step0, 8, hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    for (int64_t t = 0; t < cn; ++t)
-      enqueue_taped_step<T>(s, t, step0 + t, (T*)s->d_seg_vsub + (size_t)t * 2 * L * s->Np,
-                            (T*)s->d_seg_entry + (size_t)t * S * s->Np, s->d_seg_k, step0, cn,
-                            nullptr);
-    // reverse the segment
-    for (int64_t t = cn - 1; t >= 0; --t) {
-      const int64_t step = step0 + t;
-      const T* vs = (const T*)s->d_seg_vsub + (size_t)t * 2 * L * s->Np;
-      const T* entry = (const T*)s->d_seg_entry + (size_t)t * S * s->Np;
-      for (int m = L - 1; m >= 0; --m) {
-        launch_adj_diffusion<T>(s->layout, adj_diff_args<T>(s, lamV, lamV2, vs + (size_t)(L + m) * s->Np, m),
-                                s->stream);
-        HIP_TRY(hipMemcpyAsync(lamV, lamV2, b, hipMemcpyDeviceToDevice, s->stream));
-      }
-      AdjIonArgs<T> ai{};
-      ai.n = s->n;
-      ai.Np = s->Np;
-      ai.entry = entry;
-      ai.k = s->d_seg_k + (size_t)t * s->n;
-      ai.lam = lamV;
-      ai.par = (const T*)s->d_par;
-      for (int q = 0; q < kMaxParams; ++q) ai.par_uniform[q] = (T)s->par_uniform[q];
-      ai.par_pernode = s->par_pernode;
-      ai.dt = s->dt;
-      ai.gpart = s->d_gpart;
-      launch_adj_ionic<T>(s->model, ai, s->stream);
-      if (s->ns > 0 && step < s->target_steps)
-        launch_sensor_inject<T>(lamV, entry, s->d_sens, s->ns, s->d_target + step * s->ns,
-                                s->stream);
-      for (int m = L - 1; m >= 0; --m) {
-        launch_adj_diffusion<T>(s->layout, adj_diff_args<T>(s, lamV, lamV2, vs + (size_t)m * s->Np, m),
-                                s->stream);
-        HIP_TRY(hipMemcpyAsync(lamV, lamV2, b, hipMemcpyDeviceToDevice, s->stream));
-      }
-    }
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(load_state(s, s->d_ckpt[c], vsub));
+    launch_set_clock(s->d_base, s->tape_step0 + t0, s->stream);
+    HIP_TRY(hipGraphLaunch(cn == C ? gp.full : gp.rest, s->stream));
   }
+  HIP_TRY(hipGetLastError());
   // leave the simulation where the taped forward run ended
   HIP_TRY(load_state(s, s->d_final));
-  const int64_t endstep = s->tape_step0 + N;
-  HIP_TRY(hipMemcpyAsync(s->d_base, &endstep, 8, hipMemcpyHostToDevice, s->stream));
+  launch_set_clock(s->d_base, s->tape_step0 + N, s->stream);
   HIP_TRY(hipStreamSynchronize(s->stream));
-  s->step = endstep;
+  s->step = s->tape_step0 + N;
   return MONO_OK;
 }
 
 template <typename T>
 void sample_steps(mono_sim* s, int64_t n_steps, double* dbuf) {
   for (int64_t t = 0; t < n_steps; ++t)
-    enqueue_taped_step<T>(s, t, s->step + t, nullptr, nullptr, nullptr, 0, 0, nullptr,
-                          dbuf + t * s->ns);
+    enqueue_loss_step<T>(s, t, false, dbuf + t * s->ns);
   launch_advance_clock(s->d_base, n_steps, s->stream);
 }
 
@@ -872,6 +942,8 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
       s->n_classes = rc.n_classes;
       s->row_pattern = grid_row_pattern(sh.off) ? 1 : 0;
       if (s->row_pattern) {
+        s->grid_nx = sh.P >= 4 ? sh.off[2] : 0;
+        s->grid_nxy = sh.P >= 13 ? sh.off[8] : 0;
         // class shared by all kWaveRows rows of a wavefront, else kNoClass
         const int64_t nw = (s->n + kWaveRows - 1) / kWaveRows;
         std::vector<int32_t> wc(nw);
