@@ -12,6 +12,7 @@
 // private memory and applies the hand-written reverse substep backwards.
 #include "cell_models.h"
 #include "cell_models_adjoint.h"
+#include "grid_rows.h"
 #include "mono_internal.h"
 
 namespace mono {
@@ -91,6 +92,90 @@ __global__ __launch_bounds__(256) void k_adj_diff_stencil(AdjDiffArgs<T> a) {
   a.gsig[i] += dt_ad * (double)gs;
 }
 
+// The same substep adjoint on a structured grid with row classes: a
+// wavefront loads lambda, 1/m, V and sigma of each neighbouring grid row once
+// and passes x-neighbours between lanes (grid_rows.h); the edge weights come
+// from the class table (scalar loads when the wavefront's rows share a class).
+// Same arithmetic, in the same order, as k_adj_diff_stencil.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_adj_diff_rows(AdjDiffArgs<T> a,
+                                                       const T* __restrict__ ctab,
+                                                       const int32_t* __restrict__ wcls) {
+  using RP = RowPattern<P>;
+  constexpr int NC = RP::NC;
+  constexpr int WR = kWaveRows;
+  constexpr int ES = (int)sizeof(T);
+  const int n = (int)a.n;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int64_t row0 = wave * WR;
+  if (row0 >= a.n) return;
+  const int i = (int)row0 + lane - 1;
+  const bool produce = lane >= 1 && lane <= WR && i < n;
+  int ctr[NC];
+  ctr[0] = 0;
+  if constexpr (P == 4) {
+    ctr[1] = a.nx;
+    ctr[2] = -a.nx;
+  } else if constexpr (P == 13) {
+    ctr[1] = a.nx;
+    ctr[2] = a.nxy - a.nx;
+    ctr[3] = a.nxy;
+    ctr[4] = a.nxy + a.nx;
+    for (int k = 1; k < 5; ++k) ctr[4 + k] = -ctr[k];
+  }
+  T uc[NC], vc[NC], sc[NC], li = T(0);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const uint32_t bj = (uint32_t)(min(max(i + ctr[k], 0), n - 1) * ES);
+    const T lam = ld_bytes(a.lam_in, bj);
+    if (k == 0) li = lam;
+    uc[k] = lam * ld_bytes(a.minv, bj);
+    vc[k] = ld_bytes(a.V, bj);
+    sc[k] = ld_bytes(a.sigma, bj);
+  }
+  T ul[NC], ur[NC], vl[NC], vr[NC], sl[NC], sr[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    ul[k] = lane_shift<1>(uc[k]);
+    ur[k] = lane_shift<-1>(uc[k]);
+    vl[k] = lane_shift<1>(vc[k]);
+    vr[k] = lane_shift<-1>(vc[k]);
+    sl[k] = lane_shift<1>(sc[k]);
+    sr[k] = lane_shift<-1>(sc[k]);
+  }
+  auto pick = [](const T* c, const T* l, const T* r, int k, int d) -> T {
+    return d > 0 ? l[k] : (d < 0 ? r[k] : c[k]);
+  };
+  const T ui = uc[0], vi = vc[0], si = sc[0];
+  T acc = T(0), gs = T(0);
+  auto sweep = [&](auto w) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int kf = RP::fk(p), df = RP::fd(p), kb = RP::bk(p), db = RP::bd(p);
+      const T wf = w[p], wb = w[P + p];
+      const T uf = pick(uc, ul, ur, kf, df), ub = pick(uc, ul, ur, kb, db);
+      const T vf = pick(vc, vl, vr, kf, df), vb = pick(vc, vl, vr, kb, db);
+      const T sf = pick(sc, sl, sr, kf, df), sb = pick(sc, sl, sr, kb, db);
+      acc += wf * (uf - ui) + wb * (ub - ui);
+      gs += wf * xrcp(si + sf) * (ui - uf) * (vf - vi);
+      gs += wb * xrcp(si + sb) * (ui - ub) * (vb - vi);
+    }
+  };
+  const int wc = wcls[wave];
+  if (wc != kNoClass) {
+    using CT = const __attribute__((address_space(4))) T*;
+    sweep((CT)(ctab + (uint32_t)(wc * a.tw)));
+  } else {
+    const int ic = min(max(i, 0), n - 1);
+    sweep(ctab + (uint32_t)((int)a.cls[(uint32_t)ic] * a.tw));
+  }
+  if (!produce) return;
+  const double dt_ad = a.dt_ad[0];
+  a.lam_out[i] = li + (T)dt_ad * acc;
+  a.gsig[i] += dt_ad * (double)gs;
+}
+
 // ELL stores a_ij = e_ij / m_i, so e_ij = a_ij / (1/m_i).
 template <typename T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_adj_diff_ell(AdjDiffArgs<T> a) {
@@ -131,6 +216,18 @@ void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_adj_diff_ell<T, false>), grid, dim3(256), 0, s, a);
   } else {
+    if (a.wcls && !a.inst && (a.P == 1 || a.P == 4 || a.P == 13) &&
+        a.n * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+      const int64_t ngroups = (a.n + kWaveRows - 1) / kWaveRows;
+      const dim3 g2((unsigned)((ngroups + 3) / 4));
+      if (a.P == 1)
+        hipLaunchKernelGGL((k_adj_diff_rows<T, 1>), g2, dim3(256), 0, s, a, a.ctab, a.wcls);
+      else if (a.P == 4)
+        hipLaunchKernelGGL((k_adj_diff_rows<T, 4>), g2, dim3(256), 0, s, a, a.ctab, a.wcls);
+      else
+        hipLaunchKernelGGL((k_adj_diff_rows<T, 13>), g2, dim3(256), 0, s, a, a.ctab, a.wcls);
+      return;
+    }
     if (a.inst)
       hipLaunchKernelGGL((k_adj_diff_stencil<T, true>), grid, dim3(256), 0, s, a);
     else

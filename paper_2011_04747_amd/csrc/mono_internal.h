@@ -226,6 +226,13 @@ struct AdjDiffArgs {
   const double* dt_ad;
   int m;
   double* gsig;              // += dL/dsigma (FP64)
+  // grid-row stencils with row classes (single instance): class table and
+  // per-wavefront classes as in DiffArgs, or wcls = nullptr
+  const uint16_t* cls;
+  const T* ctab;
+  int tw;
+  const int32_t* wcls;
+  int nx, nxy;
 };
 template <typename T>
 struct AdjIonArgs {

@@ -639,6 +639,14 @@ AdjDiffArgs<T> adj_diff_args(mono_sim* s, const T* lam_in, T* lam_out, const T* 
   a.dt_ad = s->d_dtad;
   a.m = m;
   a.gsig = s->d_gsig;
+  if (s->d_wcls && s->lc.diff_classes && s->lc.diff_wave_rows) {
+    a.cls = s->d_cls;
+    a.ctab = (const T*)s->d_ctab;
+    a.tw = s->tw;
+    a.wcls = s->d_wcls;
+    a.nx = s->grid_nx;
+    a.nxy = s->grid_nxy;
+  }
   return a;
 }
 
