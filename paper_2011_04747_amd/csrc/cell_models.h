@@ -7,6 +7,7 @@
 // gates by Rush-Larsen (y <- y_inf + (y - y_inf) exp(-h/tau)), every other
 // variable by forward Euler.  State 0 is V.
 #pragma once
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 
@@ -149,10 +150,12 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   const T V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5], Rb = y[6];
   const T Ko = p[0];
   const T rtf = T(kRTF), frt = T(kFRT);
-  const T EK = rtf * xlog(xdiv(Ko, Ki));
-  const T ENa = rtf * xlog(xdiv(T(kNao), Nai));
-  const T ECa = T(0.5) * rtf * xlog(xdiv(T(kCao), Cai));
-  const T EKs = rtf * xlog(xdiv(Ko + T(kPKNa * kNao), Ki + T(kPKNa) * Nai));
+  // Nernst potentials as differences of logarithms (the logarithms of the
+  // parameter and constant concentrations do not change between substeps)
+  const T EK = rtf * (xlog(Ko) - xlog(Ki));
+  const T ENa = rtf * (T(4.941642422609304) - xlog(Nai));              // ln 140
+  const T ECa = T(0.5) * rtf * (T(0.6931471805599453) - xlog(Cai));    // ln 2
+  const T EKs = rtf * (xlog(Ko + T(kPKNa * kNao)) - xlog(Ki + T(kPKNa) * Nai));
   const T sqKo = xsqrt(Ko * T(1.0 / 5.4));
 
   const T m = y[7], hh = y[8], jj = y[9];
@@ -171,9 +174,17 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   // L-type Ca current with the removable singularity at V = 15 mV handled
   // through x / (e^x - 1)
   const T x = T(2) * (V - T(15)) * frt;
-  const T xe = (x == T(0)) ? T(1) : xdiv(x, xexpm1(x));
+  const T ex = xexp(x);
+  T xe;
+  if constexpr (std::is_same<T, float>::value) {
+    // FP32: x / (e^x - 1) from the e^x needed anyway, its Taylor series
+    // 1 - x/2 + x^2/12 where e^x - 1 would cancel (|x| < 1e-2)
+    xe = (fabsf(x) < 1e-2f) ? 1.0f + x * (-0.5f + x * (1.0f / 12.0f)) : xdiv(x, ex - 1.0f);
+  } else {
+    xe = (x == T(0)) ? T(1) : xdiv(x, xexpm1(x));
+  }
   c.ICaL = p[2] * T(kGCaL * 2.0 * kF) * y[15] * y[16] * y[17] * y[18] * xe *
-           (T(0.25) * Cass * xexp(x) - T(kCao));
+           (T(0.25) * Cass * ex - T(kCao));
 
   // e^{-VF/RT} serves the Na/Ca exchanger and the Na/K pump
   const T u = xexp(-V * frt);
@@ -203,16 +214,34 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   c.Ixfer = T(kVxfer) * (Cass - Cai);
 }
 
+// 1 / (1 + ez) for ez = e^z precomputed: the logistic factor sig(z)
+template <typename T>
+__host__ __device__ __forceinline__ T sig_e(T ez) {
+  return xrcp(T(1) + ez);
+}
+
 // Steady states and rates (1/tau) of the eleven V-driven TP06 gates, in the
-// state order m, h, j, xr1, xr2, xs, r, s, d, f, f2.
+// state order m, h, j, xr1, xr2, xs, r, s, d, f, f2.  Exponentials of V that
+// differ only by a constant factor are taken once (e^{a + bV} = e^a e^{bV}:
+// five shared powers replace fourteen exponentials), and the rates that are
+// reciprocals of products of logistic factors are formed directly as
+// products of (1 + e^z) (no reciprocal of a reciprocal).  Same functions as
+// the published forms; only the rounding differs.
 template <typename T>
 __host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) {
+  const T P5 = xexp(T(0.2) * V);             // e^{V/5}
+  const T N10 = xexp(T(-0.1) * V);           // e^{-V/10}
+  const T N20 = xexp(T(-0.05) * V);          // e^{-V/20}
+  const T P7 = xexp(V * T(1.0 / 7.0));       // e^{V/7}
+  const T N6 = xexp(V * T(-1.0 / 6.0));      // e^{-V/6}
   {
+    // m: alpha = sig(-(V+60)/5), beta = 0.1 sig((V+35)/5) + 0.1 sig((V-50)/200)
     const T e = sig((T(-56.86) - V) * T(1.0 / 9.03));
-    const T am = sig((T(-60) - V) * T(0.2));
-    const T bm = T(0.1) * sig((V + T(35)) * T(0.2)) + T(0.1) * sig((V - T(50)) * T(0.005));
+    const T ea = xexp((T(-60) - V) * T(0.2));
+    const T bm = T(0.1) * sig_e(T(1096.6331584284585) * P5) +       // e^7 e^{V/5}
+                 T(0.1) * sig((V - T(50)) * T(0.005));
     inf[0] = e * e;
-    rate[0] = xrcp(am * bm);
+    rate[0] = (T(1) + ea) * xrcp(bm);
   }
   {
     const T e = sig((V + T(71.55)) * T(1.0 / 7.43));
@@ -220,7 +249,8 @@ __host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) 
     inf[2] = e * e;
     if (V >= T(-40)) {
       rate[1] = T(0.77 / 0.13) * sig(-(V + T(10.66)) * T(1.0 / 11.1));
-      rate[2] = T(0.6) * xexp(T(0.057) * V) * sig(T(-0.1) * (V + T(32)));
+      rate[2] = T(0.6) * xexp(T(0.057) * V) *
+                sig_e(T(0.04076220397836621) * N10);                 // e^{-3.2} e^{-V/10}
     } else {
       rate[1] = T(0.057) * xexp(-(V + T(80)) * T(1.0 / 6.8)) + T(2.7) * xexp(T(0.079) * V) +
                 T(3.1e5) * xexp(T(0.3485) * V);
@@ -231,43 +261,45 @@ __host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) 
   }
   const T s30 = sig((V + T(30)) * T(0.1));    // shared by f and f2
   {
-    const T a1 = T(450) * sig((T(-45) - V) * T(0.1));
-    const T b1 = T(6) * sig((V + T(30)) * T(1.0 / 11.5));
+    // xr1: 1/(alpha beta), alpha = 450 sig(-(V+45)/10), beta = 6 sig((V+30)/11.5)
     inf[3] = sig((T(-26) - V) * T(1.0 / 7.0));
-    rate[3] = xrcp(a1 * b1);
-    const T a2 = T(3) * sig((T(-60) - V) * T(0.05));
-    const T b2 = T(1.12) * sig((V - T(60)) * T(0.05));
+    rate[3] = (T(1) + T(0.011108996538242306) * N10) *                // e^{-4.5} e^{-V/10}
+              (T(1) + xexp((V + T(30)) * T(1.0 / 11.5))) * T(1.0 / 2700.0);
+    // xr2: alpha = 3 sig(-(V+60)/20), beta = 1.12 sig((V-60)/20)
     inf[4] = sig((V + T(88)) * T(1.0 / 24.0));
-    rate[4] = xrcp(a2 * b2);
+    rate[4] = (T(1) + T(0.049787068367863944) * N20) *                // e^{-3} e^{-V/20}
+              (T(1) + xexp((V - T(60)) * T(0.05))) * T(1.0 / 3.36);
   }
   {
-    const T a = T(1400) * xrcp(xsqrt(T(1) + xexp((T(5) - V) * T(1.0 / 6.0))));
+    const T a = T(1400) * xrcp(xsqrt(T(1) + T(2.300975890892825) * N6));   // e^{5/6} e^{-V/6}
     const T b = sig((V - T(35)) * T(1.0 / 15.0));
     inf[5] = sig((T(-5) - V) * T(1.0 / 14.0));
     rate[5] = xrcp(a * b + T(80));
   }
   {
     const T vr = V + T(40), vs = V + T(45);
-    inf[6] = sig((T(20) - V) * T(1.0 / 6.0));
+    inf[6] = sig_e(T(28.03162489452614) * N6);                        // e^{20/6} e^{-V/6}
     rate[6] = xrcp(T(9.5) * xexp(-vr * vr * T(1.0 / 1800.0)) + T(0.8));
-    inf[7] = sig((V + T(20)) * T(0.2));
-    rate[7] = xrcp(T(85) * xexp(-vs * vs * T(1.0 / 320.0)) + T(5) * sig((V - T(20)) * T(0.2)) +
-                   T(3));
+    inf[7] = sig_e(T(54.598150033144236) * P5);                       // e^4 e^{V/5}
+    rate[7] = xrcp(T(85) * xexp(-vs * vs * T(1.0 / 320.0)) +
+                   T(5) * sig_e(T(0.01831563888873418) * P5) + T(3));  // e^{-4} e^{V/5}
   }
   {
     const T ad = T(1.4) * sig((T(-35) - V) * T(1.0 / 13.0)) + T(0.25);
-    const T bd = T(1.4) * sig((V + T(5)) * T(0.2));
-    const T gd = sig((T(50) - V) * T(0.05));
+    const T bd = T(1.4) * sig_e(T(2.718281828459045) * P5);            // e^1 e^{V/5}
+    const T gd = sig_e(T(12.182493960703473) * N20);                   // e^{2.5} e^{-V/20}
     inf[8] = sig((T(-8) - V) * T(1.0 / 7.5));
     rate[8] = xrcp(ad * bd + gd);
     const T vf = V + T(27);
-    inf[9] = sig((V + T(20)) * T(1.0 / 7.0));
+    inf[9] = sig_e(T(17.41170806332765) * P7);                         // e^{20/7} e^{V/7}
     rate[9] = xrcp(T(1102.5) * xexp(-vf * vf * T(1.0 / 225.0)) +
-                   T(200) * sig((T(13) - V) * T(0.1)) + T(180) * s30 + T(20));
+                   T(200) * sig_e(T(3.6692966676192444) * N10) +        // e^{1.3} e^{-V/10}
+                   T(180) * s30 + T(20));
     const T vf2 = V + T(25);
-    inf[10] = T(0.67) * sig((V + T(35)) * T(1.0 / 7.0)) + T(0.33);
+    inf[10] = T(0.67) * sig_e(T(148.4131591025766) * P7) + T(0.33);   // e^5 e^{V/7}
     rate[10] = xrcp(T(600) * xexp(-vf2 * vf2 * T(1.0 / 170.0)) +
-                    T(31) * sig((T(25) - V) * T(0.1)) + T(16) * s30);
+                    T(31) * sig_e(T(12.182493960703473) * N10) +        // e^{2.5} e^{-V/10}
+                    T(16) * s30);
   }
 }
 
