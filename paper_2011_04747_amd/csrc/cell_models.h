@@ -138,6 +138,15 @@ __host__ __device__ __forceinline__ T total_from_free(T c, T B, T K) {
   return c + xdiv(B * c, c + K);
 }
 
+// SR-calcium dependence of the RyR rates,
+// max - (max - min) / (1 + (EC/CaSR)^2) = max - (max - min) CaSR^2 / (CaSR^2 + EC^2)
+template <typename T>
+__host__ __device__ __forceinline__ T tp06_kcasr(T CaSR) {
+  using namespace tp06;
+  const T c2 = CaSR * CaSR;
+  return T(kMaxSR) - T(kMaxSR - kMinSR) * xdiv(c2, c2 + T(kEC * kEC));
+}
+
 template <typename T>
 struct TP06Fluxes {
   T Iion, INa, IbNa, INaK, INaCa, IK, ICaL, IbCa, IpCa;   // IK: K+ carrying currents
@@ -162,10 +171,12 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   c.INa = p[1] * T(kGNa) * m * m * m * hh * jj * (V - ENa);
 
   const T vk = V - EK;
-  const T aK1 = T(0.1) * sig(T(0.06) * (vk - T(200)));
+  // x_K1 = a/(a + b) with a = 0.1 sig(0.06 (vk - 200)) = 0.1/(1 + e_a):
+  // 1/(1 + 10 b (1 + e_a))
+  const T ea = xexp(T(0.06) * (vk - T(200)));
   const T bK1 = (T(3) * xexp(T(0.0002) * (vk + T(100))) + xexp(T(0.1) * (vk - T(10)))) *
                 sig(T(-0.5) * vk);
-  const T IK1 = p[5] * T(kGK1) * sqKo * xdiv(aK1, aK1 + bK1) * vk;
+  const T IK1 = p[5] * T(kGK1) * sqKo * xrcp(T(1) + T(10) * bK1 * (T(1) + ea)) * vk;
   const T Ito = T(kGto) * y[13] * y[14] * vk;
   const T IKr = p[3] * T(kGKr) * sqKo * y[10] * y[11] * vk;
   const T IKs = p[4] * T(kGKs) * y[12] * y[12] * (V - EKs);
@@ -203,11 +214,12 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   c.IK = IK1 + Ito + IKr + IKs + IpK;
   c.Iion = c.INa + c.IK + c.ICaL + c.INaCa + c.INaK + c.IpCa + c.IbNa + c.IbCa;
 
-  const T r_sr = xdiv(T(kEC), CaSR);
-  const T kcasr = T(kMaxSR) - T(kMaxSR - kMinSR) * xrcp(T(1) + r_sr * r_sr);
-  const T k1 = xdiv(T(kK1p), kcasr);
+  // open RyR fraction k1 cs^2 Rb / (k3 + k1 cs^2) with k1 = k1'/kcasr, taken
+  // with both terms multiplied by kcasr
+  const T kcasr = tp06_kcasr(CaSR);
   const T cs2 = Cass * Cass;
-  c.Irel = T(kVrel) * xdiv(k1 * cs2 * Rb, T(kK3) + k1 * cs2) * (CaSR - Cass);
+  const T k1cs2 = T(kK1p) * cs2;
+  c.Irel = T(kVrel) * xdiv(k1cs2 * Rb, T(kK3) * kcasr + k1cs2) * (CaSR - Cass);
   const T ci2 = Cai * Cai;
   c.Iup = T(kVmaxUp) * xdiv(ci2, ci2 + T(kKup * kKup));
   c.Ileak = T(kVleak) * (CaSR - Cai);
@@ -335,8 +347,7 @@ struct TP06Model {
     const T dCass = -c.ICaL * T(kCap / (2.0 * kVss * kF)) + T(kVsr / kVss) * c.Irel -
                     T(kVc / kVss) * c.Ixfer;
     const T dCaSR = c.Iup - c.Ileak - c.Irel;
-    const T r_sr = xdiv(T(kEC), y[5]);
-    const T kcasr = T(kMaxSR) - T(kMaxSR - kMinSR) * xrcp(T(1) + r_sr * r_sr);
+    const T kcasr = tp06_kcasr(y[5]);
     const T dRb = -T(kK2p) * kcasr * y[4] * y[6] + T(kK4) * (T(1) - y[6]);
 
     // gates from the substep-start V (and Ca_ss for fCass)
