@@ -95,8 +95,15 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t i, T* 
 // key), and lane t then advances the t-th node of that order, so a wavefront
 // mixes substep counts only where two keys meet.  Each node's arithmetic is
 // the same either way, so both give the same bits.
+// Occupancy floor for the register allocator: 7 wavefronts per SIMD (at most
+// 72 registers) for FP32, where the TP06 substep fits without spilling; no
+// floor in FP64.
+template <typename T>
+constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 7 : 1;
+
 template <typename T, class M, int BLOCK, bool SORT>
-__global__ __launch_bounds__(BLOCK) void k_ionic(IonArgs<T> a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kIonWavesPerEU<T>)))
+void k_ionic(IonArgs<T> a) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool live = i < a.n;
   const int64_t step = *a.clk.base + a.clk.g;
