@@ -93,11 +93,13 @@ __global__ __launch_bounds__(256) void k_adj_diff_stencil(AdjDiffArgs<T> a) {
 }
 
 // The same substep adjoint on a structured grid with row classes: a
-// wavefront loads lambda, 1/m, V and sigma of each neighbouring grid row once
-// and passes x-neighbours between lanes (grid_rows.h); the edge weights come
-// from the class table (scalar loads when the wavefront's rows share a class).
-// Same arithmetic, in the same order, as k_adj_diff_stencil.
-template <typename T, int P>
+// wavefront loads lambda, 1/m, V and sigma (unless uniform) of each
+// neighbouring grid row once and passes x-neighbours between lanes
+// (grid_rows.h); the edge weights come from the class table (scalar loads
+// when the wavefront's rows share a class).  Each wavefront produces ITER
+// consecutive groups of kWaveRows rows, loading all of them first.  Same
+// arithmetic, in the same order, as k_adj_diff_stencil.
+template <typename T, int P, int ITER, bool SIGU>
 __global__ __launch_bounds__(256) void k_adj_diff_rows(AdjDiffArgs<T> a,
                                                        const T* __restrict__ ctab,
                                                        const int32_t* __restrict__ wcls) {
@@ -107,11 +109,10 @@ __global__ __launch_bounds__(256) void k_adj_diff_rows(AdjDiffArgs<T> a,
   constexpr int ES = (int)sizeof(T);
   const int n = (int)a.n;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int64_t row0 = wave * WR;
-  if (row0 >= a.n) return;
-  const int i = (int)row0 + lane - 1;
-  const bool produce = lane >= 1 && lane <= WR && i < n;
+  const int64_t ngroups = (a.n + WR - 1) / WR;
+  const int64_t g0 =
+      ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) * ITER;
+  if (g0 >= ngroups) return;
   int ctr[NC];
   ctr[0] = 0;
   if constexpr (P == 4) {
@@ -124,56 +125,87 @@ __global__ __launch_bounds__(256) void k_adj_diff_rows(AdjDiffArgs<T> a,
     ctr[4] = a.nxy + a.nx;
     for (int k = 1; k < 5; ++k) ctr[4 + k] = -ctr[k];
   }
-  T uc[NC], vc[NC], sc[NC], li = T(0);
+  T uc[ITER][NC], vc[ITER][NC], sc[ITER][NC], li[ITER];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    const uint32_t bj = (uint32_t)(min(max(i + ctr[k], 0), n - 1) * ES);
-    const T lam = ld_bytes(a.lam_in, bj);
-    if (k == 0) li = lam;
-    uc[k] = lam * ld_bytes(a.minv, bj);
-    vc[k] = ld_bytes(a.V, bj);
-    sc[k] = ld_bytes(a.sigma, bj);
-  }
-  T ul[NC], ur[NC], vl[NC], vr[NC], sl[NC], sr[NC];
+  for (int it = 0; it < ITER; ++it) {
+    const int i = (int)((g0 + it) * WR) + lane - 1;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    ul[k] = lane_shift<1>(uc[k]);
-    ur[k] = lane_shift<-1>(uc[k]);
-    vl[k] = lane_shift<1>(vc[k]);
-    vr[k] = lane_shift<-1>(vc[k]);
-    sl[k] = lane_shift<1>(sc[k]);
-    sr[k] = lane_shift<-1>(sc[k]);
-  }
-  auto pick = [](const T* c, const T* l, const T* r, int k, int d) -> T {
-    return d > 0 ? l[k] : (d < 0 ? r[k] : c[k]);
-  };
-  const T ui = uc[0], vi = vc[0], si = sc[0];
-  T acc = T(0), gs = T(0);
-  auto sweep = [&](auto w) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int kf = RP::fk(p), df = RP::fd(p), kb = RP::bk(p), db = RP::bd(p);
-      const T wf = w[p], wb = w[P + p];
-      const T uf = pick(uc, ul, ur, kf, df), ub = pick(uc, ul, ur, kb, db);
-      const T vf = pick(vc, vl, vr, kf, df), vb = pick(vc, vl, vr, kb, db);
-      const T sf = pick(sc, sl, sr, kf, df), sb = pick(sc, sl, sr, kb, db);
-      acc += wf * (uf - ui) + wb * (ub - ui);
-      gs += wf * xrcp(si + sf) * (ui - uf) * (vf - vi);
-      gs += wb * xrcp(si + sb) * (ui - ub) * (vb - vi);
+    for (int k = 0; k < NC; ++k) {
+      const uint32_t bj = (uint32_t)(min(max(i + ctr[k], 0), n - 1) * ES);
+      const T lam = ld_bytes(a.lam_in, bj);
+      if (k == 0) li[it] = lam;
+      uc[it][k] = lam * ld_bytes(a.minv, bj);
+      vc[it][k] = ld_bytes(a.V, bj);
+      sc[it][k] = SIGU ? a.sig_val : ld_bytes(a.sigma, bj);
     }
-  };
-  const int wc = wcls[wave];
-  if (wc != kNoClass) {
-    using CT = const __attribute__((address_space(4))) T*;
-    sweep((CT)(ctab + (uint32_t)(wc * a.tw)));
-  } else {
-    const int ic = min(max(i, 0), n - 1);
-    sweep(ctab + (uint32_t)((int)a.cls[(uint32_t)ic] * a.tw));
   }
-  if (!produce) return;
   const double dt_ad = a.dt_ad[0];
-  a.lam_out[i] = li + (T)dt_ad * acc;
-  a.gsig[i] += dt_ad * (double)gs;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int64_t g = g0 + it;
+    if (g >= ngroups) break;
+    const int i = (int)(g * WR) + lane - 1;
+    const bool produce = lane >= 1 && lane <= WR && i < n;
+    T ul[NC], ur[NC], vl[NC], vr[NC], sl[NC], sr[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      ul[k] = lane_shift<1>(uc[it][k]);
+      ur[k] = lane_shift<-1>(uc[it][k]);
+      vl[k] = lane_shift<1>(vc[it][k]);
+      vr[k] = lane_shift<-1>(vc[it][k]);
+      sl[k] = SIGU ? sc[it][k] : lane_shift<1>(sc[it][k]);
+      sr[k] = SIGU ? sc[it][k] : lane_shift<-1>(sc[it][k]);
+    }
+    auto pick = [](const T* c, const T* l, const T* r, int k, int d) -> T {
+      return d > 0 ? l[k] : (d < 0 ? r[k] : c[k]);
+    };
+    const T ui = uc[it][0], vi = vc[it][0], si = sc[it][0];
+    T acc = T(0), gs = T(0);
+    auto sweep = [&](auto w) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int kf = RP::fk(p), df = RP::fd(p), kb = RP::bk(p), db = RP::bd(p);
+        const T wf = w[p], wb = w[P + p];
+        const T uf = pick(uc[it], ul, ur, kf, df), ub = pick(uc[it], ul, ur, kb, db);
+        const T vf = pick(vc[it], vl, vr, kf, df), vb = pick(vc[it], vl, vr, kb, db);
+        const T sf = pick(sc[it], sl, sr, kf, df), sb = pick(sc[it], sl, sr, kb, db);
+        acc += wf * (uf - ui) + wb * (ub - ui);
+        gs += wf * xrcp(si + sf) * (ui - uf) * (vf - vi);
+        gs += wb * xrcp(si + sb) * (ui - ub) * (vb - vi);
+      }
+    };
+    const int wc = wcls[g];
+    if (wc != kNoClass) {
+      using CT = const __attribute__((address_space(4))) T*;
+      sweep((CT)(ctab + (uint32_t)(wc * a.tw)));
+    } else {
+      const int ic = min(max(i, 0), n - 1);
+      sweep(ctab + (uint32_t)((int)a.cls[(uint32_t)ic] * a.tw));
+    }
+    if (produce) {
+      a.lam_out[i] = li[it] + (T)dt_ad * acc;
+      a.gsig[i] += dt_ad * (double)gs;
+    }
+  }
+}
+
+template <typename T, int P, int ITER>
+static void launch_adj_rows_k(const AdjDiffArgs<T>& a, hipStream_t s) {
+  const int64_t ngroups = (a.n + kWaveRows - 1) / kWaveRows;
+  const dim3 grid((unsigned)((ngroups + 4 * ITER - 1) / (4 * ITER)));
+  if (a.sig_uni)
+    hipLaunchKernelGGL((k_adj_diff_rows<T, P, ITER, true>), grid, dim3(256), 0, s, a, a.ctab,
+                       a.wcls);
+  else
+    hipLaunchKernelGGL((k_adj_diff_rows<T, P, ITER, false>), grid, dim3(256), 0, s, a, a.ctab,
+                       a.wcls);
+}
+template <typename T, int P>
+static void launch_adj_rows_p(const AdjDiffArgs<T>& a, hipStream_t s) {
+  if (a.iter >= 2)
+    launch_adj_rows_k<T, P, 2>(a, s);
+  else
+    launch_adj_rows_k<T, P, 1>(a, s);
 }
 
 // ELL stores a_ij = e_ij / m_i, so e_ij = a_ij / (1/m_i).
@@ -218,14 +250,12 @@ void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s) {
   } else {
     if (a.wcls && !a.inst && (a.P == 1 || a.P == 4 || a.P == 13) &&
         a.n * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
-      const int64_t ngroups = (a.n + kWaveRows - 1) / kWaveRows;
-      const dim3 g2((unsigned)((ngroups + 3) / 4));
       if (a.P == 1)
-        hipLaunchKernelGGL((k_adj_diff_rows<T, 1>), g2, dim3(256), 0, s, a, a.ctab, a.wcls);
+        launch_adj_rows_p<T, 1>(a, s);
       else if (a.P == 4)
-        hipLaunchKernelGGL((k_adj_diff_rows<T, 4>), g2, dim3(256), 0, s, a, a.ctab, a.wcls);
+        launch_adj_rows_p<T, 4>(a, s);
       else
-        hipLaunchKernelGGL((k_adj_diff_rows<T, 13>), g2, dim3(256), 0, s, a, a.ctab, a.wcls);
+        launch_adj_rows_p<T, 13>(a, s);
       return;
     }
     if (a.inst)

@@ -233,6 +233,9 @@ struct AdjDiffArgs {
   int tw;
   const int32_t* wcls;
   int nx, nxy;
+  int iter;                  // row groups per wavefront (1 or 2)
+  int sig_uni;               // every sigma equals sig_val (no sigma loads)
+  T sig_val;
 };
 template <typename T>
 struct AdjIonArgs {

@@ -135,6 +135,8 @@ struct mono_sim {
   int64_t klaunches[2] = {0, 0};
   // adjoint: conductivity scales, loss sensors, checkpoints and segment tape
   void* d_sigma = nullptr;         // Np, simulation precision
+  int sigma_uniform = 0;           // every node has sigma_value (in precision T)
+  double sigma_value = 1.0;
   int32_t* d_sens = nullptr;
   int ns = 0;
   double* d_target = nullptr;      // target_steps x ns
@@ -646,6 +648,9 @@ AdjDiffArgs<T> adj_diff_args(mono_sim* s, const T* lam_in, T* lam_out, const T* 
     a.wcls = s->d_wcls;
     a.nx = s->grid_nx;
     a.nxy = s->grid_nxy;
+    a.iter = s->lc.diff_rpl >= 2 ? 2 : 1;
+    a.sig_uni = s->sigma_uniform;
+    a.sig_val = (T)s->sigma_value;
   }
   return a;
 }
@@ -913,6 +918,14 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
   {
     std::vector<double> sg(s->Np, 1.0);
     if (d->sigma_node) std::copy(d->sigma_node, d->sigma_node + s->n, sg.begin());
+    {
+      // uniform in the simulation precision (padding rows hold 1 and are never read)
+      auto rnd = [s](double v) { return s->prec == MONO_F32 ? (double)(float)v : v; };
+      s->sigma_value = rnd(sg[0]);
+      s->sigma_uniform = 1;
+      for (int64_t i = 1; i < s->n && s->sigma_uniform; ++i)
+        if (rnd(sg[i]) != s->sigma_value) s->sigma_uniform = 0;
+    }
     if (dalloc((char**)&s->d_sigma, s->Np * s->es))
       return bail(fail(MONO_ENOMEM, "device allocation failed"));
     mono_status st = upload_real(s, s->d_sigma, sg.data(), sg.size());

@@ -111,20 +111,24 @@ def test_adjoint_fp32_against_fp64_oracle(torch, kind):
     assert Lg == pytest.approx(Lo, rel=1e-3)
 
 
+@pytest.mark.parametrize("sigma", ["uniform", "two_regions"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_adjoint_row_sharing_equals_per_row_stencil(torch, prec):
+def test_adjoint_row_sharing_equals_per_row_stencil(torch, prec, sigma):
     """The adjoint diffusion that shares neighbour rows across lanes (row
     classes on a grid) gives the bits of the per-row stencil kernel in FP32;
     in FP64 the compiler fuses the two kernels' products differently, so they
     agree to rounding (1e-12 of the largest gradient)."""
     w = W.adjoint_slab(shape=(29, 23, 9), dx=2.0 ** -7, t_end=6.0, n_sensors=40)
+    if sigma == "two_regions":
+        # piecewise-constant conductivity: rows still repeat within each region
+        w.mesh.sigma = np.where(w.mesh.xyz[:, 0] < 0.1, 1.0, 0.5)
     rng = np.random.default_rng(11)
     target = -80.0 + rng.uniform(-0.2, 0.2, (w.n_steps, len(w.sensors)))
     out = []
     for rows in (1, 0):
         s = mono.Sim.from_workload(w, prec)
         assert s.info()["grid_rows"] == 1
-        s.set_launch(diff_wave_rows=rows)
+        s.set_launch(diff_wave_rows=rows, diff_rows_per_lane=2 if rows else 1)
         s.set_sensors(w.sensors, target)
         L = s.forward_taped(w.n_steps, w.dt, 7)
         gs, gp = s.backward()
