@@ -14,6 +14,7 @@
 #include "cell_models_adjoint.h"
 #include "grid_rows.h"
 #include "mono_internal.h"
+#include "wg_sort.h"
 
 namespace mono {
 
@@ -285,10 +286,21 @@ struct TP06Adj {
   }
 };
 
-template <typename T, class M, class A>
+// SORT: the workgroup's nodes are taken in order of their substep count k
+// (wg_sort.h), so a wavefront replays and reverses one k where it can; the
+// per-node arithmetic is unchanged (only the order of the FP64 workgroup sum
+// of the parameter gradients differs).
+template <typename T, class M, class A, bool SORT>
 __global__ __launch_bounds__(256) void k_adj_ionic(AdjIonArgs<T> a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool live = i < a.n;
+  const int64_t b0 = (int64_t)blockIdx.x * 256;
+  int64_t i = b0 + threadIdx.x;
+  bool live = i < a.n;
+  if constexpr (SORT) {
+    __shared__ int slot_node[256];
+    wg_order_by_key<256, kAdjMaxK + 1>(live ? min((int)a.k[i], kAdjMaxK) : -1, slot_node);
+    live = (int64_t)threadIdx.x < a.n - b0;
+    if (live) i = b0 + slot_node[threadIdx.x];
+  }
   double gpd[M::P];
   for (int b = 0; b < M::P; ++b) gpd[b] = 0.0;
   if (live) {
@@ -333,11 +345,13 @@ void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s) {
   if (a.n <= 0) return;
   const dim3 grid((unsigned)((a.n + 255) / 256));
   if (model == MONO_MODEL_LINEAR)
-    hipLaunchKernelGGL((k_adj_ionic<T, LinearModel, LinearAdj>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_adj_ionic<T, LinearModel, LinearAdj, false>), grid, dim3(256), 0, s, a);
   else if (model == MONO_MODEL_MS)
-    hipLaunchKernelGGL((k_adj_ionic<T, MSModel, MSAdj>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_adj_ionic<T, MSModel, MSAdj, false>), grid, dim3(256), 0, s, a);
+  else if (a.sort)
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06Model, TP06Adj, true>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_adj_ionic<T, TP06Model, TP06Adj>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06Model, TP06Adj, false>), grid, dim3(256), 0, s, a);
 }
 
 template <typename T>

@@ -13,6 +13,7 @@
 // reaction entry, linearly interpolated) is kept in FP64 in every precision.
 #include "cell_models.h"
 #include "mono_internal.h"
+#include "wg_sort.h"
 
 namespace mono {
 
@@ -141,43 +142,17 @@ void k_ionic(IonArgs<T> a) {
     }
   }
   if constexpr (SORT) {
-    constexpr int W = BLOCK / 64;
-    constexpr int NK = kSortMaxK + 1;
-    __shared__ int wcount[NK][W];   // nodes of key q in wavefront w, then their start
     __shared__ int slot_node[BLOCK];
-    __shared__ unsigned char slot_k[BLOCK];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = live ? min(k, kSortMaxK) : -1;
-    unsigned long long mine = 0ull;
-    for (int kk = 0; kk < NK; ++kk) {
-      const unsigned long long m = __ballot(q == kk);
-      if (q == kk) mine = m;
-      if (lane == 0) wcount[kk][w] = __popcll(m);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = 0;
-      for (int kk = 0; kk < NK; ++kk)
-        for (int v = 0; v < W; ++v) {
-          const int c = wcount[kk][v];
-          wcount[kk][v] = run;
-          run += c;
-        }
-    }
-    __syncthreads();
-    if (live) {
-      const int pos = wcount[q][w] + __popcll(mine & ((1ull << lane) - 1ull));
-      slot_node[pos] = (int)threadIdx.x;
-      slot_k[pos] = (unsigned char)k;   // k <= 255 (k_max is capped there)
-    }
-    __syncthreads();
+    __shared__ unsigned char node_k[BLOCK];
+    node_k[threadIdx.x] = (unsigned char)k;   // k <= 255 (k_max is capped there)
+    wg_order_by_key<BLOCK, kSortMaxK + 1>(live ? min(k, kSortMaxK) : -1, slot_node);
     const int64_t n_here = min((int64_t)BLOCK, a.n - (int64_t)blockIdx.x * BLOCK);
     if ((int64_t)threadIdx.x >= n_here) return;
     // the node's rows addressed from the workgroup's (uniform) first node by
     // a 32-bit lane offset
     const int64_t b0 = (int64_t)blockIdx.x * BLOCK;
     const uint32_t j = (uint32_t)slot_node[threadIdx.x];
-    const int kn = slot_k[threadIdx.x];
+    const int kn = node_k[j];
     y[0] = (a.V + b0)[j];
     for (int s = 1; s < M::S; ++s) y[s] = (a.st + (int64_t)(s - 1) * a.Np + b0)[j];
     for (int c = 0; c < M::P; ++c)

@@ -249,6 +249,7 @@ struct AdjIonArgs {
   uint32_t par_pernode;
   double dt;
   double* gpart;             // per workgroup kMaxParams FP64 partial sums
+  int sort;                  // take each workgroup's nodes in order of k
 };
 template <typename T>
 void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s);

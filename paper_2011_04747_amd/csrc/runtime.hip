@@ -756,6 +756,7 @@ mono_status backward_t(mono_sim* s) {
         ai.par_pernode = s->par_pernode;
         ai.dt = s->dt;
         ai.gpart = s->d_gpart;
+        ai.sort = s->lc.react_sort;
         launch_adj_ionic<T>(s->model, ai, s->stream);
         if (s->ns > 0) launch_sensor_inject<T>(lamV, entry, sensor_args(s, t), s->stream);
         for (int m = L - 1; m >= 0; --m) {

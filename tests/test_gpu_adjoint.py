@@ -141,6 +141,25 @@ def test_adjoint_row_sharing_equals_per_row_stencil(torch, prec, sigma):
             assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_adjoint_k_ordered_reaction(torch, prec):
+    """Forward and adjoint reaction kernels that take each workgroup's nodes in
+    order of k: per-node results are the same bits (loss, sigma gradient);
+    the scaling gradients' FP64 workgroup sums only change order."""
+    w, target = _problem("tp06")
+    out = []
+    for srt in (0, 1):
+        s = mono.Sim.from_workload(w, prec)
+        s.set_launch(react_sort=srt)
+        s.set_sensors(w.sensors, target)
+        L = s.forward_taped(w.n_steps, w.dt, 9)
+        gs, gp = s.backward()
+        out.append((L, gs, gp))
+    assert out[0][0] == out[1][0]
+    assert (out[0][1] == out[1][1]).all()
+    assert np.abs(out[0][2] - out[1][2]).max() <= 1e-12 * np.abs(out[1][2]).max()
+
+
 def test_autograd_function(torch):
     from paper_2011_04747_amd.adjoint import TP06_SCALING_ROWS, AdjointProblem, mono_adjoint_fn
     w, target = _problem("tp06")
