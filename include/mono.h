@@ -233,6 +233,17 @@ mono_status mono_set_stream(mono_sim *sim, void *stream);
 /* Wait for the simulation's stream; reports MONO_ENONFINITE if latched. */
 mono_status mono_sync(mono_sim *sim);
 
+/* Device memory hook (process-wide): every device buffer of a simulation is
+ * then obtained from alloc(bytes, ctx) and returned with free_(ptr, ctx)
+ * instead of hipMalloc / hipFree, e.g. so that a framework's caching
+ * allocator owns it.  alloc must return device memory of the current device,
+ * aligned to 256 bytes, or NULL (the calling function then fails with
+ * MONO_ENOMEM); the library synchronises its stream before it frees a buffer.
+ * Both NULL restores hipMalloc / hipFree.  Only while no simulation exists
+ * (MONO_ESTATE otherwise); one NULL of the two is MONO_EINVAL. */
+mono_status mono_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                               void (*free_)(void *ptr, void *ctx), void *ctx);
+
 void mono_destroy(mono_sim *sim);
 const char *mono_last_error(void);
 

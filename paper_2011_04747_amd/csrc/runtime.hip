@@ -7,6 +7,7 @@
 // graph of a chunk of outer steps so that per-launch host overhead is paid
 // once per chunk.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -32,16 +33,37 @@ mono_status fail(mono_status s, const std::string& m) {
       return fail(MONO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
+// Device memory comes from hipMalloc or from the caller's allocator hook
+// (mono_set_allocator), which may only change while no simulation exists.
+struct DeviceAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free_)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+DeviceAllocator g_alloc;
+std::atomic<int64_t> g_live_sims{0};
+
 template <typename T>
 hipError_t dalloc(T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
+  if (g_alloc.alloc) {
+    void* q = g_alloc.alloc(count * sizeof(T), g_alloc.ctx);
+    if (!q) return hipErrorOutOfMemory;
+    *p = (T*)q;
+    return hipSuccess;
+  }
   return hipMalloc((void**)p, count * sizeof(T));
 }
 
 template <typename T>
 void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+  if (p) {
+    if (g_alloc.free_)
+      g_alloc.free_((void*)p, g_alloc.ctx);
+    else
+      (void)hipFree((void*)p);
+  }
   p = nullptr;
 }
 
@@ -824,6 +846,7 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
       if (off[q + 1] <= off[q]) return fail(MONO_EINVAL, "empty or decreasing instance");
   }
   mono_sim* s = new mono_sim();
+  g_live_sims.fetch_add(1);
   s->prec = d->prec;
   s->es = d->prec == MONO_F64 ? 8 : 4;
   s->dim = d->dim;
@@ -1003,6 +1026,18 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
   return MONO_OK;
 }
 
+mono_status mono_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
+                               void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return fail(MONO_EINVAL, "give both allocator functions or neither");
+  if (g_live_sims.load() != 0)
+    return fail(MONO_ESTATE, "the allocator can change only while no simulation exists");
+  g_alloc.alloc = alloc;
+  g_alloc.free_ = free_;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return MONO_OK;
+}
+
 void mono_destroy(mono_sim* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
@@ -1031,6 +1066,7 @@ void mono_destroy(mono_sim* s) {
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
+  g_live_sims.fetch_sub(1);
 }
 
 mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,

@@ -36,7 +36,7 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
            "mono_model_flops", "mono_set_launch", "mono_get_launch",
            "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
-           "mono_forward_taped", "mono_backward", "mono_sample_sensors")
+           "mono_forward_taped", "mono_backward", "mono_sample_sensors", "mono_set_allocator")
 
 
 class MonoError(RuntimeError):
@@ -77,6 +77,35 @@ class KTrace(C.Structure):
 _lib = None
 
 
+# device-memory hook of mono_set_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocator_refs = None   # keeps the installed callbacks alive
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through alloc(nbytes) -> int
+    pointer and free(ptr) (both Python callables), or back to hipMalloc /
+    hipFree with no arguments.  Only while no simulation exists."""
+    global _allocator_refs
+    if alloc is None and free is None:
+        _check(lib().mono_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator_refs = None
+        return
+    fa = ALLOC_FN(lambda nbytes, ctx: int(alloc(int(nbytes))) or None)
+    ff = FREE_FN(lambda ptr, ctx: free(int(ptr)))
+    _check(lib().mono_set_allocator(fa, ff, None))
+    _allocator_refs = (fa, ff)
+
+
+def use_torch_allocator():
+    """Let torch's caching allocator own the library's device memory."""
+    import torch
+    dev = torch.cuda.current_device()
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev),
+                  torch.cuda.caching_allocator_delete)
+
+
 def lib():
     """Load libmono.so (raises if it is missing: the HIP path is the only path)."""
     global _lib
@@ -113,6 +142,7 @@ def lib():
             "mono_sample_sensors": [vp, i64, dbl, vp],
             "mono_set_launch": [vp, C.POINTER(Launch)],
             "mono_get_launch": [vp, C.POINTER(Launch)],
+            "mono_set_allocator": [ALLOC_FN, FREE_FN, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)

@@ -90,3 +90,13 @@ def test_null_handles_are_rejected():
     assert L.mono_get_info(None, 0, None) == -1
     assert L.mono_sync(None) == -1
     L.mono_destroy(None)
+
+
+def test_allocator_hook_arguments():
+    """mono_set_allocator takes both functions or neither (no simulation exists
+    here, so the hook may change)."""
+    from paper_2011_04747_amd import mono
+    mono.set_allocator(lambda n: 0, lambda p: None)
+    mono.set_allocator()
+    rc = mono.lib().mono_set_allocator(mono.ALLOC_FN(lambda n, c: None), mono.FREE_FN(), None)
+    assert mono.STATUS[rc] == "EINVAL"

@@ -569,3 +569,33 @@ def test_autotuner_leaves_state_unchanged(torch, tmp_path, monkeypatch):
     assert (a.get(mono.FIELD_V) == b.get(mono.FIELD_V)).all()
     again = autotune.tune(b, w.dt)          # cached
     assert again == best
+
+
+def test_torch_caching_allocator_owns_device_memory(torch):
+    """With the allocator hook set to torch's caching allocator the library's
+    device buffers come from torch (memory_allocated grows and shrinks with
+    the simulation) and results are the same bits; the hook cannot change
+    while a simulation exists."""
+    w = W.slab_ischemic(shape=(25, 21, 9), t_end=8.0)
+    ref = mono.Sim.from_workload(w, "f32")
+    ref.step(w.n_steps, w.dt)
+    v_ref = ref.get(mono.FIELD_V)
+    ref.close()
+    import gc
+    gc.collect()                      # simulations of earlier tests are destroyed
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    mono.use_torch_allocator()
+    try:
+        s = mono.Sim.from_workload(w, "f32")
+        grown = torch.cuda.memory_allocated() - base
+        assert grown >= 20 * w.mesh.n_nodes * 4          # states, potential, operator
+        with pytest.raises(mono.MonoError):
+            mono.set_allocator()
+        s.step(w.n_steps, w.dt)
+        assert (s.get(mono.FIELD_V) == v_ref).all()
+        s.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        mono.set_allocator()
