@@ -59,19 +59,29 @@ def _traffic(kernel, workload, launch):
     return t["bytes_per_launch"]
 
 
-def cpu_baseline(w, steps):
-    """The FP64 CPU oracle, as it stands, on a bounded sample of the workload."""
-    from oracle.oracle import Oracle
+def cpu_baseline(w, steps, steps_1t):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the workload:
+    `steps` outer steps on all threads, then `steps_1t` more on one thread."""
+    from oracle.oracle import Oracle, get_threads, set_threads
     o = Oracle.from_workload(w)
     o.prepare(w.dt)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = get_threads()
     t0 = time.perf_counter()
     o.step(steps, w.dt)
     el = time.perf_counter() - t0
-    return {"value": w.mesh.n_nodes * steps / el, "unit": "node-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"full {w.mesh.n_nodes}-node slab, FP64, first {steps} outer steps "
-                      f"from t=0 (assembly excluded), {el:.1f} s"}
+    out = {"value": w.mesh.n_nodes * steps / el, "unit": "node-updates/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"full {w.mesh.n_nodes}-node slab, FP64, first {steps} outer steps "
+                     f"from t=0 (assembly excluded), {el:.1f} s"}
+    if steps_1t > 0:
+        set_threads(1)
+        t0 = time.perf_counter()
+        o.step(steps_1t, w.dt)
+        el1 = time.perf_counter() - t0
+        set_threads(threads)
+        out["value_1_thread"] = w.mesh.n_nodes * steps_1t / el1
+        out["sample_1_thread"] = f"the next {steps_1t} outer steps on 1 thread, {el1:.1f} s"
+    return out
 
 
 def adjoint_leg(stream, with_accuracy, tune=True):
@@ -164,6 +174,8 @@ def main():
     ap.add_argument("--workload", default="slab", choices=["slab", "batched"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps-1t", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -203,16 +215,29 @@ def main():
         from paper_2011_04747_amd import autotune
         launch = autotune.tune(sim, w.dt)
     sim.step(args.steps, w.dt, flags=mono.STEP_CAPTURE)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    t0 = time.perf_counter()
-    sim.step(args.steps, w.dt)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
+    # the window is timed `repeats` times from the same state (restored from a
+    # snapshot); value = the median
+    snap = None
+    if args.repeats > 1:
+        fields = [mono.FIELD_VPREV, mono.FIELD_LAT] + \
+            [mono.FIELD_STATE0 + j for j in range(info["n_states"])]
+        snap = (sim.info()["step"], {f: sim.get(f) for f in fields})
+    times = []
+    for r in range(max(1, args.repeats)):
+        if snap and r:
+            for f, v in snap[1].items():
+                sim.set(f, v)
+            sim.set_time_level(snap[0])
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        t0 = time.perf_counter()
+        sim.step(args.steps, w.dt)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append((ev0.elapsed_time(ev1), time.perf_counter() - t0))
+    ms, wall = sorted(times)[len(times) // 2]
     info = sim.info()
     value = n * args.steps / (ms * 1e-3)
 
@@ -231,12 +256,14 @@ def main():
     kbuf = torch.zeros(((n + 1023) // 1024) * 1024, dtype=torch.uint8, device="cuda")
     rb = launch.get("react_block", 256)
     ksum = kwave = ksat = 0
+    khist = torch.zeros(256, dtype=torch.int64, device="cuda")
     kt_steps = args.steps
     for _ in range(kt_steps):
         sim.step(1, w.dt, flags=mono.STEP_TIMED)
         with torch.cuda.stream(stream):
             sim.get_device_async(mono.FIELD_K, kbuf.data_ptr())
             kk = kbuf.to(torch.int64)
+            khist += torch.bincount(kk[:n], minlength=256)[:256]
             ksum += int(kk.sum())
             if launch.get("react_sort", 0):
                 # lanes take the nodes of their workgroup in order of k
@@ -323,7 +350,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_steps)
+        cpu = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
 
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -336,6 +363,9 @@ def main():
                       "sim_ms_per_s": w.dt * args.steps / (ms * 1e-3),
                       "row_classes": info["row_classes"],
                       "mean_k": ksum / (n * kt_steps), "k_at_kmax_frac": ksat / (n * kt_steps),
+                      "k_histogram": {str(k): int(c) for k, c in enumerate(khist.tolist()) if c},
+                      "node_ms_per_s": n * w.dt * args.steps / (ms * 1e-3),
+                      "repeats_ms": [t[0] for t in times],
                       "wall_s": wall},
            "roofline": roofline,
            "kernels": {"diffusion": diff_roof, "reaction": react_roof,

@@ -73,6 +73,22 @@ def lib():
     return _lib
 
 
+def set_threads(n):
+    """Number of OpenMP threads of the oracle's parallel loops (the OpenMP
+    runtime the oracle library is linked against)."""
+    import ctypes.util
+    lib()
+    gomp = C.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    gomp.omp_set_num_threads(int(n))
+
+
+def get_threads():
+    import ctypes.util
+    lib()
+    gomp = C.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    return int(gomp.omp_get_max_threads())
+
+
 def _check(rc):
     if rc != 0:
         raise RuntimeError("oracle: " + lib().orc_last_error().decode())
