@@ -39,9 +39,41 @@ inline float xsqrt(float x) { return sqrtf(x); }
 inline float xrcp(float x) { return 1.0f / x; }
 #endif
 
+// base-2 exponential and logarithm: e^x = 2^(x log2 e), ln x = ln 2 log2 x.
+// Written with the base-2 forms, an exponential of an affine function of V
+// is 2^(A V + B) with A, B folded into constants (one fused multiply-add and
+// the hardware exp2 in FP32) instead of a subtraction, a scaling and the
+// base conversion.
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+__host__ __device__ __forceinline__ double xexp2(double x) { return exp2(x); }
+__host__ __device__ __forceinline__ double xlog2(double x) { return log2(x); }
+// xlog2c: the same for operands that do not change inside the substep loop
+// (parameters), in a form the compiler may move out of the loop
+__host__ __device__ __forceinline__ double xlog2c(double x) { return log2(x); }
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ float xexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float xlog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float xlog2c(float x) { return __builtin_log2f(x); }
+#else
+inline float xexp2(float x) { return exp2f(x); }
+inline float xlog2(float x) { return log2f(x); }
+inline float xlog2c(float x) { return log2f(x); }
+#endif
+
 template <typename T>
 __host__ __device__ __forceinline__ T xdiv(T a, T b) {
   return a * xrcp(b);
+}
+// a V + b with the constants rounded once to T
+template <typename T>
+__host__ __device__ __forceinline__ T lin(T V, double a, double b) {
+  return V * T(a) + T(b);
+}
+// logistic 1 / (1 + 2^z2), i.e. sig(z) for z2 = z log2 e
+template <typename T>
+__host__ __device__ __forceinline__ T sig2(T z2) {
+  return xrcp(T(1) + xexp2(z2));
 }
 // logistic 1 / (1 + e^z)
 template <typename T>
@@ -56,6 +88,11 @@ __host__ __device__ __forceinline__ T rl_rate(T y, T yinf, T rate, T h) {
 template <typename T>
 __host__ __device__ __forceinline__ T rush_larsen(T y, T yinf, T tau, T h) {
   return rl_rate(y, yinf, xrcp(tau), h);
+}
+// Rush-Larsen update with hl = -h log2 e taken once per substep
+template <typename T>
+__host__ __device__ __forceinline__ T rl_rate2(T y, T yinf, T rate, T hl) {
+  return yinf + (y - yinf) * xexp2(rate * hl);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,13 +195,14 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   using namespace tp06;
   const T V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5], Rb = y[6];
   const T Ko = p[0];
-  const T rtf = T(kRTF), frt = T(kFRT);
-  // Nernst potentials as differences of logarithms (the logarithms of the
-  // parameter and constant concentrations do not change between substeps)
-  const T EK = rtf * (xlog(Ko) - xlog(Ki));
-  const T ENa = rtf * (T(4.941642422609304) - xlog(Nai));              // ln 140
-  const T ECa = T(0.5) * rtf * (T(0.6931471805599453) - xlog(Cai));    // ln 2
-  const T EKs = rtf * (xlog(Ko + T(kPKNa * kNao)) - xlog(Ki + T(kPKNa) * Nai));
+  // Nernst potentials as differences of base-2 logarithms (the logarithms
+  // of the parameter and constant concentrations do not change between
+  // substeps); RT/F ln 2 is one constant
+  const T rtf2 = T(kRTF * kLn2);
+  const T EK = rtf2 * (xlog2c(Ko) - xlog2(Ki));
+  const T ENa = rtf2 * (T(7.129283016944966) - xlog2(Nai));            // log2 140
+  const T ECa = T(0.5 * kRTF * kLn2) * (T(1) - xlog2(Cai));            // log2 2
+  const T EKs = rtf2 * (xlog2c(Ko + T(kPKNa * kNao)) - xlog2(Ki + T(kPKNa) * Nai));
   const T sqKo = xsqrt(Ko * T(1.0 / 5.4));
 
   const T m = y[7], hh = y[8], jj = y[9];
@@ -173,19 +211,21 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
   const T vk = V - EK;
   // x_K1 = a/(a + b) with a = 0.1 sig(0.06 (vk - 200)) = 0.1/(1 + e_a):
   // 1/(1 + 10 b (1 + e_a))
-  const T ea = xexp(T(0.06) * (vk - T(200)));
-  const T bK1 = (T(3) * xexp(T(0.0002) * (vk + T(100))) + xexp(T(0.1) * (vk - T(10)))) *
-                sig(T(-0.5) * vk);
+  const T ea = xexp2(lin(vk, 0.06 * kLog2e, -12.0 * kLog2e));
+  // 3 e^{0.0002 (vk + 100)} = 2^{0.0002 log2e vk + 0.02 log2e + log2 3}
+  const T bK1 = (xexp2(lin(vk, 0.0002 * kLog2e, 0.02 * kLog2e + 1.5849625007211563)) +
+                 xexp2(lin(vk, 0.1 * kLog2e, -kLog2e))) *
+                sig2(vk * T(-0.5 * kLog2e));
   const T IK1 = p[5] * T(kGK1) * sqKo * xrcp(T(1) + T(10) * bK1 * (T(1) + ea)) * vk;
   const T Ito = T(kGto) * y[13] * y[14] * vk;
   const T IKr = p[3] * T(kGKr) * sqKo * y[10] * y[11] * vk;
   const T IKs = p[4] * T(kGKs) * y[12] * y[12] * (V - EKs);
-  const T IpK = T(kGpK) * vk * sig((T(25) - V) * T(1.0 / 5.98));
+  const T IpK = T(kGpK) * vk * sig2(lin(V, -kLog2e / 5.98, 25.0 * kLog2e / 5.98));
 
   // L-type Ca current with the removable singularity at V = 15 mV handled
   // through x / (e^x - 1)
-  const T x = T(2) * (V - T(15)) * frt;
-  const T ex = xexp(x);
+  const T x = lin(V, 2.0 * kFRT, -30.0 * kFRT);
+  const T ex = xexp2(x * T(kLog2e));
   T xe;
   if constexpr (std::is_same<T, float>::value) {
     // FP32: x / (e^x - 1) from the e^x needed anyway, its Taylor series
@@ -198,15 +238,15 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
            (T(0.25) * Cass * ex - T(kCao));
 
   // e^{-VF/RT} serves the Na/Ca exchanger and the Na/K pump
-  const T u = xexp(-V * frt);
-  const T eg = xexp(T(kNaCaGam) * V * frt);
+  const T u = xexp2(V * T(-kFRT * kLog2e));
+  const T eg = xexp2(V * T(kNaCaGam * kFRT * kLog2e));
   const T eg1 = eg * u;
   const T denom = T((kKmNai * kKmNai * kKmNai + kNao * kNao * kNao) * (kKmCa + kCao));
   c.INaCa = T(kNaCaMax) *
             xdiv(eg * Nai * Nai * Nai * T(kCao) - eg1 * T(kNao * kNao * kNao * kNaCaAlpha) * Cai,
                  denom * (T(1) + T(kNaCaSat) * eg1));
   c.INaK = T(kPNaK) * xdiv(Ko * Nai, (Ko + T(kKmK)) * (Nai + T(kKmNa)) *
-                                         (T(1) + T(0.1245) * xexp(T(-0.1) * V * frt) +
+                                         (T(1) + T(0.1245) * xexp2(V * T(-0.1 * kFRT * kLog2e)) +
                                           T(0.0353) * u));
   c.IpCa = T(kGpCa) * xdiv(Cai, T(kKpCa) + Cai);
   c.IbNa = T(kGbNa) * (V - ENa);
@@ -241,75 +281,78 @@ __host__ __device__ __forceinline__ T sig_e(T ez) {
 // the published forms; only the rounding differs.
 template <typename T>
 __host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) {
-  const T P5 = xexp(T(0.2) * V);             // e^{V/5}
-  const T N10 = xexp(T(-0.1) * V);           // e^{-V/10}
-  const T N20 = xexp(T(-0.05) * V);          // e^{-V/20}
-  const T P7 = xexp(V * T(1.0 / 7.0));       // e^{V/7}
-  const T N6 = xexp(V * T(-1.0 / 6.0));      // e^{-V/6}
+  constexpr double L = kLog2e;
+  const T P5 = xexp2(V * T(0.2 * L));         // e^{V/5}
+  const T N10 = xexp2(V * T(-0.1 * L));       // e^{-V/10}
+  const T N20 = xexp2(V * T(-0.05 * L));      // e^{-V/20}
+  const T P7 = xexp2(V * T(L / 7.0));         // e^{V/7}
+  const T N6 = xexp2(V * T(-L / 6.0));        // e^{-V/6}
   {
     // m: alpha = sig(-(V+60)/5), beta = 0.1 sig((V+35)/5) + 0.1 sig((V-50)/200)
-    const T e = sig((T(-56.86) - V) * T(1.0 / 9.03));
-    const T ea = xexp((T(-60) - V) * T(0.2));
+    const T e = sig2(lin(V, -L / 9.03, -56.86 * L / 9.03));
+    const T ea = xexp2(lin(V, -0.2 * L, -12.0 * L));                 // e^{-(V+60)/5}
     const T bm = T(0.1) * sig_e(T(1096.6331584284585) * P5) +       // e^7 e^{V/5}
-                 T(0.1) * sig((V - T(50)) * T(0.005));
+                 T(0.1) * sig2(lin(V, 0.005 * L, -0.25 * L));
     inf[0] = e * e;
     rate[0] = (T(1) + ea) * xrcp(bm);
   }
   {
-    const T e = sig((V + T(71.55)) * T(1.0 / 7.43));
+    const T e = sig2(lin(V, L / 7.43, 71.55 * L / 7.43));
     inf[1] = e * e;
     inf[2] = e * e;
     if (V >= T(-40)) {
-      rate[1] = T(0.77 / 0.13) * sig(-(V + T(10.66)) * T(1.0 / 11.1));
-      rate[2] = T(0.6) * xexp(T(0.057) * V) *
+      rate[1] = T(0.77 / 0.13) * sig2(lin(V, -L / 11.1, -10.66 * L / 11.1));
+      rate[2] = T(0.6) * xexp2(V * T(0.057 * L)) *
                 sig_e(T(0.04076220397836621) * N10);                 // e^{-3.2} e^{-V/10}
     } else {
-      rate[1] = T(0.057) * xexp(-(V + T(80)) * T(1.0 / 6.8)) + T(2.7) * xexp(T(0.079) * V) +
-                T(3.1e5) * xexp(T(0.3485) * V);
-      rate[2] = (T(-2.5428e4) * xexp(T(0.2444) * V) - T(6.948e-6) * xexp(T(-0.04391) * V)) *
-                    (V + T(37.78)) * sig(T(0.311) * (V + T(79.23))) +
-                T(0.02424) * xexp(T(-0.01052) * V) * sig(T(-0.1378) * (V + T(40.14)));
+      rate[1] = T(0.057) * xexp2(lin(V, -L / 6.8, -80.0 * L / 6.8)) +
+                T(2.7) * xexp2(V * T(0.079 * L)) + T(3.1e5) * xexp2(V * T(0.3485 * L));
+      rate[2] = (T(-2.5428e4) * xexp2(V * T(0.2444 * L)) -
+                 T(6.948e-6) * xexp2(V * T(-0.04391 * L))) *
+                    (V + T(37.78)) * sig2(lin(V, 0.311 * L, 0.311 * 79.23 * L)) +
+                T(0.02424) * xexp2(V * T(-0.01052 * L)) *
+                    sig2(lin(V, -0.1378 * L, -0.1378 * 40.14 * L));
     }
   }
-  const T s30 = sig((V + T(30)) * T(0.1));    // shared by f and f2
+  const T s30 = sig2(lin(V, 0.1 * L, 3.0 * L));    // sig((V+30)/10), shared by f and f2
   {
     // xr1: 1/(alpha beta), alpha = 450 sig(-(V+45)/10), beta = 6 sig((V+30)/11.5)
-    inf[3] = sig((T(-26) - V) * T(1.0 / 7.0));
+    inf[3] = sig2(lin(V, -L / 7.0, -26.0 * L / 7.0));
     rate[3] = (T(1) + T(0.011108996538242306) * N10) *                // e^{-4.5} e^{-V/10}
-              (T(1) + xexp((V + T(30)) * T(1.0 / 11.5))) * T(1.0 / 2700.0);
+              (T(1) + xexp2(lin(V, L / 11.5, 30.0 * L / 11.5))) * T(1.0 / 2700.0);
     // xr2: alpha = 3 sig(-(V+60)/20), beta = 1.12 sig((V-60)/20)
-    inf[4] = sig((V + T(88)) * T(1.0 / 24.0));
+    inf[4] = sig2(lin(V, L / 24.0, 88.0 * L / 24.0));
     rate[4] = (T(1) + T(0.049787068367863944) * N20) *                // e^{-3} e^{-V/20}
-              (T(1) + xexp((V - T(60)) * T(0.05))) * T(1.0 / 3.36);
+              (T(1) + xexp2(lin(V, 0.05 * L, -3.0 * L))) * T(1.0 / 3.36);
   }
   {
     const T a = T(1400) * xrcp(xsqrt(T(1) + T(2.300975890892825) * N6));   // e^{5/6} e^{-V/6}
-    const T b = sig((V - T(35)) * T(1.0 / 15.0));
-    inf[5] = sig((T(-5) - V) * T(1.0 / 14.0));
+    const T b = sig2(lin(V, L / 15.0, -35.0 * L / 15.0));
+    inf[5] = sig2(lin(V, -L / 14.0, -5.0 * L / 14.0));
     rate[5] = xrcp(a * b + T(80));
   }
   {
     const T vr = V + T(40), vs = V + T(45);
     inf[6] = sig_e(T(28.03162489452614) * N6);                        // e^{20/6} e^{-V/6}
-    rate[6] = xrcp(T(9.5) * xexp(-vr * vr * T(1.0 / 1800.0)) + T(0.8));
+    rate[6] = xrcp(T(9.5) * xexp2(vr * vr * T(-L / 1800.0)) + T(0.8));
     inf[7] = sig_e(T(54.598150033144236) * P5);                       // e^4 e^{V/5}
-    rate[7] = xrcp(T(85) * xexp(-vs * vs * T(1.0 / 320.0)) +
+    rate[7] = xrcp(T(85) * xexp2(vs * vs * T(-L / 320.0)) +
                    T(5) * sig_e(T(0.01831563888873418) * P5) + T(3));  // e^{-4} e^{V/5}
   }
   {
-    const T ad = T(1.4) * sig((T(-35) - V) * T(1.0 / 13.0)) + T(0.25);
+    const T ad = T(1.4) * sig2(lin(V, -L / 13.0, -35.0 * L / 13.0)) + T(0.25);
     const T bd = T(1.4) * sig_e(T(2.718281828459045) * P5);            // e^1 e^{V/5}
     const T gd = sig_e(T(12.182493960703473) * N20);                   // e^{2.5} e^{-V/20}
-    inf[8] = sig((T(-8) - V) * T(1.0 / 7.5));
+    inf[8] = sig2(lin(V, -L / 7.5, -8.0 * L / 7.5));
     rate[8] = xrcp(ad * bd + gd);
     const T vf = V + T(27);
     inf[9] = sig_e(T(17.41170806332765) * P7);                         // e^{20/7} e^{V/7}
-    rate[9] = xrcp(T(1102.5) * xexp(-vf * vf * T(1.0 / 225.0)) +
+    rate[9] = xrcp(T(1102.5) * xexp2(vf * vf * T(-L / 225.0)) +
                    T(200) * sig_e(T(3.6692966676192444) * N10) +        // e^{1.3} e^{-V/10}
                    T(180) * s30 + T(20));
     const T vf2 = V + T(25);
     inf[10] = T(0.67) * sig_e(T(148.4131591025766) * P7) + T(0.33);   // e^5 e^{V/7}
-    rate[10] = xrcp(T(600) * xexp(-vf2 * vf2 * T(1.0 / 170.0)) +
+    rate[10] = xrcp(T(600) * xexp2(vf2 * vf2 * T(-L / 170.0)) +
                     T(31) * sig_e(T(12.182493960703473) * N10) +        // e^{2.5} e^{-V/10}
                     T(16) * s30);
   }
@@ -355,7 +398,8 @@ struct TP06Model {
     tp06_gate_params(V, inf, rate);
     tp06_fcass_params(y[4], inf[11], rate[11]);
     T g[12];
-    for (int a = 0; a < 12; ++a) g[a] = rl_rate(y[7 + a], inf[a], rate[a], h);
+    const T hl = h * T(-kLog2e);
+    for (int a = 0; a < 12; ++a) g[a] = rl_rate2(y[7 + a], inf[a], rate[a], hl);
 
     // commit
     y[3] = free_from_total(total_from_free(y[3], T(kBufc), T(kKbufc)) + h * dCai, T(kBufc),

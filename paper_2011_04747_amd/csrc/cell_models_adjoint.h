@@ -50,6 +50,11 @@ __host__ __device__ __forceinline__ Dual<S> xexp(Dual<S> a) {
   return Dual<S>(e, e * a.d);
 }
 template <typename S>
+__host__ __device__ __forceinline__ Dual<S> xexp2(Dual<S> a) {
+  const S e = xexp2(a.v);
+  return Dual<S>(e, e * S(kLn2) * a.d);
+}
+template <typename S>
 __host__ __device__ __forceinline__ Dual<S> xrcp(Dual<S> a) {
   const S r = xrcp(a.v);
   return Dual<S>(r, -r * r * a.d);

@@ -37,6 +37,9 @@ inline bool operator==(CF a, CF b) { g_ops->cmp++; return a.v == b.v; }
 inline CF xexp(CF x) { g_ops->exp++; return CF(std::exp(x.v)); }
 inline CF xexpm1(CF x) { g_ops->exp++; return CF(std::expm1(x.v)); }
 inline CF xlog(CF x) { g_ops->log++; return CF(std::log(x.v)); }
+inline CF xexp2(CF x) { g_ops->exp++; return CF(std::exp2(x.v)); }
+inline CF xlog2(CF x) { g_ops->log++; return CF(std::log2(x.v)); }
+inline CF xlog2c(CF x) { g_ops->log++; return CF(std::log2(x.v)); }
 inline CF xsqrt(CF x) { g_ops->sqrt++; return CF(std::sqrt(x.v)); }
 inline CF xrcp(CF x) { g_ops->div++; return CF(1.0 / x.v); }
 
