@@ -94,6 +94,34 @@ __device__ __forceinline__ T stimulus_rate(const DiffArgs<T>& a, int64_t i, doub
   return r;
 }
 
+// Stimuli open on this substep of a single instance (bit s for stimulus s):
+// by the integer substep windows when the table carries them (no floating
+// point on the way), else from the start time tau.
+template <typename T>
+__device__ __forceinline__ uint32_t open_stimuli(const DiffArgs<T>& a, double dt_ad) {
+  if (a.stim.n == 0 || a.stim_mask == nullptr) return 0u;
+  uint32_t active = 0;
+  if (a.stim.L > 0) {
+    const int64_t q = ((*a.clk.base + a.clk.g) * 2 + a.half) * (int64_t)a.stim.L + a.m;
+    for (int s = 0; s < a.stim.n; ++s)
+      if (a.stim.q_on[s] <= q && q < a.stim.q_end[s]) active |= 1u << s;
+  } else {
+    const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
+    for (int s = 0; s < a.stim.n; ++s)
+      if (a.stim.t_on[s] <= tau && tau < a.stim.t_end[s]) active |= 1u << s;
+  }
+  return active;
+}
+// summed amplitude of the open stimuli that include node i
+template <typename T>
+__device__ __forceinline__ T stimulus_sum(const DiffArgs<T>& a, uint32_t active, int64_t i) {
+  const uint32_t mask = a.stim_mask[i] & active;
+  T r = T(0);
+  for (int s = 0; s < a.stim.n; ++s)
+    if (mask & (1u << s)) r += (T)a.stim.amp[s];
+  return r;
+}
+
 template <typename T, bool BATCHED, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_diff_ell(DiffArgs<T> a) {
   const int64_t nb = (a.n + BLOCK - 1) / BLOCK;
@@ -208,11 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_diff_classes(DiffArgs<T> a) {
   const T* V = a.Vin;
   const double dt_ad = a.dt_ad[0];
   const T hT = (T)dt_ad;
-  const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
-  uint32_t active = 0;
-  if (a.stim_mask)
-    for (int q = 0; q < a.stim.n; ++q)
-      if (a.stim.t_on[q] <= tau && tau < a.stim.t_end[q]) active |= 1u << q;
+  const uint32_t active = open_stimuli(a, dt_ad);
   using Clamp = std::integral_constant<bool, true>;
   using NoClamp = std::integral_constant<bool, false>;
   for (int it = 0; it < ITER; ++it) {
@@ -257,12 +281,7 @@ __global__ __launch_bounds__(BLOCK) void k_diff_classes(DiffArgs<T> a) {
     } else {
       sweep(a.ctab + (uint32_t)(c * a.tw), Clamp{});
     }
-    T sr = T(0);
-    if (active) {
-      const uint32_t mask = a.stim_mask[(uint32_t)i] & active;
-      for (int q = 0; q < a.stim.n; ++q)
-        if (mask & (1u << q)) sr += (T)a.stim.amp[q];
-    }
+    const T sr = active ? stimulus_sum(a, active, (int64_t)i) : T(0);
     *(T*)((char*)a.Vout + (uint32_t)bi) = vi + hT * (mv * acc + sr);
   }
 }
@@ -320,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
   }
   const double dt_ad = a.dt_ad[0];
   const T hT = (T)dt_ad;
-  const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
+  const uint32_t active = open_stimuli(a, dt_ad);
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int64_t g = g0 + it;
@@ -360,7 +379,7 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
       sweep(ctab + (uint32_t)((int)a.cls[(uint32_t)ic] * a.tw));
     }
     if (produce) {
-      const T sr = stimulus_rate(a, (int64_t)i, tau);
+      const T sr = active ? stimulus_sum(a, active, (int64_t)i) : T(0);
       *(T*)((char*)a.Vout + (uint32_t)(i * ES)) = vi + hT * (mv * acc + sr);
     }
   }

@@ -124,6 +124,13 @@ struct StimTable {
   double t_on[kMaxStim];
   double t_end[kMaxStim];
   double amp[kMaxStim];
+  // Single instance: with L > 0 substeps per half step, stimulus s is open
+  // on the substeps q = (2 step + half) L + m with q_on[s] <= q < q_end[s],
+  // which are exactly those whose start time tau (below) lies in
+  // [t_on, t_end); L = 0 leaves the test to tau.
+  int L;
+  int64_t q_on[kMaxStim];
+  int64_t q_end[kMaxStim];
 };
 
 struct StepClock {

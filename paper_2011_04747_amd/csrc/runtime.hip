@@ -288,6 +288,33 @@ mono_status prepare(mono_sim* s, double dt) {
   return MONO_OK;
 }
 
+// Start time of substep q = (2 step + half) L + m, with the rounding of the
+// diffusion kernels' substep clock.
+double substep_start(int64_t q, double dt, int L, double dt_ad) {
+  const int64_t step = q / (2 * (int64_t)L), r = q % (2 * (int64_t)L);
+  double t0 = rn_mul((double)step, dt);
+  if (r >= L) t0 = rn_add(t0, rn_mul(0.5, dt));
+  return rn_add(t0, rn_mul((double)(r % L), dt_ad));
+}
+// First substep whose start time is at or after t (start times increase
+// with q: within a half step by m dt_ad, across halves and steps by at least
+// dt_ad, far above their rounding)
+int64_t first_substep_from(double t, double dt, int L, double dt_ad) {
+  if (!(t > 0.0)) return 0;
+  const double qf = t / dt * 2.0 * L + 4.0;
+  if (!(qf < 4.0e18)) return INT64_MAX;
+  int64_t lo = 0, hi = (int64_t)qf;          // tau(lo) < t <= tau(hi)
+  if (substep_start(hi, dt, L, dt_ad) < t) return INT64_MAX;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (substep_start(mid, dt, L, dt_ad) >= t)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
 template <typename T>
 DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   DiffArgs<T> a{};
@@ -314,6 +341,14 @@ DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   a.dt_ad = s->d_dtad;
   a.stim_mask = s->d_mask;
   a.stim = s->stim;
+  a.stim.L = 0;
+  if (s->n_inst == 1 && !s->l.empty() && s->l[0] > 0) {
+    a.stim.L = s->l[0];
+    for (int q = 0; q < a.stim.n; ++q) {
+      a.stim.q_on[q] = first_substep_from(a.stim.t_on[q], s->dt, s->l[0], s->dt_ad[0]);
+      a.stim.q_end[q] = first_substep_from(a.stim.t_end[q], s->dt, s->l[0], s->dt_ad[0]);
+    }
+  }
   a.clk.base = s->d_base;
   a.clk.g = g;
   a.clk.dt = s->dt;

@@ -507,6 +507,34 @@ def test_row_classes_match_per_row_arrays(torch, prec, which):
             assert (a == b).all()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stimulus_windows_on_substep_edges(torch, prec):
+    """Stimulus windows that open and close on or between substep start times
+    (t = 0.35 falls on a half-step start, 0.4 + 0.1/12 inside a half step,
+    an end exactly on a step start, a zero-length window, one opening after
+    the run): the single-instance kernels, which test integer substep
+    windows, give the bits of the per-row stencil kernel, which tests the
+    FP64 start time."""
+    w = W.slab_ischemic(shape=(37, 29, 11), dx=2.0 ** -7, t_end=4.0)
+    nodes = np.arange(0, w.mesh.n_nodes, 7, dtype=np.int32)
+    w.stimuli = [W.Stimulus(nodes, 0.35, 0.3, 40.0),
+                 W.Stimulus(nodes[::2], 0.4 + 0.1 / 12.0, 1.2, 30.0),
+                 W.Stimulus(nodes[1::3], 1.0, 0.0, 50.0),
+                 W.Stimulus(nodes[::5], 2.0, 1e300, 5.0),
+                 W.Stimulus(nodes[::4], 3.95, 9.0, 20.0),
+                 W.Stimulus(nodes[::3], 50.0, 1.0, 20.0)]
+    outs = []
+    for cls, rows in ((1, 1), (1, 0), (0, 0)):
+        s = mono.Sim.from_workload(w, prec)
+        s.set_launch(diff_classes=cls, diff_wave_rows=rows)
+        s.step(w.n_steps, w.dt)
+        assert s.info()["l"] >= 2
+        outs.append((s.get(mono.FIELD_V), s.get(mono.FIELD_LAT)))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert (a == b).all()
+
+
 def test_row_classes_absent_where_rows_do_not_repeat(torch):
     w = W.batched_sheets(n_inst=3, side_lo=12, side_hi=20)
     assert mono.Sim.from_workload(w, "f32").info()["row_classes"] == 0
