@@ -88,6 +88,10 @@ enum {
   MONO_FIELD_VPREV = 1,  /* V at the previous reaction entry                */
   MONO_FIELD_LAT = 2,    /* activation time [ms], FP64, -1 = not activated   */
   MONO_FIELD_K = 3,      /* reaction substeps k of the last step (get only)  */
+  MONO_FIELD_APD = 4,    /* APD90 [ms], FP64 (get only), -1 = not measured;
+                            needs mono_track_apd                             */
+  MONO_FIELD_TUP = 5,    /* time of the steepest sampled upstroke [ms], FP64
+                            (get only), -1 = not activated                   */
   MONO_FIELD_STATE0 = 16 /* + j: cell state j (j = 0 is V)                  */
 };
 
@@ -193,6 +197,32 @@ mono_status mono_prepare(mono_sim *sim, double dt);
 
 /* Diagnostics of instance `inst` (0-based). */
 mono_status mono_get_info(mono_sim *sim, int32_t inst, mono_info *out);
+
+/* Action-potential duration at 90 % repolarisation (APD90, paper Sec. 3.1
+ * and Sec. 4, measured there from the time of the maximum upstroke
+ * derivative), tracked per node from the same reaction-entry samples V_n at
+ * t_n = (n + 1/2) dt that give the activation time.  For the first activation
+ * of a node (first n with V_{n-1} < threshold <= V_n): V_rest = V_{n-1}; the
+ * upstroke time is the midpoint of the sampled interval with the largest
+ * slope (V_n - V_{n-1}) / dt from that interval on (the first such interval
+ * on ties); V_90 = V_max - 0.9 (V_max - V_rest) with V_max the largest sample
+ * since activation; repolarisation is the first interval after activation
+ * with V_{n-1} >= V_90 > V_n, its time interpolated linearly; APD90 is the
+ * repolarisation time minus the upstroke time.  Times and slopes in FP64 in
+ * every precision.  on = 1 allocates the trackers (5 doubles per node) and
+ * resets them (every node not activated), on = 0 frees them.  Tracking
+ * follows ordinary steps (mono_step, mono_step_loss); the taped forward run
+ * and the adjoint sweep do not update it, and snapshots do not carry it.
+ * Errors: EINVAL, ESTATE (no model), ENOMEM. */
+mono_status mono_track_apd(mono_sim *sim, int32_t on);
+
+/* Normalised root-mean-square error of eq. (4):
+ * sqrt(mean_i (u_hat_i - u_i)^2) / (max_i u_i - min_i u_i) over the n host
+ * values (reference u, e.g. OST's LAT or APD90 per node); entries where either
+ * value is negative (not measured) are left out of the mean and of the range.
+ * *out = NaN when no entry is left or the range is 0.  Errors: EINVAL. */
+mono_status mono_nrmse(const double *u_hat, const double *u, int64_t n, double *out);
+
 
 /* Estimate lambda_max(M_L^-1 K) of every instance by `iters` FP64 power
  * iterations on the device (generalised Rayleigh quotient, a lower bound)

@@ -1289,4 +1289,58 @@ int orc_tp06_currents(const double* p, const double* y, double* out) {
 int orc_k_rule(double dvdt, int k_max) { return k_rule(dvdt, k_max); }
 int orc_l_rule(double dt, double dt_s, int l_round) { return l_rule(dt, dt_s, l_round); }
 
+
+// APD90 of the first action potential of each of ns nodes from its
+// reaction-entry samples V[n * ns + q], n = 0..steps-1, taken at
+// t_n = (step0 + n) dt + dt/2 (the samples the activation time uses).
+// Readings (the paper measures APD90 from the time of the maximum upstroke
+// derivative, Sec. 4): activation is the first n with V_{n-1} < thr <= V_n
+// and V_rest = V_{n-1} there; repolarisation is the first later interval with
+// V_{n-1} >= V_90 > V_n, V_90 = V_max - 0.9 (V_max - V_rest), V_max the
+// largest sample from activation to V_{n-1}, its time interpolated linearly;
+// the upstroke time is the midpoint of the interval of largest slope
+// (V_n - V_{n-1}) / dt from activation to repolarisation (to the last sample
+// if there is none), the first one on ties.  apd = -1 where there is no
+// repolarisation, tup = -1 where there is no activation.
+int orc_apd90(int64_t steps, int64_t ns, const double* V, int64_t step0, double dt, double thr,
+              double* apd, double* tup) {
+  if (steps < 0 || ns < 0 || (steps * ns > 0 && !V) || !(dt > 0.0) || !apd || !tup)
+    return fail("bad argument");
+  for (int64_t q = 0; q < ns; ++q) {
+    apd[q] = -1.0;
+    tup[q] = -1.0;
+    auto v = [&](int64_t n) { return V[n * ns + q]; };
+    auto t_prev = [&](int64_t n) { return ((step0 + n) * dt + 0.5 * dt) - dt; };
+    auto slope = [&](int64_t n) { return (v(n) - v(n - 1)) / dt; };
+    int64_t na = -1;
+    for (int64_t n = 1; n < steps; ++n)
+      if (v(n - 1) < thr && v(n) >= thr) {
+        na = n;
+        break;
+      }
+    if (na < 0) continue;
+    const double vrest = v(na - 1);
+    double vmax = v(na), v90 = 0.0;
+    int64_t nr = -1;
+    for (int64_t n = na + 1; n < steps; ++n) {
+      v90 = vmax - 0.9 * (vmax - vrest);
+      if (v(n - 1) >= v90 && v(n) < v90) {
+        nr = n;
+        break;
+      }
+      vmax = std::max(vmax, v(n));
+    }
+    const int64_t nend = nr >= 0 ? nr : steps - 1;
+    int64_t best = na;
+    for (int64_t n = na + 1; n <= nend; ++n)
+      if (slope(n) > slope(best)) best = n;
+    tup[q] = t_prev(best) + 0.5 * dt;
+    if (nr >= 0) {
+      const double w = (v(nr - 1) - v90) / (v(nr - 1) - v(nr));
+      apd[q] = (t_prev(nr) + w * dt) - tup[q];
+    }
+  }
+  return 0;
+}
+
 }  // extern "C"

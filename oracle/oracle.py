@@ -69,6 +69,8 @@ def lib():
         L.orc_backward.argtypes = [vp, _dp, _dp]
         L.orc_k_rule.argtypes = [C.c_double, C.c_int]
         L.orc_l_rule.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.orc_apd90.argtypes = [C.c_int64, C.c_int64, _dp, C.c_int64, C.c_double, C.c_double,
+                                _dp, _dp]
         _lib = L
     return _lib
 
@@ -319,3 +321,16 @@ def k_rule(dvdt, k_max):
 
 def l_rule(dt, dt_s, l_round=0):
     return lib().orc_l_rule(float(dt), float(dt_s), int(l_round))
+
+
+def apd90(samples, dt, thr, step0=0):
+    """APD90 and upstroke time per node from reaction-entry samples
+    (steps x nodes, sample n taken at (step0 + n) dt + dt/2); see orc_apd90
+    in oracle.cpp for the definition.  Returns (apd, tup), -1 where not
+    measured."""
+    V = np.ascontiguousarray(samples, np.float64)
+    steps, ns = V.shape
+    apd = np.zeros(ns, np.float64)
+    tup = np.zeros(ns, np.float64)
+    _check(lib().orc_apd90(steps, ns, V, int(step0), float(dt), float(thr), apd, tup))
+    return apd, tup

@@ -29,6 +29,40 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// APD90 of the first action potential from the reaction-entry samples v0 =
+// V_{n-1}, v1 = V_n of outer step n (times in FP64, one rounding per
+// operation): the sampled interval of largest slope from activation on gives
+// the upstroke time (its midpoint), V_rest is the sample before activation,
+// V_max the largest sample since, and repolarisation the first interval
+// crossing V_max - 0.9 (V_max - V_rest) downwards, interpolated linearly.
+__device__ __forceinline__ void track_apd(double* apd, int64_t Np, int64_t i, int64_t step,
+                                          double dt, double v0, double v1, bool first) {
+  double* tup = apd;
+  double* dmax = apd + Np;
+  double* vmax = apd + 2 * Np;
+  double* vrest = apd + 3 * Np;
+  double* trep = apd + 4 * Np;
+  const double t0 = rn_add(rn_add(rn_mul((double)step, dt), rn_mul(0.5, dt)), -dt);
+  const double tmid = rn_add(t0, rn_mul(0.5, dt));
+  const double d = (v1 - v0) / dt;
+  if (first) {
+    tup[i] = tmid;
+    dmax[i] = d;
+    vmax[i] = v1;
+    vrest[i] = v0;
+    return;
+  }
+  if (trep[i] >= 0.0 || tup[i] < 0.0) return;   // done, or not activated
+  if (d > dmax[i]) {
+    dmax[i] = d;
+    tup[i] = tmid;
+  }
+  const double vm = vmax[i];
+  const double v90 = rn_add(vm, -rn_mul(0.9, rn_add(vm, -vrest[i])));
+  if (v0 >= v90 && v1 < v90) trep[i] = rn_add(t0, rn_mul((v0 - v90) / (v0 - v1), dt));
+  if (v1 > vm) vmax[i] = v1;
+}
+
 // The substep count of node i at outer step `step`, with the bookkeeping that
 // goes with reaction entry: non-finite check, activation time, V_prev, k-trace
 // record/replay and the stored k.  y/p are needed only for dvdt_src = 1.
@@ -47,11 +81,14 @@ __device__ __forceinline__ int decide_k(const IonArgs<T>& a, int64_t i, int64_t 
   // activation time: first upward crossing between reaction-entry samples
   if (step > 0) {
     const double thr = a.lat_thr, v0 = (double)vp, v1 = (double)Vb;
+    bool first = false;
     if (v0 < thr && v1 >= thr && a.lat[i] < 0.0) {
       const double w = (thr - v0) / (v1 - v0);
       const double tA = rn_add(rn_mul((double)step, dt), rn_mul(0.5, dt));
       a.lat[i] = rn_add(rn_add(tA, -dt), rn_mul(w, dt));
+      first = true;
     }
+    if (a.apd) track_apd(a.apd, a.Np, i, step, dt, v0, v1, first);
   }
   a.vprev[i] = Vb;
   // k = min(k0 + floor|d|, k_max), k0 = 5 for d > 0 else 1

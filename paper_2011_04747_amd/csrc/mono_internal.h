@@ -206,6 +206,9 @@ struct IonArgs {
   KTraceArgs kt;
   int* flag;                 // non-finite latch
   unsigned long long* stats; // 4 counters or nullptr
+  double* apd;               // APD90 trackers (rows of Np: upstroke time,
+                             // largest slope, V_max, V_rest, repolarisation
+                             // time) or nullptr
 };
 
 // ---------------------------------------------------------------------------

@@ -116,6 +116,7 @@ struct mono_sim {
   void* d_st = nullptr;
   void* d_vprev = nullptr;
   double* d_lat = nullptr;
+  double* d_apd = nullptr;         // APD90 trackers (5 rows of Np) or nullptr
   uint8_t* d_k = nullptr;
   void* d_par = nullptr;
   uint32_t par_pernode = 0;
@@ -381,6 +382,7 @@ IonArgs<T> ion_args(mono_sim* s, void* V, int64_t g) {
   a.kt = s->kt;
   a.flag = s->d_flag;
   a.stats = s->stats_on ? s->d_stats : nullptr;
+  a.apd = s->d_apd;
   return a;
 }
 
@@ -561,6 +563,7 @@ void free_model(mono_sim* s) {
   dfree(s->d_st);
   dfree(s->d_vprev);
   dfree(s->d_lat);
+  dfree(s->d_apd);
   dfree(s->d_k);
   dfree(s->d_par);
 }
@@ -661,6 +664,7 @@ void enqueue_tape_step(mono_sim* s, int64_t g, T* vs, T* entry, uint8_t* krec, i
     launch_diffusion<T>(s->layout, a, s->lc, s->stream);
   }
   IonArgs<T> ia = ion_args<T>(s, entry, g);
+  ia.apd = nullptr;   // segment recomputes replay earlier steps
   ia.Vout = vs + (size_t)L * Np;
   ia.tape_st = entry + Np;
   ia.kt.mode |= 1;
@@ -1328,6 +1332,18 @@ mono_status mono_get_state(mono_sim* s, int32_t field, double* dst, int64_t coun
   mono_status st = require_model(s);
   if (st != MONO_OK) return st;
   if (!dst || count != s->n) return fail(MONO_EINVAL, "count must equal n_nodes");
+  if (field == MONO_FIELD_APD || field == MONO_FIELD_TUP) {
+    if (!s->d_apd) return fail(MONO_ESTATE, "APD tracking is off (mono_track_apd)");
+    std::vector<double> tup(s->n), trep(s->n);
+    HIP_TRY(hipMemcpyAsync(tup.data(), s->d_apd, s->n * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(trep.data(), s->d_apd + 4 * s->Np, s->n * 8, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < s->n; ++i)
+      dst[i] = field == MONO_FIELD_TUP ? tup[i]
+                                       : ((tup[i] >= 0.0 && trep[i] >= 0.0) ? trep[i] - tup[i] : -1.0);
+    return check_flag(s);
+  }
   size_t es = 0;
   void* src = field_ptr(s, field, es);
   if (!src) return fail(MONO_EINVAL, "unknown field");
@@ -1361,7 +1377,8 @@ mono_status mono_set_state(mono_sim* s, int32_t field, const double* src, int64_
   mono_status st = require_model(s);
   if (st != MONO_OK) return st;
   if (!src || count != s->n) return fail(MONO_EINVAL, "count must equal n_nodes");
-  if (field == MONO_FIELD_K) return fail(MONO_EINVAL, "field K is read-only");
+  if (field == MONO_FIELD_K || field == MONO_FIELD_APD || field == MONO_FIELD_TUP)
+    return fail(MONO_EINVAL, "field is read-only");
   size_t es = 0;
   void* dst = field_ptr(s, field, es);
   if (!dst) return fail(MONO_EINVAL, "unknown field");
@@ -1377,6 +1394,42 @@ mono_status mono_set_state(mono_sim* s, int32_t field, const double* src, int64_
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->latched = false;
   }
+  return MONO_OK;
+}
+
+mono_status mono_track_apd(mono_sim* s, int32_t on) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (on != 0 && on != 1) return fail(MONO_EINVAL, "on must be 0 or 1");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  drop_graph(s);
+  if (!on) {
+    dfree(s->d_apd);
+    return MONO_OK;
+  }
+  if (!s->d_apd && dalloc(&s->d_apd, 5 * s->Np))
+    return fail(MONO_ENOMEM, "device allocation failed");
+  // upstroke and repolarisation times -1 (not activated), the rest 0
+  std::vector<double> init(5 * s->Np, 0.0);
+  std::fill(init.begin(), init.begin() + s->Np, -1.0);
+  std::fill(init.begin() + 4 * s->Np, init.end(), -1.0);
+  HIP_TRY(hipMemcpy(s->d_apd, init.data(), init.size() * 8, hipMemcpyHostToDevice));
+  return MONO_OK;
+}
+
+mono_status mono_nrmse(const double* u_hat, const double* u, int64_t n, double* out) {
+  if (!u_hat || !u || !out || n < 0) return fail(MONO_EINVAL, "bad argument");
+  double ss = 0.0, lo = INFINITY, hi = -INFINITY;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(u_hat[i] >= 0.0) || !(u[i] >= 0.0)) continue;
+    const double e = u_hat[i] - u[i];
+    ss += e * e;
+    lo = std::min(lo, u[i]);
+    hi = std::max(hi, u[i]);
+    ++cnt;
+  }
+  *out = (cnt > 0 && hi > lo) ? std::sqrt(ss / (double)cnt) / (hi - lo) : NAN;
   return MONO_OK;
 }
 

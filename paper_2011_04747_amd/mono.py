@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmono.so")
 
 F64, F32 = 0, 1
 LAYOUT_AUTO, LAYOUT_ELL, LAYOUT_STENCIL = 0, 1, 2
-FIELD_V, FIELD_VPREV, FIELD_LAT, FIELD_K, FIELD_STATE0 = 0, 1, 2, 3, 16
+FIELD_V, FIELD_VPREV, FIELD_LAT, FIELD_K, FIELD_APD, FIELD_TUP, FIELD_STATE0 = 0, 1, 2, 3, 4, 5, 16
 DAETI, OSTAR, OST = 0, 1, 2
 DEBUG_KTRACE, DEBUG_VCLAMP, DEBUG_FORCE_L, DEBUG_STATS, DEBUG_STATS_ENABLE = 1, 2, 3, 4, 5
 DEBUG_KTIMES = 6
@@ -36,7 +36,8 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_sync", "mono_destroy", "mono_last_error", "mono_apply_phase", "mono_debug",
            "mono_model_flops", "mono_set_launch", "mono_get_launch",
            "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
-           "mono_forward_taped", "mono_backward", "mono_sample_sensors", "mono_set_allocator")
+           "mono_forward_taped", "mono_backward", "mono_sample_sensors", "mono_set_allocator",
+           "mono_track_apd", "mono_nrmse")
 
 
 class MonoError(RuntimeError):
@@ -143,6 +144,8 @@ def lib():
             "mono_set_launch": [vp, C.POINTER(Launch)],
             "mono_get_launch": [vp, C.POINTER(Launch)],
             "mono_set_allocator": [ALLOC_FN, FREE_FN, vp],
+            "mono_track_apd": [vp, i32],
+            "mono_nrmse": [vp, vp, i64, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -163,6 +166,17 @@ def _check(rc):
 
 def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def nrmse(u_hat, u):
+    """Eq. (4): sqrt(mean (u_hat - u)^2) / (max u - min u) over the entries
+    where both values are measured (non-negative); NaN if none or no range."""
+    a = _c(u_hat, np.float64)
+    b = _c(u, np.float64)
+    assert a.shape == b.shape and a.ndim == 1
+    out = np.zeros(1, np.float64)
+    _check(lib().mono_nrmse(a.ctypes.data, b.ctypes.data, a.size, out.ctypes.data))
+    return float(out[0])
 
 
 def model_flops(model, state, params):
@@ -292,6 +306,10 @@ class Sim:
 
     def set_time_level(self, step):
         _check(lib().mono_set_time_level(self.h, int(step)))
+
+    def track_apd(self, on=True):
+        """Start (and reset) or stop APD90 tracking (FIELD_APD, FIELD_TUP)."""
+        _check(lib().mono_track_apd(self.h, 1 if on else 0))
 
     def info(self, inst=0):
         i = Info()

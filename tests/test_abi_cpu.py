@@ -100,3 +100,18 @@ def test_allocator_hook_arguments():
     mono.set_allocator()
     rc = mono.lib().mono_set_allocator(mono.ALLOC_FN(lambda n, c: None), mono.FREE_FN(), None)
     assert mono.STATUS[rc] == "EINVAL"
+
+
+def test_nrmse_of_eq4():
+    """mono_nrmse (host function of the library): eq. (4) over the entries
+    measured in both fields."""
+    from paper_2011_04747_amd import mono
+    rng = np.random.default_rng(0)
+    u = rng.uniform(10.0, 60.0, 1000)
+    uh = u + rng.normal(0.0, 0.5, 1000)
+    uh[::97] = -1.0                    # unmeasured entries are left out
+    keep = uh >= 0
+    ref = np.sqrt(np.mean((uh[keep] - u[keep]) ** 2)) / (u[keep].max() - u[keep].min())
+    assert mono.nrmse(uh, u) == pytest.approx(ref, rel=1e-12)
+    assert mono.nrmse(u, u) == 0.0
+    assert np.isnan(mono.nrmse(np.full(3, 5.0), np.full(3, 5.0)))

@@ -1,0 +1,109 @@
+"""APD90 tracked by the reaction kernel (MONO_FIELD_APD / MONO_FIELD_TUP)
+against the oracle's measurement from the same reaction-entry samples, and
+the nRMSE of eq. (4).
+
+Tolerances: FP64 with the oracle's k decisions replayed, 1e-6 ms on every
+upstroke and APD90 time (the samples agree to ~1e-12 relative; a repolarising
+slope of ~1 mV/ms turns that into ~1e-10 ms); FP32, 0.5 ms (the activation-
+time tolerance), identical sets of measured nodes."""
+import numpy as np
+import pytest
+
+from paper_2011_04747_amd import mono
+from paper_2011_04747_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    T.cuda.set_device(0)
+    return T
+
+
+def _oracle_apd(w, n_steps, record_k=True):
+    from oracle.oracle import Oracle, apd90
+    o = Oracle.from_workload(w)
+    kt = o.record_k(n_steps)[0] if record_k else None
+    buf = o.record_sensors(np.arange(w.mesh.n_nodes, dtype=np.int32), n_steps)
+    o.step(n_steps, w.dt)
+    apd, tup = apd90(buf, w.dt, w.lat_threshold)
+    return apd, tup, kt
+
+
+def _gpu_apd(torch, w, n_steps, prec, kt=None, launch=None, chunks=None):
+    s = mono.Sim.from_workload(w, prec)
+    if launch:
+        s.set_launch(**launch)
+    if kt is not None:
+        rep = torch.from_numpy(kt).cuda()
+        rec = torch.zeros_like(rep)
+        s.ktrace(3, rec.data_ptr(), rep.data_ptr(), n_steps, 0)
+    s.track_apd()
+    for c in (chunks or [n_steps]):
+        s.step(c, w.dt)
+    torch.cuda.synchronize()
+    return s.get(mono.FIELD_APD), s.get(mono.FIELD_TUP), s
+
+
+@pytest.mark.parametrize("which", ["cable", "sheet"])
+def test_apd_fp64_matches_oracle(torch, which):
+    if which == "cable":
+        w = W.cable_ms(t_end=500.0)
+    else:
+        w = W.sheet_tp06(n=21, dx=0.025, t_end=420.0)
+    n = w.n_steps
+    apd_o, tup_o, kt = _oracle_apd(w, n)
+    assert (apd_o > 0).all()
+    apd_g, tup_g, _ = _gpu_apd(torch, w, n, "f64", kt=kt)
+    assert np.abs(tup_g - tup_o).max() <= 1e-6
+    assert np.abs(apd_g - apd_o).max() <= 1e-6
+
+
+def test_apd_fp32_sheet(torch):
+    w = W.sheet_tp06(n=21, dx=0.025, t_end=420.0)
+    n = w.n_steps
+    apd_o, tup_o, _ = _oracle_apd(w, n, record_k=False)
+    apd_g, tup_g, _ = _gpu_apd(torch, w, n, "f32")
+    assert ((apd_g >= 0) == (apd_o >= 0)).all()
+    assert np.abs(apd_g - apd_o).max() <= 0.5
+    assert np.abs(tup_g - tup_o).max() <= 0.5
+
+
+def test_apd_graph_eager_and_launch_shapes_agree(torch):
+    """Graph replays of any size, eager steps, the ordered reaction and every
+    diffusion kernel give the same tracked times (bitwise)."""
+    w = W.slab_ischemic(shape=(23, 19, 9), t_end=330.0)
+    n = w.n_steps
+    ref = None
+    for launch, chunks in ((None, None), (dict(graph_steps=7), [1, 2, 300, n - 303]),
+                           (dict(react_sort=1, graph_steps=64), None),
+                           (dict(diff_classes=0, react_block=128), None)):
+        a, t, _ = _gpu_apd(torch, w, n, "f32", launch=launch, chunks=chunks)
+        if ref is None:
+            ref = (a, t)
+            assert (a > 0).sum() > 0
+        else:
+            assert (a == ref[0]).all() and (t == ref[1]).all()
+
+
+def test_apd_off_reset_and_incomplete(torch):
+    w = W.cable_ms(t_end=100.0)
+    s = mono.Sim.from_workload(w, "f64")
+    with pytest.raises(mono.MonoError):
+        s.get(mono.FIELD_APD)          # tracking is off
+    s.track_apd()
+    s.step(w.n_steps, w.dt)
+    apd, tup = s.get(mono.FIELD_APD), s.get(mono.FIELD_TUP)
+    # 100 ms: every node activated, none repolarised yet
+    assert (tup > 0).all() and (apd == -1.0).all()
+    s.track_apd()                      # reset: nothing measured
+    assert (s.get(mono.FIELD_TUP) == -1.0).all()
+    with pytest.raises(mono.MonoError):
+        s.set(mono.FIELD_APD, apd)     # read-only
+    s.track_apd(False)
+    with pytest.raises(mono.MonoError):
+        s.get(mono.FIELD_TUP)
