@@ -1,0 +1,99 @@
+"""DAETI / OSTAR / OST on the 2D sheet experiment of the paper (Sec. 3.1),
+with the paper's accuracy measures, on the GPU.
+
+All three methods integrate both terms explicitly with the same kernels:
+  * OST:   dt = 0.01 ms, one reaction substep (k = 1), one diffusion substep
+           per half step;
+  * OSTAR: adaptive reaction substeps, one diffusion substep per half step,
+           dt = 0.1 ms where the diffusion bound of eq. (3) allows it, else
+           dt = dt_s (Sec. 3);
+  * DAETI: dt = 0.1 ms, adaptive reaction and diffusion substeps (Sec. 2).
+Reported per method: wall time of the run on the GPU, longitudinal
+conduction velocity (from the activation times of the two nodes a quarter of
+the sheet from either edge on its middle row), APD90 at the sheet centre,
+mean activation time and APD90, and, for DAETI and OSTAR, e_LAT and e_APD of
+eq. (4) against OST.
+
+    python -m paper_2011_04747_amd.compare [--n 501] [--dx 0.01] [--t-end 500]
+                                           [--precision f64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import mono
+from . import workloads as W
+
+
+def run_method(w, method: int, dt: float, precision: str) -> dict:
+    s = mono.Sim.from_workload(w, precision)
+    s.set_method(method)
+    s.track_apd()
+    n_steps = int(np.ceil(w.t_end / dt - 1e-9))
+    s.prepare(dt)
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(n_steps, dt)
+    s.sync()
+    wall = time.perf_counter() - t0
+    info = s.info()
+    out = {"dt": dt, "steps": n_steps, "l": info["l"], "k_max": info["k_max"],
+           "wall_s": wall, "lat": s.get(mono.FIELD_LAT), "apd": s.get(mono.FIELD_APD)}
+    s.close()
+    return out
+
+
+def compare(n: int = 501, dx: float = 0.01, t_end: float = 500.0,
+            precision: str = "f64") -> dict:
+    w = W.sheet_planar_tp06(n=n, dx=dx, t_end=t_end, precision=precision)
+    probe = mono.Sim.from_workload(w, precision)
+    dt_s = probe.info()["dt_s"]
+    probe.close()
+    plan = {"OST": (mono.OST, 0.01), "OSTAR": (mono.OSTAR, min(0.1, dt_s)),
+            "DAETI": (mono.DAETI, 0.1)}
+    runs = {name: run_method(w, m, dt, precision) for name, (m, dt) in plan.items()}
+    mid = n // 2
+    i1, i2 = mid * n + n // 4, mid * n + (3 * n) // 4
+    centre = mid * n + mid
+    dist = (3 * n // 4 - n // 4) * dx
+    ref = runs["OST"]
+    res = {"workload": f"sheet_planar_tp06 {n}x{n}, dx={dx} cm, fibres along x, "
+                       f"S1 x<=0.05 cm at 50 ms, {t_end} ms, {precision}",
+           "dt_s": dt_s, "methods": {}}
+    for name, r in runs.items():
+        lat, apd = r["lat"], r["apd"]
+        cv = dist / (lat[i2] - lat[i1]) if lat[i1] >= 0 and lat[i2] > lat[i1] else float("nan")
+        e = {"dt": r["dt"], "steps": r["steps"], "l": r["l"], "k_max": r["k_max"],
+             "wall_s": r["wall_s"], "cv_cm_per_ms": cv,
+             "apd90_centre_ms": float(apd[centre]),
+             "mean_lat_ms": float(lat[lat >= 0].mean()) if (lat >= 0).any() else float("nan"),
+             "mean_apd90_ms": float(apd[apd >= 0].mean()) if (apd >= 0).any() else float("nan"),
+             "activated": int((lat >= 0).sum()), "apd_measured": int((apd >= 0).sum())}
+        if name != "OST":
+            e["e_lat"] = mono.nrmse(lat, ref["lat"])
+            e["e_apd"] = mono.nrmse(apd, ref["apd"])
+            e["speedup_vs_ost"] = ref["wall_s"] / r["wall_s"]
+        res["methods"][name] = e
+    res["methods"]["DAETI"]["speedup_vs_ostar"] = (runs["OSTAR"]["wall_s"]
+                                                   / runs["DAETI"]["wall_s"])
+    return res
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=501)
+    ap.add_argument("--dx", type=float, default=0.01)
+    ap.add_argument("--t-end", type=float, default=500.0)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    a = ap.parse_args(argv)
+    print(json.dumps(compare(a.n, a.dx, a.t_end, a.precision)), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

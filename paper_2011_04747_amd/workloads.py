@@ -290,6 +290,22 @@ def slab_ischemic(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,
                     extra={"ischemic_nodes": int(isc.sum())})
 
 
+def sheet_planar_tp06(n: int = 501, dx: float = 0.01, D_l: float = 0.0017,
+                      ratio: float = 0.25, t_on: float = 50.0, t_end: float = 500.0,
+                      dt: float = 0.1, precision: str = "f64",
+                      amp: Optional[float] = None) -> Workload:
+    """The 2D experiment of Sec. 3.1 on a 5 x 5 cm sheet (n x n nodes at dx):
+    fibres along x, d0 = 0.0017 cm^2/ms with transverse ratio 0.25, a 1 ms
+    planar stimulus on the left edge at t = 50 ms.  TP06 epicardial cells
+    stand in for the O'Hara model."""
+    xyz, conn, et = structured_grid((n, n), dx)
+    De = fibre_tensor(angle_fibres(np.zeros(conn.shape[0]), 2), D_l, ratio * D_l)
+    mesh = Mesh(2, xyz, et, conn, De, grid_shape=(n, n))
+    a = STIM_AMP_TP06_PLANAR if amp is None else amp
+    return Workload("sheet_planar_tp06_2d", mesh, MODEL_TP06, tp06_params(mesh.n_nodes),
+                    [_planar_s1(xyz, a, t_on=t_on)], dt, t_end, 0.01, precision, -40.0)
+
+
 def batched_sheets(n_inst: int = 64, side_lo: int = 50, side_hi: int = 400,
                    dx: float = 0.025, D_l: float = 0.0012, D_t: float = 0.0003,
                    t_end: float = 400.0, dt: float = 0.1, seed: int = 4,

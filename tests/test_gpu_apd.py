@@ -107,3 +107,26 @@ def test_apd_off_reset_and_incomplete(torch):
     s.track_apd(False)
     with pytest.raises(mono.MonoError):
         s.get(mono.FIELD_TUP)
+
+
+def test_method_comparison_driver(torch):
+    """The three-method comparison on a small sheet: every node activates and
+    repolarises under every method, DAETI and OSTAR stay close to OST in the
+    paper's nRMSE measures, and the conduction velocities are physiological."""
+    from paper_2011_04747_amd.compare import compare
+    r = compare(n=41, dx=0.025, t_end=420.0, precision="f64")
+    n = 41 * 41
+    for name, m in r["methods"].items():
+        assert m["activated"] == n and m["apd_measured"] == n, name
+        assert 0.02 < m["cv_cm_per_ms"] < 0.12, (name, m["cv_cm_per_ms"])
+        assert 200.0 < m["apd90_centre_ms"] < 400.0, (name, m["apd90_centre_ms"])
+    ost = r["methods"]["OST"]
+    for name in ("DAETI", "OSTAR"):
+        m = r["methods"][name]
+        assert m["e_lat"] < 0.05
+        # on a homogeneous sheet the APD90 range is a few ms, so eq. (4)
+        # divides by a small number; the mean APD90 itself agrees closely
+        assert abs(m["mean_apd90_ms"] - ost["mean_apd90_ms"]) < 5.0
+        assert np.isfinite(m["e_apd"])
+    assert r["methods"]["OST"]["k_max"] == 1 and r["methods"]["OST"]["l"] == 1
+    assert r["methods"]["DAETI"]["l"] >= 1
