@@ -9,7 +9,8 @@
 //
 // What it computes (paper Sec. 2):
 //   * FE stiffness K and row-sum lumped mass m of the diffusion problem,
-//     eq. (2b)-(2c), on Q1 line / quad / hex elements (2^d Gauss points).
+//     eq. (2b)-(2c), on Q1 line / quad / hex elements (2^d Gauss points)
+//     and on linear triangles and tetrahedra (constant gradients).
 //   * The Gershgorin stable step, eq. (3):
 //       dt_s = 0.9 * min_i m_ii / (k_ii + sum_{j!=i} |k_ij|)
 //     and the diffusion substep count l and dt_ad = dt/(2l) (Sec. 2).
@@ -112,6 +113,39 @@ double invert(int dim, const double* A, double* Ai) {
   Ai[7] = (A[1] * A[6] - A[0] * A[7]) / det;
   Ai[8] = (A[0] * A[4] - A[1] * A[3]) / det;
   return det;
+}
+
+// Linear simplex (triangle, tetrahedron) with nodes x_0..x_dim: on it
+// x - x_0 = E^T lambda for E's rows x_a - x_0 (a = 1..dim), so the gradient
+// of the barycentric coordinate lambda_a is column a-1 of E^-1 and that of
+// lambda_0 minus their sum; all constant.  Ke[a][b] = vol grad l_a . D
+// grad l_b, me[a] = vol / (dim + 1) (int lambda_a over the simplex).
+int simplex_matrices(int dim, const double* X, const double* D, double* Ke, double* me) {
+  const int nen = dim + 1;
+  double E[9], Ei[9];
+  for (int r = 0; r < dim; ++r)
+    for (int c = 0; c < dim; ++c) E[r * dim + c] = X[(r + 1) * dim + c] - X[c];
+  const double det = invert(dim, E, Ei);
+  if (!(det > 0.0)) return -1;
+  const double vol = det / (dim == 2 ? 2.0 : 6.0);
+  double G[4][3];
+  for (int c = 0; c < dim; ++c) {
+    G[0][c] = 0.0;
+    for (int a = 1; a < nen; ++a) {
+      G[a][c] = Ei[c * dim + (a - 1)];
+      G[0][c] -= G[a][c];
+    }
+  }
+  for (int a = 0; a < nen; ++a) {
+    me[a] = vol / nen;
+    for (int b = 0; b < nen; ++b) {
+      double sum = 0.0;
+      for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) sum += G[a][i] * D[i * dim + j] * G[b][j];
+      Ke[a * nen + b] = vol * sum;
+    }
+  }
+  return 0;
 }
 
 // Element stiffness Ke[a][b] = int grad N_a . D grad N_b and lumped mass
@@ -850,7 +884,8 @@ const char* orc_last_error() { return g_err.c_str(); }
 void* orc_create(int dim, int64_t n_nodes, const double* xyz, int etype, int64_t n_elems,
                  const int32_t* conn, const double* D_elem, const double* sigma, int32_t n_inst,
                  const int64_t* inst_node_off) {
-  if (dim < 1 || dim > 3 || n_nodes <= 0 || n_elems < 0 || etype != (1 << dim)) {
+  const bool simplex = dim >= 2 && etype == dim + 1;
+  if (dim < 1 || dim > 3 || n_nodes <= 0 || n_elems < 0 || (etype != (1 << dim) && !simplex)) {
     fail("bad mesh description");
     return nullptr;
   }
@@ -873,7 +908,9 @@ void* orc_create(int dim, int64_t n_nodes, const double* xyz, int etype, int64_t
       }
       for (int d = 0; d < dim; ++d) X[a * dim + d] = xyz[(int64_t)g * dim + d];
     }
-    if (element_matrices(dim, nen, X, D_elem + e * dim * dim, Ke, me) != 0) {
+    const int bad = simplex ? simplex_matrices(dim, X, D_elem + e * dim * dim, Ke, me)
+                            : element_matrices(dim, nen, X, D_elem + e * dim * dim, Ke, me);
+    if (bad != 0) {
       delete s;
       fail("non-positive Jacobian");
       return nullptr;

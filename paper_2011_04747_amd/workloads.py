@@ -11,6 +11,7 @@ Element node ordering (both sides rely on it):
   * line2: x-, x+
   * quad4: (0,0) (1,0) (1,1) (0,1)                        counter-clockwise
   * hex8 : the quad4 face at z-, then the quad4 face at z+
+  * tri3 / tet4 (linear simplices): any order with positive orientation
 
 Node numbering of structured grids is lexicographic, x fastest:
   node(ix, iy, iz) = ix + nx*(iy + ny*iz).
@@ -33,7 +34,9 @@ MODEL_MS = 1
 MODEL_TP06 = 2
 
 ETYPE_LINE2 = 2
+ETYPE_TRI3 = 3
 ETYPE_QUAD4 = 4
+ETYPE_TET4 = 4          # with dim 3
 ETYPE_HEX8 = 8
 
 # Per-node TP06 parameter rows (SoA): extracellular K+ and five conductance
@@ -145,6 +148,66 @@ def structured_grid(shape: Tuple[int, ...], h: float | Tuple[float, ...]):
     else:
         raise ValueError("dim must be 1, 2 or 3")
     return xyz, conn.astype(np.int32), et
+
+
+def structured_simplices(shape: Tuple[int, ...], h: float):
+    """Regular grid split into linear simplices: every square into two
+    triangles, every cube into the six tetrahedra around its main diagonal
+    (Kuhn / Freudenthal split), all positively oriented.  Returns
+    (xyz, conn, etype) with the grid's node numbering."""
+    xyz, q1, _ = structured_grid(shape, h)
+    if len(shape) == 2:
+        n00, n10, n11, n01 = (q1[:, a] for a in range(4))
+        conn = np.concatenate([np.stack([n00, n10, n11], 1), np.stack([n00, n11, n01], 1)])
+        return xyz, conn.astype(np.int32), ETYPE_TRI3
+    if len(shape) != 3:
+        raise ValueError("simplices need dim 2 or 3")
+    # cube corner with offset bits (bx, by, bz) is hex node
+    # 4 bz + [(0,0),(1,0),(1,1),(0,1)].index((bx, by))
+    def corner(bx, by, bz):
+        return q1[:, 4 * bz + [(0, 0), (1, 0), (1, 1), (0, 1)].index((bx, by))]
+    tets = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        b = [0, 0, 0]
+        path = [corner(*b)]
+        for ax in perm:
+            b[ax] = 1
+            path.append(corner(*b))
+        # det [e_p0, e_p0 + e_p1, e_p0 + e_p1 + e_p2] = sign of the permutation
+        odd = perm in ((0, 2, 1), (1, 0, 2), (2, 1, 0))
+        if odd:
+            path[1], path[2] = path[2], path[1]
+        tets.append(np.stack(path, 1))
+    return xyz, np.concatenate(tets).astype(np.int32), ETYPE_TET4
+
+
+def renumber(xyz: np.ndarray, conn: np.ndarray, order: str, seed: int = 0):
+    """Node renumbering of a mesh: "grid" keeps it, "random" shuffles it
+    (seeded), "rcm" shuffles and then applies reverse Cuthill-McKee on the
+    node graph (the bandwidth-reducing order an unstructured mesh would be
+    stored in).  Returns (xyz, conn, new_of_old)."""
+    n = xyz.shape[0]
+    if order == "grid":
+        return xyz, conn, np.arange(n)
+    rng = np.random.default_rng(seed)
+    new_of_old = rng.permutation(n)
+    if order == "rcm":
+        import scipy.sparse as sp
+        from scipy.sparse.csgraph import reverse_cuthill_mckee
+        c = new_of_old[conn]
+        k = c.shape[1]
+        rows = np.repeat(c, k, axis=1).reshape(-1)
+        cols = np.tile(c, (1, k)).reshape(-1)
+        g = sp.csr_matrix((np.ones(rows.size, np.int8), (rows, cols)), shape=(n, n))
+        rcm = np.asarray(reverse_cuthill_mckee(g, symmetric_mode=True))   # old(shuffled) at new
+        pos = np.empty(n, np.int64)
+        pos[rcm] = np.arange(n)
+        new_of_old = pos[new_of_old]
+    elif order != "random":
+        raise ValueError("order must be grid, random or rcm")
+    xyz2 = np.empty_like(xyz)
+    xyz2[new_of_old] = xyz
+    return xyz2, new_of_old[conn].astype(np.int32), new_of_old
 
 
 def centroids(xyz: np.ndarray, conn: np.ndarray) -> np.ndarray:
@@ -288,6 +351,37 @@ def slab_ischemic(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,
     return Workload("slab_tp06_3d_ischemic", mesh, MODEL_TP06, p, [s1, s2], dt,
                     t_end, 0.01, precision, -40.0,
                     extra={"ischemic_nodes": int(isc.sum())})
+
+
+def slab_ischemic_tets(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,
+                       D_t: float = 0.0003, order: str = "rcm", seed: int = 7,
+                       t_end: float = 1000.0, dt: float = 0.1, s2_time: float = 320.0,
+                       precision: str = "f32", amp: Optional[float] = None) -> Workload:
+    """The ischemic TP06 slab on linear tetrahedra (six per grid cube), its
+    nodes renumbered as an unstructured mesh would be (`order`, see
+    renumber): the 3D workload class of the paper's biventricular runs
+    (Sec. 3.3), with the slab's fibres, ischemic zone and stimuli."""
+    xyz, conn, et = structured_simplices(shape, dx)
+    xyz, conn, _ = renumber(xyz, conn, order, seed)
+    thickness = (shape[2] - 1) * dx
+    c = centroids(xyz, conn)
+    theta = np.deg2rad(-60.0 + 120.0 * c[:, 2] / thickness)
+    De = fibre_tensor(angle_fibres(theta, 3), D_l, D_t)
+    mesh = Mesh(3, xyz, et, conn, De, grid_shape=None)
+    p = tp06_params(mesh.n_nodes)
+    Lx, Ly = (shape[0] - 1) * dx, (shape[1] - 1) * dx
+    isc = ischemic_zone(xyz, (Lx, Ly), 0.5 * thickness,
+                        semi=(0.4 * Lx / 2.0, 0.3 * Ly / 2.0, 0.25 * thickness / 0.5))
+    p[0, isc] = 8.0
+    p[1, isc] = 0.7
+    a = STIM_AMP_TP06_PLANAR if amp is None else amp
+    s1 = _planar_s1(xyz, a)
+    s2n = np.nonzero((xyz[:, 0] <= 0.25 * Lx + 1e-12) &
+                     (xyz[:, 1] <= 0.5 * Ly + 1e-12))[0].astype(np.int32)
+    s2 = Stimulus(s2n, s2_time, 1.0, a)
+    return Workload("slab_tp06_3d_ischemic_tets", mesh, MODEL_TP06, p, [s1, s2], dt,
+                    t_end, 0.01, precision, -40.0,
+                    extra={"ischemic_nodes": int(isc.sum()), "order": order})
 
 
 def sheet_planar_tp06(n: int = 501, dx: float = 0.01, D_l: float = 0.0017,

@@ -467,3 +467,73 @@ def test_workload_stimulus_amplitudes_are_twice_calibrated_thresholds():
     assert W.STIM_AMP_MS_CABLE == 2.0 * th["ms_cable"]
     assert W.STIM_AMP_TP06_CORNER == 2.0 * th["tp06_corner"]
     assert W.STIM_AMP_TP06_PLANAR == 2.0 * th["tp06_planar"]
+
+
+# ---------------------------------------------------------------------------
+# linear simplices (the element class of the paper's 3D meshes, Sec. 3.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_simplex_split_grid_gives_the_finite_difference_stencil(oracle_mod, dim):
+    """On the Freudenthal / Kuhn split of a uniform grid with isotropic D = d,
+    linear elements give exactly the (2 dim + 1)-point finite-difference
+    stencil times h^(dim-2): every coupling along a split diagonal vanishes,
+    and each interior node carries the lumped mass h^dim."""
+    h, d = 0.25, 0.7
+    shape = (6, 5) if dim == 2 else (5, 4, 4)
+    xyz, conn, et = W.structured_simplices(shape, h)
+    De = np.broadcast_to(d * np.eye(dim), (conn.shape[0], dim, dim)).copy()
+    o = oracle_mod.Oracle(W.Mesh(dim, xyz, et, conn, De))
+    K, m = o.dense_K()
+    n = xyz.shape[0]
+    strides = [1, shape[0]] + ([shape[0] * shape[1]] if dim == 3 else [])
+    idx = np.indices(shape[::-1]).reshape(dim, -1)[::-1]          # x fastest
+    interior = np.all([(idx[a] > 0) & (idx[a] < shape[a] - 1) for a in range(dim)], axis=0)
+    scale = d * h ** (dim - 2)
+    for i in np.flatnonzero(interior):
+        want = np.zeros(n)
+        want[i] = 2 * dim * scale
+        for s in strides:
+            want[i + s] = want[i - s] = -scale
+        assert np.abs(K[i] - want).max() <= 1e-13 * scale
+        assert m[i] == pytest.approx(h ** dim, rel=1e-13)
+    assert m.sum() == pytest.approx(np.prod([(k - 1) * h for k in shape]), rel=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linear_fields_energy_exact_on_distorted_simplices(oracle_mod, dim):
+    """Linear elements reproduce linear fields: u^T K u = sum_e g^T D_e g |e|
+    for any anisotropic per-element D, on a randomly perturbed split grid;
+    zero row sums, symmetry, lumped mass = volume."""
+    rng = np.random.default_rng(11 + dim)
+    shape = (7, 6) if dim == 2 else (5, 5, 4)
+    xyz, conn, et = W.structured_simplices(shape, 0.1)
+    xyz = xyz + rng.uniform(-0.015, 0.015, xyz.shape)
+    A = rng.uniform(-1, 1, (conn.shape[0], dim, dim))
+    De = np.einsum("eij,ekj->eik", A, A) * 1e-3 + 1e-4 * np.eye(dim)
+    o = oracle_mod.Oracle(W.Mesh(dim, xyz, et, conn, De))
+    K, m = o.dense_K()
+    E = xyz[conn[:, 1:]] - xyz[conn[:, :1]]
+    vol = np.linalg.det(E) / math.factorial(dim)
+    assert (vol > 0).all()
+    assert m.sum() == pytest.approx(vol.sum(), rel=1e-13)
+    for g in np.eye(dim).tolist() + [[1.0, -2.0, 0.5][:dim]]:
+        g = np.array(g)
+        u = xyz @ g
+        ref = np.sum(np.einsum("i,eij,j->e", g, De, g) * vol)
+        assert u @ K @ u == pytest.approx(ref, rel=1e-12)
+    assert np.allclose(K, K.T, atol=1e-15 * np.abs(K).max())
+    assert np.abs(K.sum(1)).max() <= 1e-14 * np.abs(K).max()
+
+
+def test_renumbering_is_a_relabelling(oracle_mod):
+    """The random and RCM orders of the tetrahedral slab relabel nodes only:
+    K and the lumped mass permute with them."""
+    xyz, conn, et = W.structured_simplices((5, 4, 3), 0.2)
+    De = np.broadcast_to(np.diag([1.0, 0.5, 0.25]) * 1e-3, (conn.shape[0], 3, 3)).copy()
+    K0, m0 = oracle_mod.Oracle(W.Mesh(3, xyz, et, conn, De)).dense_K()
+    for order in ("random", "rcm"):
+        x2, c2, new = W.renumber(xyz, conn, order, seed=3)
+        assert sorted(new.tolist()) == list(range(xyz.shape[0]))
+        K, m = oracle_mod.Oracle(W.Mesh(3, x2, et, c2, De)).dense_K()
+        assert np.allclose(K[np.ix_(new, new)], K0, rtol=0, atol=1e-15)
+        assert np.allclose(m[new], m0, rtol=1e-15, atol=0)
