@@ -56,10 +56,21 @@ typedef enum {
 
 typedef enum { MONO_F64 = 0, MONO_F32 = 1 } mono_precision;
 
-/* Q1 elements; the value is the number of element nodes.  Node order:
- * LINE2 x-,x+;  QUAD4 (0,0) (1,0) (1,1) (0,1) in reference coordinates;
- * HEX8 the QUAD4 face at z- followed by the QUAD4 face at z+. */
-typedef enum { MONO_LINE2 = 2, MONO_QUAD4 = 4, MONO_HEX8 = 8 } mono_element;
+/* Elements; the value is the number of element nodes, and with dim it
+ * names the element.  Q1 (2^dim Gauss points): LINE2 x-,x+ (dim 1); QUAD4
+ * (0,0) (1,0) (1,1) (0,1) in reference coordinates (dim 2); HEX8 the QUAD4
+ * face at z- followed by the QUAD4 face at z+ (dim 3).  P1 simplices (one
+ * point at the centroid, exact for their constant gradients; the lumped mass
+ * of a node is the element's volume / (dim + 1)): TRI3 (dim 2) and TET4
+ * (dim 3, the value of QUAD4 in 3D), any node order with positive
+ * orientation (det [x1 - x0, ..., x_dim - x0] > 0). */
+typedef enum {
+  MONO_LINE2 = 2,
+  MONO_TRI3 = 3,
+  MONO_QUAD4 = 4,
+  MONO_TET4 = 4,
+  MONO_HEX8 = 8
+} mono_element;
 
 /* Cell models.  State 0 is always V.
  *  LINEAR   dV/dt = -g (V - E)                    params {g, E}, 1 state

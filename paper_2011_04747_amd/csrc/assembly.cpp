@@ -4,7 +4,9 @@
 // K_ij = sum_e int_e grad N_i . D_e grad N_j,  m_i = sum_e int_e N_i
 // (row-sum lumping of the consistent mass, which is what makes the
 // forward-Euler diffusion substep explicit and what eq. 3's m_ii refers to).
-// Q1 isoparametric elements, 2^dim Gauss points.  Per-node conductivity
+// Q1 isoparametric elements with 2^dim Gauss points, and P1 simplices
+// (triangles, tetrahedra) with one point at the centroid (their gradients
+// are constant, so the rule is exact).  Per-node conductivity
 // scales the off-diagonal entries by (sigma_i + sigma_j)/2 and the diagonal
 // is reset to minus the off-diagonal row sum, so K stays symmetric with zero
 // row sums.
@@ -30,17 +32,34 @@ inline double ref_sign(int a, int k) {
 
 struct RefTables {
   int dim, nen, nq;
+  double w[8];            // quadrature weight of point q
   double N[8][8];         // [q][a]
   double dN[8][8][3];     // [q][a][k] = dN_a/dxi_k at Gauss point q
 };
 
+// P1 simplex on the unit reference simplex: N_0 = 1 - sum xi, N_a = xi_a;
+// one point at the centroid with the reference volume 1/dim! as weight.
+RefTables make_simplex_tables(int dim) {
+  RefTables t{};
+  t.dim = dim;
+  t.nen = dim + 1;
+  t.nq = 1;
+  t.w[0] = dim == 2 ? 0.5 : 1.0 / 6.0;
+  for (int a = 0; a < t.nen; ++a) {
+    t.N[0][a] = 1.0 / (dim + 1);
+    for (int k = 0; k < dim; ++k) t.dN[0][a][k] = a == 0 ? -1.0 : (a - 1 == k ? 1.0 : 0.0);
+  }
+  return t;
+}
+
 RefTables make_tables(int dim) {
-  RefTables t;
+  RefTables t{};
   t.dim = dim;
   t.nen = 1 << dim;
   t.nq = 1 << dim;
   const double gp = 1.0 / std::sqrt(3.0);
   for (int q = 0; q < t.nq; ++q) {
+    t.w[q] = 1.0;
     double xi[3] = {0, 0, 0};
     // Gauss point q takes the sign pattern of element node q
     for (int k = 0; k < dim; ++k) xi[k] = gp * ref_sign(q, k);
@@ -98,7 +117,8 @@ double solve_small(int dim, double J[3][3], double B[3][8], int nen) {
 int assemble_fe(const mono_mesh_desc* d, HostCSR& K, std::string& err) {
   const int dim = d->dim;
   const int64_t n = d->n_nodes, ne = d->n_elems;
-  const int nen = 1 << dim;
+  const bool simplex = dim >= 2 && d->etype == dim + 1;
+  const int nen = simplex ? dim + 1 : 1 << dim;
   if (!d->xyz || !d->conn || !d->D_elem) {
     err = "mesh arrays must not be NULL";
     return MONO_EINVAL;
@@ -146,7 +166,7 @@ int assemble_fe(const mono_mesh_desc* d, HostCSR& K, std::string& err) {
   K.val.assign(K.col.size(), 0.0);
   K.mass.assign(n, 0.0);
 
-  const RefTables t = make_tables(dim);
+  const RefTables t = simplex ? make_simplex_tables(dim) : make_tables(dim);
   for (int64_t e = 0; e < ne; ++e) {
     const int32_t* en = d->conn + e * nen;
     const double* D = d->D_elem + e * dim * dim;
@@ -169,11 +189,12 @@ int assemble_fe(const mono_mesh_desc* d, HostCSR& K, std::string& err) {
       double B[3][8];
       for (int k = 0; k < dim; ++k)
         for (int a = 0; a < nen; ++a) B[k][a] = t.dN[q][a][k];
-      const double det = solve_small(dim, J, B, nen);   // B <- J^-1 dN (physical gradients)
-      if (!(det > 0.0)) {
+      const double jac = solve_small(dim, J, B, nen);   // B <- J^-1 dN (physical gradients)
+      if (!(jac > 0.0)) {
         err = "element " + std::to_string(e) + " has a non-positive Jacobian";
         return MONO_EINVAL;
       }
+      const double det = jac * t.w[q];
       // DB = D * B
       double DB[3][8];
       for (int k = 0; k < dim; ++k)

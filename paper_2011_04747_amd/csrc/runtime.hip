@@ -866,7 +866,8 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
   if (!d || !out) return fail(MONO_EINVAL, "NULL argument");
   *out = nullptr;
   if (d->dim < 1 || d->dim > 3) return fail(MONO_EINVAL, "dim must be 1, 2 or 3");
-  if (d->etype != (1 << d->dim)) return fail(MONO_EINVAL, "etype does not match dim");
+  if (d->etype != (1 << d->dim) && !(d->dim >= 2 && d->etype == d->dim + 1))
+    return fail(MONO_EINVAL, "etype does not match dim");
   if (d->n_nodes < 1 || d->n_nodes > (int64_t)INT32_MAX - 1024)
     return fail(MONO_EINVAL, "n_nodes out of range");
   if (d->n_elems < 0) return fail(MONO_EINVAL, "n_elems must be >= 0");
