@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--steps", type=int, default=320)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--layout", default="auto", choices=["auto", "ell", "stencil"])
-    ap.add_argument("--workload", default="slab", choices=["slab", "batched"])
+    ap.add_argument("--workload", default="slab", choices=["slab", "batched", "tets"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--cpu-steps-1t", type=int, default=3)
@@ -195,6 +195,11 @@ def main():
     if args.workload == "slab":
         w = W.slab_ischemic(precision="f32")
         wl_name = ("slab_tp06_3d_ischemic 201x201x51 (2,060,451 nodes), Q1 hexes, dx=0.01 cm, "
+                   "dt=0.1 ms, S1+S2")
+    elif args.workload == "tets":
+        w = W.slab_ischemic_tets(precision="f32")
+        wl_name = ("slab_tp06_3d_ischemic_tets 201x201x51 (2,060,451 nodes, "
+                   f"{w.mesh.n_elems:,} linear tetrahedra), RCM node order, dx=0.01 cm, "
                    "dt=0.1 ms, S1+S2")
     else:
         w = W.batched_sheets(precision="f32")

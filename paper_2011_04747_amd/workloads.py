@@ -194,11 +194,12 @@ def renumber(xyz: np.ndarray, conn: np.ndarray, order: str, seed: int = 0):
     if order == "rcm":
         import scipy.sparse as sp
         from scipy.sparse.csgraph import reverse_cuthill_mckee
-        c = new_of_old[conn]
+        c = new_of_old[conn].astype(np.int32)
         k = c.shape[1]
-        rows = np.repeat(c, k, axis=1).reshape(-1)
-        cols = np.tile(c, (1, k)).reshape(-1)
-        g = sp.csr_matrix((np.ones(rows.size, np.int8), (rows, cols)), shape=(n, n))
+        pairs = [(a, b) for a in range(k) for b in range(k) if a != b]
+        rows = np.concatenate([c[:, a] for a, _ in pairs])
+        cols = np.concatenate([c[:, b] for _, b in pairs])
+        g = sp.coo_matrix((np.ones(rows.size, np.int8), (rows, cols)), shape=(n, n)).tocsr()
         rcm = np.asarray(reverse_cuthill_mckee(g, symmetric_mode=True))   # old(shuffled) at new
         pos = np.empty(n, np.int64)
         pos[rcm] = np.arange(n)
