@@ -122,7 +122,10 @@ __device__ __forceinline__ T stimulus_sum(const DiffArgs<T>& a, uint32_t active,
   return r;
 }
 
-template <typename T, bool BATCHED, int BLOCK>
+// WC > 0: the ELL width as a compile-time constant (the slot loop unrolls,
+// so every slot's column and value loads, then every gather, are in flight
+// together); WC = 0 reads it at run time.  Same sums in the same order.
+template <typename T, bool BATCHED, int BLOCK, int WC>
 __global__ __launch_bounds__(BLOCK) void k_diff_ell(DiffArgs<T> a) {
   const int64_t nb = (a.n + BLOCK - 1) / BLOCK;
   const int64_t i = row_block(nb, a.xcd) * BLOCK + threadIdx.x;
@@ -135,10 +138,23 @@ __global__ __launch_bounds__(BLOCK) void k_diff_ell(DiffArgs<T> a) {
   }
   const double dt_ad = a.dt_ad[q];
   T acc = T(0);
-  for (int s = 0; s < a.W; ++s) {
-    const int64_t k = (int64_t)s * a.Np + i;
-    const int32_t j = a.col[k];
-    acc += a.val[k] * (a.Vin[j] - vi);
+  if constexpr (WC > 0) {
+    int32_t j[WC];
+    T v[WC];
+#pragma unroll
+    for (int s = 0; s < WC; ++s) {
+      const int64_t k = (int64_t)s * a.Np + i;
+      j[s] = a.col[k];
+      v[s] = a.val[k];
+    }
+#pragma unroll
+    for (int s = 0; s < WC; ++s) acc += v[s] * (a.Vin[j[s]] - vi);
+  } else {
+    for (int s = 0; s < a.W; ++s) {
+      const int64_t k = (int64_t)s * a.Np + i;
+      const int32_t j = a.col[k];
+      acc += a.val[k] * (a.Vin[j] - vi);
+    }
   }
   const double tau = substep_time(a.clk, a.half, a.m, dt_ad);
   acc += stimulus_rate(a, i, tau);
@@ -462,7 +478,15 @@ static void launch_stencil_p(const DiffArgs<T>& a, const LaunchCfg& c, hipStream
 template <typename T, bool BATCHED, int BLOCK>
 static void launch_ell_k(const DiffArgs<T>& a, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + BLOCK - 1) / BLOCK));
-  launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK>, grid, dim3(BLOCK), s, a);
+  // widths of the element types on structured and split grids
+  switch (a.W) {
+    case 2: return launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK, 2>, grid, dim3(BLOCK), s, a);
+    case 6: return launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK, 6>, grid, dim3(BLOCK), s, a);
+    case 8: return launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK, 8>, grid, dim3(BLOCK), s, a);
+    case 14: return launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK, 14>, grid, dim3(BLOCK), s, a);
+    case 26: return launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK, 26>, grid, dim3(BLOCK), s, a);
+    default: return launch_step_kernel(k_diff_ell<T, BATCHED, BLOCK, 0>, grid, dim3(BLOCK), s, a);
+  }
 }
 template <typename T, bool BATCHED>
 static void launch_ell_b(const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s) {
