@@ -28,6 +28,9 @@ METRIC = ("node-updates/s (ionic+diffusion) at stated accuracy vs FP64 plain; "
           "adjoint/fwd ratio")
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# the same FP32 vector units without packed (two-wide) instructions, which
+# the build disables: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PLAIN_VALU_PEAK_TFLOPS = 78.6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -330,6 +333,9 @@ def main():
     dominant = react_roof if react_total >= diff_total else diff_roof
     roofline = {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
     roofline["kernel"] = dominant["kernel"]
+    if dominant is react_roof:
+        roofline["peak_plain_valu"] = FP32_PLAIN_VALU_PEAK_TFLOPS
+        roofline["frac_plain_valu"] = react_roof["achieved"] / FP32_PLAIN_VALU_PEAK_TFLOPS
 
     # accuracy against the FP64 path (itself checked against the FP64 oracle)
     accuracy = None
