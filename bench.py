@@ -308,8 +308,12 @@ def main():
     if info["n_instances"] > 1:
         row_bytes += 4               # instance id of the row
     diff_bytes = n * row_bytes
-    from oracle.oracle import model_init  # rest state for the op count
-    ops = mono.model_flops(W.MODEL_TP06, model_init(W.MODEL_TP06), W.TP06_PARAM_DEFAULT)
+    # op count of one substep at the library's own initial (resting) state,
+    # read from a 4-node simulation
+    tiny = mono.Sim.from_workload(W.sheet_tp06(n=2, t_end=0.1), "f64")
+    rest = [float(tiny.get(mono.FIELD_STATE0 + j)[0]) for j in range(tiny.info()["n_states"])]
+    tiny.close()
+    ops = mono.model_flops(W.MODEL_TP06, rest, W.TP06_PARAM_DEFAULT)
     f_model = ops["add"] + ops["mul"] + ops["div"] + ops["exp"] + ops["log"] + ops["sqrt"]
     react_flops = (ksum / kt_steps) * f_model
     diff_total = 2 * L * d_us * 1e-3
