@@ -46,16 +46,6 @@ __global__ __launch_bounds__(256) void k_sensor_sample(const T* V, const int32_t
   if (q < ns) out[q] = (double)V[sens[q]];
 }
 
-// lam_V[sensor_q] += 2 (V_entry[sensor_q] - target_q)   (sensors are distinct)
-template <typename T>
-__global__ __launch_bounds__(256) void k_sensor_inject(T* lamV, const T* V, SensorArgs a) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  const int64_t step = *a.clk.base + a.clk.g;
-  if (q >= a.ns || step >= a.target_steps) return;
-  const int32_t i = a.sens[q];
-  lamV[i] = (T)((double)lamV[i] + 2.0 * ((double)V[i] - a.target[step * a.ns + q]));
-}
-
 // --- adjoint diffusion substep ------------------------------------------------
 template <typename T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_adj_diff_stencil(AdjDiffArgs<T> a) {
@@ -321,6 +311,14 @@ __global__ __launch_bounds__(256) void k_adj_ionic(AdjIonArgs<T> a) {
     T gp[M::P];
     for (int b = 0; b < M::P; ++b) gp[b] = T(0);
     for (int q = k - 1; q >= 0; --q) A::vjp(ys[q], p, h, lam, gp);
+    // loss term of a sensor node: lam_V += 2 (V_entry - target)
+    if (a.sens_of) {
+      const int32_t sq = a.sens_of[i];
+      const int64_t step = *a.clk.base + a.clk.g;
+      if (sq >= 0 && step < a.target_steps)
+        lam[0] = (T)((double)lam[0] +
+                     2.0 * ((double)ys[0][0] - a.target[step * a.ns + sq]));
+    }
     a.lamV[i] = lam[0];
     for (int s = 1; s < M::S; ++s) a.lam[(int64_t)s * a.Np + i] = lam[s];
     // derivative with respect to a common multiplier of each parameter row
@@ -360,12 +358,6 @@ void launch_sensor_loss(const T* V, const SensorArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_sensor_loss<T>), dim3(1), dim3(256), 0, s, V, a);
 }
 template <typename T>
-void launch_sensor_inject(T* lamV, const T* V, const SensorArgs& a, hipStream_t s) {
-  if (a.ns <= 0) return;
-  hipLaunchKernelGGL((k_sensor_inject<T>), dim3((a.ns + 255) / 256), dim3(256), 0, s, lamV, V, a);
-}
-
-template <typename T>
 void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, hipStream_t s) {
   if (ns <= 0) return;
   hipLaunchKernelGGL((k_sensor_sample<T>), dim3((ns + 255) / 256), dim3(256), 0, s, V, sens, ns,
@@ -380,8 +372,4 @@ template void launch_adj_ionic<float>(int, const AdjIonArgs<float>&, hipStream_t
 template void launch_adj_ionic<double>(int, const AdjIonArgs<double>&, hipStream_t);
 template void launch_sensor_loss<float>(const float*, const SensorArgs&, hipStream_t);
 template void launch_sensor_loss<double>(const double*, const SensorArgs&, hipStream_t);
-template void launch_sensor_inject<float>(float*, const float*, const SensorArgs&, hipStream_t);
-template void launch_sensor_inject<double>(double*, const double*, const SensorArgs&,
-                                           hipStream_t);
-
 }  // namespace mono

@@ -260,6 +260,13 @@ struct AdjIonArgs {
   double dt;
   double* gpart;             // per workgroup kMaxParams FP64 partial sums
   int sort;                  // take each workgroup's nodes in order of k
+  // loss gradient at reaction entry, added to the adjoint of V where a node
+  // is a sensor: sens_of[i] = its sensor index or -1 (nullptr: no sensors)
+  const int32_t* sens_of;
+  const double* target;      // target_steps x ns
+  int ns;
+  int64_t target_steps;
+  StepClock clk;
 };
 template <typename T>
 void launch_adj_diffusion(int layout, const AdjDiffArgs<T>& a, hipStream_t s);
@@ -280,8 +287,6 @@ template <typename T>
 void launch_sensor_loss(const T* V, const SensorArgs& a, hipStream_t s);
 template <typename T>
 void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, hipStream_t s);
-template <typename T>
-void launch_sensor_inject(T* lamV, const T* V, const SensorArgs& a, hipStream_t s);
 
 template <typename T>
 void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s);

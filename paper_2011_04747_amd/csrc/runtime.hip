@@ -161,6 +161,7 @@ struct mono_sim {
   int sigma_uniform = 0;           // every node has sigma_value (in precision T)
   double sigma_value = 1.0;
   int32_t* d_sens = nullptr;
+  int32_t* d_sens_of = nullptr;    // per node: sensor index or -1
   int ns = 0;
   double* d_target = nullptr;      // target_steps x ns
   int64_t target_steps = 0;
@@ -777,8 +778,9 @@ mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
 // potential straight into the tape's first slot) and set the clock, then one
 // graph recomputes the segment, taping what the reverse needs, and runs the
 // reverse steps: adjoint diffusion substeps (the V adjoint ping-pongs between
-// two rows, an even number of times per step), adjoint reaction, sensor
-// injection.  Every segment of ckpt_every steps replays the same graph.
+// two rows, an even number of times per step), adjoint reaction with the
+// sensors' loss gradient added in the same kernel.  Every segment of
+// ckpt_every steps replays the same graph.
 template <typename T>
 mono_status backward_t(mono_sim* s) {
   const int64_t C = s->ckpt_every, N = s->tape_steps;
@@ -818,8 +820,17 @@ mono_status backward_t(mono_sim* s) {
         ai.dt = s->dt;
         ai.gpart = s->d_gpart;
         ai.sort = s->lc.react_sort;
+        if (s->ns > 0) {
+          // the loss gradient at reaction entry goes in with the reaction's
+          // adjoint (one launch instead of two)
+          const SensorArgs sa = sensor_args(s, t);
+          ai.sens_of = s->d_sens_of;
+          ai.target = sa.target;
+          ai.ns = sa.ns;
+          ai.target_steps = sa.target_steps;
+          ai.clk = sa.clk;
+        }
         launch_adj_ionic<T>(s->model, ai, s->stream);
-        if (s->ns > 0) launch_sensor_inject<T>(lamV, entry, sensor_args(s, t), s->stream);
         for (int m = L - 1; m >= 0; --m) {
           launch_adj_diffusion<T>(
               s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)m * Np, m), s->stream);
@@ -1102,6 +1113,7 @@ void mono_destroy(mono_sim* s) {
   free_tape(s);
   dfree(s->d_sigma);
   dfree(s->d_sens);
+  dfree(s->d_sens_of);
   dfree(s->d_target);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -1526,14 +1538,20 @@ mono_status mono_set_sensors(mono_sim* s, int32_t n, const int32_t* nodes, const
   if (std::adjacent_find(u.begin(), u.end()) != u.end())
     return fail(MONO_EINVAL, "sensor nodes must be distinct");
   HIP_TRY(hipStreamSynchronize(s->stream));
+  drop_graph(s);
   dfree(s->d_sens);
+  dfree(s->d_sens_of);
   dfree(s->d_target);
   s->ns = n;
   s->target_steps = n_steps;
   if (n > 0) {
-    if (dalloc(&s->d_sens, n) || dalloc(&s->d_target, (size_t)n * std::max<int64_t>(n_steps, 1)))
+    if (dalloc(&s->d_sens, n) || dalloc(&s->d_target, (size_t)n * std::max<int64_t>(n_steps, 1)) ||
+        dalloc(&s->d_sens_of, s->Np))
       return fail(MONO_ENOMEM, "device allocation failed");
     HIP_TRY(hipMemcpy(s->d_sens, v.data(), n * 4, hipMemcpyHostToDevice));
+    std::vector<int32_t> of(s->Np, -1);
+    for (int32_t q = 0; q < n; ++q) of[v[q]] = q;
+    HIP_TRY(hipMemcpy(s->d_sens_of, of.data(), s->Np * 4, hipMemcpyHostToDevice));
     if (n_steps > 0)
       HIP_TRY(hipMemcpy(s->d_target, target, (size_t)n * n_steps * 8, hipMemcpyHostToDevice));
   }
