@@ -50,7 +50,7 @@ typedef enum {
   MONO_ENOMEM = -2,       /* device or host allocation failed               */
   MONO_EDEVICE = -3,      /* a HIP runtime call failed                      */
   MONO_ESTATE = -4,       /* call not valid in the simulation's state       */
-  MONO_EUNSUPPORTED = -5, /* valid request this build does not implement    */
+  MONO_EUNSUPPORTED = -5, /* valid request the library does not implement   */
   MONO_ENONFINITE = -6    /* a NaN/Inf potential appeared during stepping   */
 } mono_status;
 

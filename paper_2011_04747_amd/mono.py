@@ -112,8 +112,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
-                              "or python paper_2011_04747_amd/build.py")
+            raise ImportError(f"{LIB_PATH} is not built; run "
+                              "python paper_2011_04747_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
