@@ -46,7 +46,8 @@ def _traffic(kernel, workload, launch):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (copy-calibrated), or None when absent, taken on another workload
     or launch shape, or when the kernel's sources have changed since."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    suffix = "" if workload == "slab" else f"_{workload}"
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}{suffix}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
