@@ -200,7 +200,10 @@ __global__ __launch_bounds__(BLOCK) void k_diff_stencil(DiffArgs<T> a) {
       const int64_t jf = i + o;
       const int64_t jb = i - o;
       const int64_t jbc = jb >= first[r] ? jb : first[r];
-      const T wb = (jb >= first[r]) ? a.e[(int64_t)p * a.Np + jbc] : T(0);
+      // loaded unconditionally (jbc is always a row of this instance), so
+      // that no branch holds the slots' loads apart
+      const T wbl = a.e[(int64_t)p * a.Np + jbc];
+      const T wb = (jb >= first[r]) ? wbl : T(0);
       const T vf = a.Vin[jf <= last ? jf : last];
       const T vb = a.Vin[jbc];
       acc[r] += wf[r] * (vf - vi[r]);
