@@ -79,8 +79,18 @@ typedef enum {
  *  TP06_EPI ten Tusscher & Panfilov (2006) epicardial, V in mV,
  *           params {Ko [mM], gNa, gCaL, gKr, gKs, gK1 scalings}, 19 states
  *           {V, K_i, Na_i, Ca_i, Ca_ss, Ca_SR, Rbar, m, h, j, xr1, xr2, xs,
- *            r, s, d, f, f2, fCass}                                         */
-typedef enum { MONO_MODEL_LINEAR = 0, MONO_MODEL_MS = 1, MONO_MODEL_TP06_EPI = 2 } mono_model;
+ *            r, s, d, f, f2, fCass}
+ *  TP06_TYPES the same with a transmural cell type per node in a 7th
+ *           parameter row: 0 epicardial, 1 endocardial (G_to = 0.073, the
+ *           endocardial s gate), 2 M cell (G_Ks = 0.098); heterogeneous
+ *           tissue in one simulation.  No adjoint (mono_forward_taped
+ *           returns EUNSUPPORTED).                                          */
+typedef enum {
+  MONO_MODEL_LINEAR = 0,
+  MONO_MODEL_MS = 1,
+  MONO_MODEL_TP06_EPI = 2,
+  MONO_MODEL_TP06_TYPES = 3
+} mono_model;
 
 /* DAETI: adaptive k and l (Sec. 2).  OSTAR: l = 1 (adaptive reaction only).
  * OST: k = l = 1 (the caller picks dt).  The comparison methods of Sec. 3. */
@@ -159,7 +169,9 @@ mono_status mono_create_mesh(const mono_mesh_desc *desc, mono_sim **out);
  * model's defaults (uniform rows are stored once).  init_state: n_states *
  * n_nodes SoA or NULL for the model's published initial values.  dt0 [ms] is
  * the largest stable cell step: k_max = max(1, floor(dt/dt0)) (Sec. 2).
- * Resets time, V_prev (= V) and activation times. */
+ * Resets time, V_prev (= V) and activation times.  Errors: EINVAL for an
+ * unknown model, a wrong n_params, dt0 <= 0 or a TP06_TYPES cell type other
+ * than 0, 1 or 2; ENOMEM; EDEVICE. */
 mono_status mono_set_cell_model(mono_sim *sim, int32_t model, int32_t n_params,
                                 const double *params, const double *init_state, double dt0);
 

@@ -268,10 +268,20 @@ template <int N> DualN<N> sqrt(const DualN<N>& a) {
 // ---------------------------------------------------------------------------
 // cell models
 // ---------------------------------------------------------------------------
-enum { M_LINEAR = 0, M_MS = 1, M_TP06 = 2 };
+// M_TP06T is TP06 with the transmural cell type as a seventh parameter
+// (0 epicardial, 1 endocardial, 2 mid-myocardial); M_TP06 is the epicardial
+// cell alone.
+enum { M_LINEAR = 0, M_MS = 1, M_TP06 = 2, M_TP06T = 3 };
 
+bool is_tp06(int m) { return m == M_TP06 || m == M_TP06T; }
+// cell type stored as a parameter value (checked to be 0, 1 or 2 on input)
+int cell_type(double v) { return v == 1.0 ? 1 : (v == 2.0 ? 2 : 0); }
+template <int N>
+int cell_type(const DualN<N>& v) { return cell_type(v.v); }
 int model_nstates(int m) { return m == M_LINEAR ? 1 : (m == M_MS ? 2 : 19); }
-int model_nparams(int m) { return m == M_LINEAR ? 2 : (m == M_MS ? 5 : 6); }
+int model_nparams(int m) {
+  return m == M_LINEAR ? 2 : (m == M_MS ? 5 : (m == M_TP06 ? 6 : 7));
+}
 
 // Rates of one cell.  For every state y the model reports either a forward
 // Euler slope (is_gate = 0: rate = dy/dt) or Rush-Larsen data (is_gate = 1:
@@ -356,7 +366,7 @@ struct TPCurrents {
 };
 
 template <typename Num>
-void tp06_currents(const Num* y, const Num* p, TPCurrents<Num>& c) {
+void tp06_currents(const Num* y, const Num* p, TPCurrents<Num>& c, int type = 0) {
   using std::exp;
   using std::expm1;
   using std::log;
@@ -381,9 +391,14 @@ void tp06_currents(const Num* y, const Num* p, TPCurrents<Num>& c) {
   const Num xK1 = aK1 / (aK1 + bK1);
   c.IK1 = p[5] * GK1 * sqrt(Ko / 5.4) * xK1 * (V - EK);
 
-  c.Ito = Gto * r * s * (V - EK);
+  // ten Tusscher-Panfilov 2006 cell types: endocardial cells carry a smaller
+  // transient outward current, mid-myocardial cells a smaller slow delayed
+  // rectifier; everything else is shared.
+  const double gto = type == 1 ? 0.073 : Gto;
+  const double gks = type == 2 ? 0.098 : GKs;
+  c.Ito = gto * r * s * (V - EK);
   c.IKr = p[3] * GKr * sqrt(Ko / 5.4) * xr1 * xr2 * (V - EK);
-  c.IKs = p[4] * GKs * xs * xs * (V - EKs);
+  c.IKs = p[4] * gks * xs * xs * (V - EKs);
 
   // L-type current; x/(e^x - 1) -> 1 at x = 0 (removable singularity at V=15)
   const Num x = 2.0 * (V - 15.0) * F / (R * T);
@@ -416,12 +431,12 @@ void tp06_currents(const Num* y, const Num* p, TPCurrents<Num>& c) {
 }
 
 template <typename Num>
-void rates_tp06(const Num* y, const Num* p, Rates<Num>& r) {
+void rates_tp06(const Num* y, const Num* p, Rates<Num>& r, int type = 0) {
   using std::exp;
   using std::sqrt;
   using namespace tp;
   TPCurrents<Num> c;
-  tp06_currents(y, p, c);
+  tp06_currents(y, p, c, type);
   const Num V = y[0], Cass = y[4], CaSR = y[5], Rb = y[6];
 
   for (int i = 0; i < 7; ++i) r.is_gate[i] = 0;
@@ -487,13 +502,18 @@ void rates_tp06(const Num* y, const Num* p, Rates<Num>& r) {
     Num b = 1.0 / (1.0 + exp((V - 35.0) / 15.0));
     r.tau[12] = a * b + 80.0;
   }
-  // r, s (epicardial)
+  // r, s (the s gate of endocardial cells inactivates more slowly)
   {
     r.inf[13] = 1.0 / (1.0 + exp((20.0 - V) / 6.0));
     r.tau[13] = 9.5 * exp(-(V + 40.0) * (V + 40.0) / 1800.0) + 0.8;
-    r.inf[14] = 1.0 / (1.0 + exp((V + 20.0) / 5.0));
-    r.tau[14] = 85.0 * exp(-(V + 45.0) * (V + 45.0) / 320.0) +
-                5.0 / (1.0 + exp((V - 20.0) / 5.0)) + 3.0;
+    if (type == 1) {
+      r.inf[14] = 1.0 / (1.0 + exp((V + 28.0) / 5.0));
+      r.tau[14] = 1000.0 * exp(-(V + 67.0) * (V + 67.0) / 1000.0) + 8.0;
+    } else {
+      r.inf[14] = 1.0 / (1.0 + exp((V + 20.0) / 5.0));
+      r.tau[14] = 85.0 * exp(-(V + 45.0) * (V + 45.0) / 320.0) +
+                  5.0 / (1.0 + exp((V - 20.0) / 5.0)) + 3.0;
+    }
   }
   // d, f, f2, fCass
   {
@@ -538,8 +558,10 @@ void model_rates(int model, const Num* y, const Num* p, Rates<Num>& r) {
     rates_linear(y, p, r);
   else if (model == M_MS)
     rates_ms(y, p, r);
-  else
+  else if (model == M_TP06)
     rates_tp06(y, p, r);
+  else
+    rates_tp06(y, p, r, cell_type(p[6]));
 }
 
 // One substep of length h from y (all rates taken at the substep start):
@@ -991,7 +1013,7 @@ int orc_get_matrix(void* h, int64_t* rowptr, int32_t* col, double* val, double* 
 int orc_set_model(void* h, int model, int n_params, const double* params,
                   const double* init_state, double dt0, double lat_thr) {
   Sim* s = (Sim*)h;
-  if (model < 0 || model > 2) return fail("unknown model");
+  if (model < 0 || model > 3) return fail("unknown model");
   if (!(dt0 > 0.0)) return fail("dt0 must be positive");
   s->model = model;
   s->S = model_nstates(model);
@@ -1006,18 +1028,23 @@ int orc_set_model(void* h, int model, int n_params, const double* params,
     for (int a = 0; a < s->S; ++a) {
       double v = 0.0;
       if (model == M_MS) v = (a == 0) ? 0.0 : 1.0;
-      if (model == M_TP06) v = tp::INIT[a];
+      if (is_tp06(model)) v = tp::INIT[a];
       for (int64_t i = 0; i < n; ++i) s->state[a * n + i] = v;
     }
   }
   if (params) {
+    if (model == M_TP06T)
+      for (int64_t i = 0; i < n; ++i) {
+        const double c = params[6 * n + i];
+        if (c != 0.0 && c != 1.0 && c != 2.0) return fail("cell type must be 0, 1 or 2");
+      }
     std::memcpy(s->params.data(), params, sizeof(double) * s->P * n);
   } else {
     const double ms[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
-    const double tp6[6] = {5.4, 1, 1, 1, 1, 1};
+    const double tp6[7] = {5.4, 1, 1, 1, 1, 1, 0};
     const double lin[2] = {0.0, 0.0};
     for (int a = 0; a < s->P; ++a) {
-      double v = model == M_MS ? ms[a] : (model == M_TP06 ? tp6[a] : lin[a]);
+      double v = model == M_MS ? ms[a] : (is_tp06(model) ? tp6[a] : lin[a]);
       for (int64_t i = 0; i < n; ++i) s->params[a * n + i] = v;
     }
   }
@@ -1164,6 +1191,7 @@ int orc_set_target(void* h, int32_t n, const int32_t* nodes, const double* targe
 int orc_forward_taped(void* h, int64_t n_steps, double dt, double* loss) {
   Sim* s = (Sim*)h;
   if (s->model < 0) return fail("no cell model");
+  if (s->model == M_TP06T) return fail("adjoint of the cell-type model not provided");
   if (s->dt != dt && prepare(s, dt) != 0) return -1;
   int lmax = 0;
   for (int x : s->l) lmax = std::max(lmax, x);
@@ -1287,7 +1315,7 @@ int orc_model_nparams(int model) { return model_nparams(model); }
 int orc_model_init(int model, double* y) {
   const int S = model_nstates(model);
   for (int a = 0; a < S; ++a)
-    y[a] = model == M_TP06 ? tp::INIT[a] : (model == M_MS ? (a == 0 ? 0.0 : 1.0) : 0.0);
+    y[a] = is_tp06(model) ? tp::INIT[a] : (model == M_MS ? (a == 0 ? 0.0 : 1.0) : 0.0);
   return 0;
 }
 

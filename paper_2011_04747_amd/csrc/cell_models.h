@@ -190,8 +190,12 @@ struct TP06Fluxes {
   T Irel, Iup, Ileak, Ixfer;
 };
 
+// gto, gks: maximal I_to and I_Ks conductances (the epicardial values unless
+// a cell type says otherwise)
 template <typename T>
-__host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP06Fluxes<T>& c) {
+__host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP06Fluxes<T>& c,
+                                                     T gto = T(tp06::kGto),
+                                                     T gks = T(tp06::kGKs)) {
   using namespace tp06;
   const T V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5], Rb = y[6];
   const T Ko = p[0];
@@ -217,9 +221,9 @@ __host__ __device__ __forceinline__ void tp06_fluxes(const T* y, const T* p, TP0
                  xexp2(lin(vk, 0.1 * kLog2e, -kLog2e))) *
                 sig2(vk * T(-0.5 * kLog2e));
   const T IK1 = p[5] * T(kGK1) * sqKo * xrcp(T(1) + T(10) * bK1 * (T(1) + ea)) * vk;
-  const T Ito = T(kGto) * y[13] * y[14] * vk;
+  const T Ito = gto * y[13] * y[14] * vk;
   const T IKr = p[3] * T(kGKr) * sqKo * y[10] * y[11] * vk;
-  const T IKs = p[4] * T(kGKs) * y[12] * y[12] * (V - EKs);
+  const T IKs = p[4] * gks * y[12] * y[12] * (V - EKs);
   const T IpK = T(kGpK) * vk * sig2(lin(V, -kLog2e / 5.98, 25.0 * kLog2e / 5.98));
 
   // L-type Ca current with the removable singularity at V = 15 mV handled
@@ -279,8 +283,11 @@ __host__ __device__ __forceinline__ T sig_e(T ez) {
 // reciprocals of products of logistic factors are formed directly as
 // products of (1 + e^z) (no reciprocal of a reciprocal).  Same functions as
 // the published forms; only the rounding differs.
+// endo: the endocardial s gate (steady state half-activation at -28 mV, slow
+// recovery) instead of the epicardial / M-cell one
 template <typename T>
-__host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) {
+__host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate,
+                                                          bool endo = false) {
   constexpr double L = kLog2e;
   const T P5 = xexp2(V * T(0.2 * L));         // e^{V/5}
   const T N10 = xexp2(V * T(-0.1 * L));       // e^{-V/10}
@@ -335,9 +342,15 @@ __host__ __device__ __forceinline__ void tp06_gate_params(T V, T* inf, T* rate) 
     const T vr = V + T(40), vs = V + T(45);
     inf[6] = sig_e(T(28.03162489452614) * N6);                        // e^{20/6} e^{-V/6}
     rate[6] = xrcp(T(9.5) * xexp2(vr * vr * T(-L / 1800.0)) + T(0.8));
-    inf[7] = sig_e(T(54.598150033144236) * P5);                       // e^4 e^{V/5}
-    rate[7] = xrcp(T(85) * xexp2(vs * vs * T(-L / 320.0)) +
-                   T(5) * sig_e(T(0.01831563888873418) * P5) + T(3));  // e^{-4} e^{V/5}
+    if (endo) {
+      const T ve = V + T(67);
+      inf[7] = sig_e(T(270.42640742615254) * P5);                      // e^5.6 e^{V/5}
+      rate[7] = xrcp(T(1000) * xexp2(ve * ve * T(-L / 1000.0)) + T(8));
+    } else {
+      inf[7] = sig_e(T(54.598150033144236) * P5);                     // e^4 e^{V/5}
+      rate[7] = xrcp(T(85) * xexp2(vs * vs * T(-L / 320.0)) +
+                     T(5) * sig_e(T(0.01831563888873418) * P5) + T(3));  // e^{-4} e^{V/5}
+    }
   }
   {
     const T ad = T(1.4) * sig2(lin(V, -L / 13.0, -35.0 * L / 13.0)) + T(0.25);
@@ -367,6 +380,48 @@ __host__ __device__ __forceinline__ void tp06_fcass_params(T Cass, T& inf, T& ra
   rate = xrcp(T(80) * r1q + T(2));
 }
 
+// One TP06 substep with the cell type's I_to / I_Ks conductances and s gate.
+template <typename T>
+__host__ __device__ __forceinline__ void tp06_substep(T* y, const T* p, T h, bool clamp, T gto,
+                                                      T gks, bool endo) {
+  using namespace tp06;
+  TP06Fluxes<T> c;
+  tp06_fluxes(y, p, c, gto, gks);
+  const T V = y[0];
+  const T cc = T(kCurToConc);
+  // forward Euler: V, Ki, Nai, Rbar; buffered totals of Ca_i, Ca_ss, Ca_SR
+  const T dKi = -(c.IK - T(2) * c.INaK) * cc;
+  const T dNai = -(c.INa + c.IbNa + T(3) * c.INaK + T(3) * c.INaCa) * cc;
+  const T dCai = -(c.IbCa + c.IpCa - T(2) * c.INaCa) * T(0.5) * cc +
+                 T(kVsr / kVc) * (c.Ileak - c.Iup) + c.Ixfer;
+  const T dCass = -c.ICaL * T(kCap / (2.0 * kVss * kF)) + T(kVsr / kVss) * c.Irel -
+                  T(kVc / kVss) * c.Ixfer;
+  const T dCaSR = c.Iup - c.Ileak - c.Irel;
+  const T kcasr = tp06_kcasr(y[5]);
+  const T dRb = -T(kK2p) * kcasr * y[4] * y[6] + T(kK4) * (T(1) - y[6]);
+
+  // gates from the substep-start V (and Ca_ss for fCass)
+  T inf[12], rate[12];
+  tp06_gate_params(V, inf, rate, endo);
+  tp06_fcass_params(y[4], inf[11], rate[11]);
+  T g[12];
+  const T hl = h * T(-kLog2e);
+  for (int a = 0; a < 12; ++a) g[a] = rl_rate2(y[7 + a], inf[a], rate[a], hl);
+
+  // commit
+  y[3] = free_from_total(total_from_free(y[3], T(kBufc), T(kKbufc)) + h * dCai, T(kBufc),
+                         T(kKbufc));
+  y[4] = free_from_total(total_from_free(y[4], T(kBufss), T(kKbufss)) + h * dCass, T(kBufss),
+                         T(kKbufss));
+  y[5] = free_from_total(total_from_free(y[5], T(kBufsr), T(kKbufsr)) + h * dCaSR, T(kBufsr),
+                         T(kKbufsr));
+  y[1] = y[1] + h * dKi;
+  y[2] = y[2] + h * dNai;
+  y[6] = y[6] + h * dRb;
+  for (int a = 0; a < 12; ++a) y[7 + a] = g[a];
+  if (!clamp) y[0] = V - h * c.Iion;
+}
+
 struct TP06Model {
   static constexpr int S = 19, P = 6;
   template <typename T>
@@ -377,42 +432,37 @@ struct TP06Model {
   }
   template <typename T>
   __host__ __device__ static void substep(T* y, const T* p, T h, bool clamp) {
-    using namespace tp06;
+    tp06_substep(y, p, h, clamp, T(tp06::kGto), T(tp06::kGKs), false);
+  }
+};
+
+// TP06 with a transmural cell type per node in parameter row 6 (0
+// epicardial, 1 endocardial, 2 M cell; ten Tusscher & Panfilov 2006): the
+// endocardial cell has G_to = 0.073 and the endocardial s gate, the M cell
+// G_Ks = 0.098; everything else is the epicardial model.
+struct TP06TypesModel {
+  static constexpr int S = 19, P = 7;
+  template <typename T>
+  __host__ __device__ static void type_constants(const T* p, T& gto, T& gks, bool& endo) {
+    endo = p[6] == T(1);
+    gto = endo ? T(0.073) : T(tp06::kGto);
+    gks = p[6] == T(2) ? T(0.098) : T(tp06::kGKs);
+  }
+  template <typename T>
+  __host__ __device__ static T vrate(const T* y, const T* p) {
+    T gto, gks;
+    bool endo;
+    type_constants(p, gto, gks, endo);
     TP06Fluxes<T> c;
-    tp06_fluxes(y, p, c);
-    const T V = y[0];
-    const T cc = T(kCurToConc);
-    // forward Euler: V, Ki, Nai, Rbar; buffered totals of Ca_i, Ca_ss, Ca_SR
-    const T dKi = -(c.IK - T(2) * c.INaK) * cc;
-    const T dNai = -(c.INa + c.IbNa + T(3) * c.INaK + T(3) * c.INaCa) * cc;
-    const T dCai = -(c.IbCa + c.IpCa - T(2) * c.INaCa) * T(0.5) * cc +
-                   T(kVsr / kVc) * (c.Ileak - c.Iup) + c.Ixfer;
-    const T dCass = -c.ICaL * T(kCap / (2.0 * kVss * kF)) + T(kVsr / kVss) * c.Irel -
-                    T(kVc / kVss) * c.Ixfer;
-    const T dCaSR = c.Iup - c.Ileak - c.Irel;
-    const T kcasr = tp06_kcasr(y[5]);
-    const T dRb = -T(kK2p) * kcasr * y[4] * y[6] + T(kK4) * (T(1) - y[6]);
-
-    // gates from the substep-start V (and Ca_ss for fCass)
-    T inf[12], rate[12];
-    tp06_gate_params(V, inf, rate);
-    tp06_fcass_params(y[4], inf[11], rate[11]);
-    T g[12];
-    const T hl = h * T(-kLog2e);
-    for (int a = 0; a < 12; ++a) g[a] = rl_rate2(y[7 + a], inf[a], rate[a], hl);
-
-    // commit
-    y[3] = free_from_total(total_from_free(y[3], T(kBufc), T(kKbufc)) + h * dCai, T(kBufc),
-                           T(kKbufc));
-    y[4] = free_from_total(total_from_free(y[4], T(kBufss), T(kKbufss)) + h * dCass, T(kBufss),
-                           T(kKbufss));
-    y[5] = free_from_total(total_from_free(y[5], T(kBufsr), T(kKbufsr)) + h * dCaSR, T(kBufsr),
-                           T(kKbufsr));
-    y[1] = y[1] + h * dKi;
-    y[2] = y[2] + h * dNai;
-    y[6] = y[6] + h * dRb;
-    for (int a = 0; a < 12; ++a) y[7 + a] = g[a];
-    if (!clamp) y[0] = V - h * c.Iion;
+    tp06_fluxes(y, p, c, gto, gks);
+    return -c.Iion;
+  }
+  template <typename T>
+  __host__ __device__ static void substep(T* y, const T* p, T h, bool clamp) {
+    T gto, gks;
+    bool endo;
+    type_constants(p, gto, gks, endo);
+    tp06_substep(y, p, h, clamp, gto, gks, endo);
   }
 };
 

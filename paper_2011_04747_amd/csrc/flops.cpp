@@ -67,6 +67,8 @@ extern "C" mono_status mono_model_flops(int32_t model, const double* state, cons
     count_substep<mono::MSModel>(state, params, c);
   else if (model == MONO_MODEL_TP06_EPI)
     count_substep<mono::TP06Model>(state, params, c);
+  else if (model == MONO_MODEL_TP06_TYPES)
+    count_substep<mono::TP06TypesModel>(state, params, c);
   else
     return MONO_EINVAL;
   const long long v[7] = {c.add, c.mul, c.div, c.exp, c.log, c.sqrt, c.cmp};
@@ -84,6 +86,8 @@ extern "C" mono_status mono_model_substep_host(int32_t model, double* y, const d
     mono::MSModel::substep(y, p, h, clamp != 0);
   else if (model == MONO_MODEL_TP06_EPI)
     mono::TP06Model::substep(y, p, h, clamp != 0);
+  else if (model == MONO_MODEL_TP06_TYPES)
+    mono::TP06TypesModel::substep(y, p, h, clamp != 0);
   else
     return MONO_EINVAL;
   return MONO_OK;

@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void k_adj_diff_stencil(AdjDiffArgs<T> a) {
     const int64_t jfc = jf <= last ? jf : last;
     const int64_t jbc = jb >= first ? jb : first;
     const T wf = a.e[(int64_t)p * a.Np + i];
-    const T wb = (jb >= first) ? a.e[(int64_t)p * a.Np + jbc] : T(0);
+    const T wbl = a.e[(int64_t)p * a.Np + jbc];   // jbc is a row of this instance
+    const T wb = (jb >= first) ? wbl : T(0);
     const T uf = a.lam_in[jfc] * a.minv[jfc];
     const T ub = a.lam_in[jbc] * a.minv[jbc];
     acc += wf * (uf - ui) + wb * (ub - ui);

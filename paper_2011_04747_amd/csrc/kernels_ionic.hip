@@ -234,6 +234,8 @@ void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_
     launch_ionic_m<T, LinearModel>(a, c, s);
   else if (model == MONO_MODEL_MS)
     launch_ionic_m<T, MSModel>(a, c, s);
+  else if (model == MONO_MODEL_TP06_TYPES)
+    launch_ionic_m<T, TP06TypesModel>(a, c, s);
   else
     launch_ionic_m<T, TP06Model>(a, c, s);
 }

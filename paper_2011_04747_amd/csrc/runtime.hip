@@ -72,12 +72,15 @@ void dfree(T*& p) {
 const double kTP06Init[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0, 0.0, 0.75, 0.75,
                               0.0,   1.0,   0.0,  0.0,     1.0,     0.0, 1.0, 1.0, 1.0};
 const double kMSParams[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
-const double kTP06Params[6] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0};
+const double kTP06Params[7] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0};   // row 6: cell type
 
+bool is_tp06(int m) { return m == MONO_MODEL_TP06_EPI || m == MONO_MODEL_TP06_TYPES; }
 int model_states(int m) { return m == MONO_MODEL_LINEAR ? 1 : (m == MONO_MODEL_MS ? 2 : 19); }
-int model_params(int m) { return m == MONO_MODEL_LINEAR ? 2 : (m == MONO_MODEL_MS ? 5 : 6); }
+int model_params(int m) {
+  return m == MONO_MODEL_LINEAR ? 2 : (m == MONO_MODEL_MS ? 5 : (m == MONO_MODEL_TP06_EPI ? 6 : 7));
+}
 double default_lat_threshold(int m) {
-  return m == MONO_MODEL_TP06_EPI ? -40.0 : (m == MONO_MODEL_MS ? 0.5 : 0.0);
+  return is_tp06(m) ? -40.0 : (m == MONO_MODEL_MS ? 0.5 : 0.0);
 }
 
 }  // namespace
@@ -1124,11 +1127,17 @@ void mono_destroy(mono_sim* s) {
 mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
                                 const double* params, const double* init_state, double dt0) {
   if (!s) return fail(MONO_EINVAL, "NULL simulation");
-  if (model < MONO_MODEL_LINEAR || model > MONO_MODEL_TP06_EPI)
+  if (model < MONO_MODEL_LINEAR || model > MONO_MODEL_TP06_TYPES)
     return fail(MONO_EINVAL, "unknown cell model");
   if (!(dt0 > 0.0)) return fail(MONO_EINVAL, "dt0 must be positive");
   const int S = model_states(model), P = model_params(model);
   if (params && n_params != P) return fail(MONO_EINVAL, "wrong number of parameter rows");
+  if (params && model == MONO_MODEL_TP06_TYPES)
+    for (int64_t i = 0; i < s->n; ++i) {
+      const double c = params[(size_t)6 * s->n + i];
+      if (c != 0.0 && c != 1.0 && c != 2.0)
+        return fail(MONO_EINVAL, "cell type row must hold 0, 1 or 2");
+    }
   HIP_TRY(hipStreamSynchronize(s->stream));
   drop_graph(s);
   free_model(s);
@@ -1153,7 +1162,7 @@ mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
   } else {
     for (int a = 0; a < S; ++a) {
       double v = 0.0;
-      if (model == MONO_MODEL_TP06_EPI) v = kTP06Init[a];
+      if (is_tp06(model)) v = kTP06Init[a];
       if (model == MONO_MODEL_MS) v = (a == 0) ? 0.0 : 1.0;
       std::fill(y.begin() + (size_t)a * s->n, y.begin() + (size_t)(a + 1) * s->n, v);
     }
@@ -1173,7 +1182,7 @@ mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
   std::vector<double> pu(P);
   for (int a = 0; a < P; ++a) {
     double v = model == MONO_MODEL_MS ? kMSParams[a]
-                                      : (model == MONO_MODEL_TP06_EPI ? kTP06Params[a] : 0.0);
+                                      : (is_tp06(model) ? kTP06Params[a] : 0.0);
     if (params) {
       const double* row = params + (size_t)a * s->n;
       v = row[0];
@@ -1587,6 +1596,8 @@ mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t 
   mono_status st = require_model(s);
   if (st != MONO_OK) return st;
   if (n_steps < 1 || ckpt_every < 1 || !loss) return fail(MONO_EINVAL, "bad argument");
+  if (s->model == MONO_MODEL_TP06_TYPES)
+    return fail(MONO_EUNSUPPORTED, "no adjoint for the cell-type TP06 model");
   if (s->latched) return fail(MONO_ESTATE, "simulation latched after a non-finite potential");
   st = prepare(s, dt);
   if (st != MONO_OK) return st;

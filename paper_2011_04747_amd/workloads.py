@@ -32,6 +32,12 @@ import numpy as np
 MODEL_LINEAR = 0
 MODEL_MS = 1
 MODEL_TP06 = 2
+MODEL_TP06_TYPES = 3    # TP06 with a per-node transmural cell type (7th row)
+
+# transmural cell types of MODEL_TP06_TYPES
+CELL_EPI = 0
+CELL_ENDO = 1
+CELL_M = 2
 
 ETYPE_LINE2 = 2
 ETYPE_TRI3 = 3
@@ -258,6 +264,13 @@ def tp06_params(n_nodes: int) -> np.ndarray:
     return _default_params(TP06_PARAM_DEFAULT, n_nodes)
 
 
+def tp06_types_params(types: np.ndarray) -> np.ndarray:
+    """Parameter rows of MODEL_TP06_TYPES: the TP06 defaults plus the cell
+    type of each node (CELL_EPI, CELL_ENDO or CELL_M)."""
+    types = np.asarray(types)
+    return np.vstack([tp06_params(types.size), types.astype(np.float64)[None, :]])
+
+
 def ms_params(n_nodes: int) -> np.ndarray:
     return _default_params(MS_PARAM_DEFAULT, n_nodes)
 
@@ -398,6 +411,27 @@ def sheet_planar_tp06(n: int = 501, dx: float = 0.01, D_l: float = 0.0017,
     mesh = Mesh(2, xyz, et, conn, De, grid_shape=(n, n))
     a = STIM_AMP_TP06_PLANAR if amp is None else amp
     return Workload("sheet_planar_tp06_2d", mesh, MODEL_TP06, tp06_params(mesh.n_nodes),
+                    [_planar_s1(xyz, a, t_on=t_on)], dt, t_end, 0.01, precision, -40.0)
+
+
+def sheet_transmural_tp06(n_wall: int = 151, n_height: int = 51, dx: float = 0.01,
+                          D_l: float = 0.0017, ratio: float = 0.25,
+                          layers: Tuple[float, float] = (0.3, 0.6), t_on: float = 0.0,
+                          t_end: float = 500.0, dt: float = 0.1, precision: str = "f64",
+                          amp: Optional[float] = None) -> Workload:
+    """A transmural sheet of ventricular wall: x runs from the endocardium
+    (x = 0) to the epicardium, endocardial cells up to layers[0] of the
+    thickness, M cells up to layers[1], epicardial cells beyond; fibres
+    along y, parallel to the wall surfaces, at the planar sheet's
+    conductivities (the wall is crossed transverse to the fibres), and a 1 ms
+    planar stimulus on the endocardial edge."""
+    xyz, conn, et = structured_grid((n_wall, n_height), dx)
+    De = fibre_tensor(angle_fibres(np.full(conn.shape[0], 0.5 * np.pi), 2), D_l, ratio * D_l)
+    mesh = Mesh(2, xyz, et, conn, De, grid_shape=(n_wall, n_height))
+    depth = xyz[:, 0] / ((n_wall - 1) * dx)
+    types = np.where(depth <= layers[0], CELL_ENDO, np.where(depth <= layers[1], CELL_M, CELL_EPI))
+    a = STIM_AMP_TP06_PLANAR if amp is None else amp
+    return Workload("sheet_transmural_tp06_2d", mesh, MODEL_TP06_TYPES, tp06_types_params(types),
                     [_planar_s1(xyz, a, t_on=t_on)], dt, t_end, 0.01, precision, -40.0)
 
 
