@@ -83,8 +83,8 @@ typedef enum {
  *  TP06_TYPES the same with a transmural cell type per node in a 7th
  *           parameter row: 0 epicardial, 1 endocardial (G_to = 0.073, the
  *           endocardial s gate), 2 M cell (G_Ks = 0.098); heterogeneous
- *           tissue in one simulation.  No adjoint (mono_forward_taped
- *           returns EUNSUPPORTED).                                          */
+ *           tissue in one simulation.  In mono_backward the type row is
+ *           a label: its gradient entry is 0.                               */
 typedef enum {
   MONO_MODEL_LINEAR = 0,
   MONO_MODEL_MS = 1,

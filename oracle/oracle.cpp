@@ -825,7 +825,7 @@ void reaction(Sim* s, int64_t nstep) {
 // ---------------------------------------------------------------------------
 // Jacobian of one substep at (y, p): J[i][j] = d y'_i / d (y_j for j < S,
 // p_{j-S} for j >= S), by forward-mode derivatives through the model code.
-constexpr int kJac = 25;   // 19 states + 6 parameters (TP06), the largest model
+constexpr int kJac = 26;   // 19 states + 7 parameters (TP06 with cell types), the largest model
 void substep_jacobian(int model, const double* y, const double* p, double h, int S, int P,
                       double* J) {
   DualN<kJac> yd[19], pd[8];
@@ -1191,7 +1191,6 @@ int orc_set_target(void* h, int32_t n, const int32_t* nodes, const double* targe
 int orc_forward_taped(void* h, int64_t n_steps, double dt, double* loss) {
   Sim* s = (Sim*)h;
   if (s->model < 0) return fail("no cell model");
-  if (s->model == M_TP06T) return fail("adjoint of the cell-type model not provided");
   if (s->dt != dt && prepare(s, dt) != 0) return -1;
   int lmax = 0;
   for (int x : s->l) lmax = std::max(lmax, x);

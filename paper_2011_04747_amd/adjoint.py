@@ -25,8 +25,8 @@ class AdjointProblem:
 
     def __init__(self, w: W.Workload, target: np.ndarray, n_steps: int, ckpt_every: int = 50,
                  precision: str = "f32", stream=None, replay_k=None):
-        if w.model != W.MODEL_TP06:
-            raise ValueError("scaling gradients are defined for the TP06 model")
+        if w.model not in (W.MODEL_TP06, W.MODEL_TP06_TYPES):
+            raise ValueError("scaling gradients are defined for the TP06 models")
         self.w = w
         self.target = np.ascontiguousarray(target, dtype=np.float64)
         self.n_steps = int(n_steps)

@@ -107,11 +107,13 @@ __host__ __device__ void ms_substep_vjp(const T* y, const T* p, T h, bool clamp,
 }
 
 // ---------------------------------------------------------------------------
-// TP06: reverse of TP06Model::substep.  gp[6] adjoints of {Ko, gNa, gCaL,
-// gKr, gKs, gK1}.
+// TP06: reverse of tp06_substep.  gp[6] adjoints of {Ko, gNa, gCaL, gKr,
+// gKs, gK1}; gto, gks and endo as in the forward substep (the cell type's
+// I_to and I_Ks conductances and s gate).
 template <typename T>
 __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clamp, T* lam,
-                                          T* gp) {
+                                          T* gp, T gto = T(tp06::kGto), T gks = T(tp06::kGKs),
+                                          bool endo = false) {
   using namespace tp06;
   using D = Dual<T>;
   // ---- forward intermediates ------------------------------------------------
@@ -177,7 +179,7 @@ __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clam
   const T cc = T(kCurToConc);
   // concentration slopes (for the buffered updates)
   TP06Fluxes<T> c;
-  tp06_fluxes(y, p, c);
+  tp06_fluxes(y, p, c, gto, gks);
   const T dCai = -(c.IbCa + c.IpCa - T(2) * c.INaCa) * T(0.5) * cc +
                  T(kVsr / kVc) * (c.Ileak - c.Iup) + c.Ixfer;
   const T dCass = -c.ICaL * T(kCap / (2.0 * kVss * kF)) + T(kVsr / kVss) * c.Irel -
@@ -191,7 +193,7 @@ __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clam
                                    T(kBufsr), T(kKbufsr));
   // gates: steady states and rates with their derivatives
   D ginf[12], grate[12];
-  tp06_gate_params(D(V, T(1)), ginf, grate);
+  tp06_gate_params(D(V, T(1)), ginf, grate, endo);
   tp06_fcass_params(D(Cass, T(1)), ginf[11], grate[11]);
 
   // ---- reverse ----------------------------------------------------------------
@@ -274,9 +276,9 @@ __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clam
   lsqKo += lIK1 * p[5] * T(kGK1) * xK1.v * vk;
   lvk += lIK1 * p[5] * T(kGK1) * sqKo * (xK1.v + xK1.d * vk);
   // Ito = Gto r s vk
-  ag[6] += lIto * T(kGto) * sg * vk;
-  ag[7] += lIto * T(kGto) * rg * vk;
-  lvk += lIto * T(kGto) * rg * sg;
+  ag[6] += lIto * gto * sg * vk;
+  ag[7] += lIto * gto * rg * vk;
+  lvk += lIto * gto * rg * sg;
   // IKr = gKr GKr sqKo xr1 xr2 vk
   gp[3] += lIKr * T(kGKr) * sqKo * xr1 * xr2 * vk;
   lsqKo += lIKr * p[3] * T(kGKr) * xr1 * xr2 * vk;
@@ -286,10 +288,10 @@ __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clam
   // IKs = gKs GKs xs^2 (V - EKs)
   {
     const T ve = V - EKs;
-    gp[4] += lIKs * T(kGKs) * xs * xs * ve;
-    ag[5] += lIKs * p[4] * T(kGKs) * T(2) * xs * ve;
-    aV += lIKs * p[4] * T(kGKs) * xs * xs;
-    lEKs -= lIKs * p[4] * T(kGKs) * xs * xs;
+    gp[4] += lIKs * gks * xs * xs * ve;
+    ag[5] += lIKs * p[4] * gks * T(2) * xs * ve;
+    aV += lIKs * p[4] * gks * xs * xs;
+    lEKs -= lIKs * p[4] * gks * xs * xs;
   }
   // IpK = GpK vk sig((25 - V)/5.98)
   lvk += lIpK * T(kGpK) * spk.v;
@@ -379,6 +381,16 @@ __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clam
   lam[5] = aCaSR;
   lam[6] = aRb;
   for (int a = 0; a < 12; ++a) lam[7 + a] = ag[a];
+}
+
+// TP06 with cell types: the type row (p[6]) is a label, its adjoint is zero
+template <typename T>
+__host__ __device__ void tp06_types_substep_vjp(const T* y, const T* p, T h, bool clamp, T* lam,
+                                                T* gp) {
+  T gto, gks;
+  bool endo;
+  TP06TypesModel::type_constants(p, gto, gks, endo);
+  tp06_substep_vjp(y, p, h, clamp, lam, gp, gto, gks, endo);
 }
 
 }  // namespace mono

@@ -102,6 +102,8 @@ extern "C" mono_status mono_model_vjp_host(int32_t model, const double* y, const
     mono::ms_substep_vjp(y, p, h, clamp != 0, lam, gp);
   else if (model == MONO_MODEL_TP06_EPI)
     mono::tp06_substep_vjp(y, p, h, clamp != 0, lam, gp);
+  else if (model == MONO_MODEL_TP06_TYPES)
+    mono::tp06_types_substep_vjp(y, p, h, clamp != 0, lam, gp);
   else
     return MONO_EINVAL;
   return MONO_OK;

@@ -276,6 +276,12 @@ struct TP06Adj {
     tp06_substep_vjp(y, p, h, false, lam, gp);
   }
 };
+struct TP06TypesAdj {
+  template <typename T>
+  __device__ static void vjp(const T* y, const T* p, T h, T* lam, T* gp) {
+    tp06_types_substep_vjp(y, p, h, false, lam, gp);
+  }
+};
 
 // SORT: the workgroup's nodes are taken in order of their substep count k
 // (wg_sort.h), so a wavefront replays and reverses one k where it can; the
@@ -347,6 +353,12 @@ void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_ionic<T, LinearModel, LinearAdj, false>), grid, dim3(256), 0, s, a);
   else if (model == MONO_MODEL_MS)
     hipLaunchKernelGGL((k_adj_ionic<T, MSModel, MSAdj, false>), grid, dim3(256), 0, s, a);
+  else if (model == MONO_MODEL_TP06_TYPES && a.sort)
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06TypesModel, TP06TypesAdj, true>), grid, dim3(256), 0,
+                       s, a);
+  else if (model == MONO_MODEL_TP06_TYPES)
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06TypesModel, TP06TypesAdj, false>), grid, dim3(256), 0,
+                       s, a);
   else if (a.sort)
     hipLaunchKernelGGL((k_adj_ionic<T, TP06Model, TP06Adj, true>), grid, dim3(256), 0, s, a);
   else

@@ -1596,8 +1596,6 @@ mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t 
   mono_status st = require_model(s);
   if (st != MONO_OK) return st;
   if (n_steps < 1 || ckpt_every < 1 || !loss) return fail(MONO_EINVAL, "bad argument");
-  if (s->model == MONO_MODEL_TP06_TYPES)
-    return fail(MONO_EUNSUPPORTED, "no adjoint for the cell-type TP06 model");
   if (s->latched) return fail(MONO_ESTATE, "simulation latched after a non-finite potential");
   st = prepare(s, dt);
   if (st != MONO_OK) return st;

@@ -358,7 +358,7 @@ class Sim:
         gs = np.zeros(self.n)
         gp = np.zeros(8)
         _check(lib().mono_backward(self.h, gs.ctypes.data, gp.ctypes.data))
-        P = n_params if n_params is not None else {0: 2, 1: 5, 2: 6}[self.model]
+        P = n_params if n_params is not None else {0: 2, 1: 5, 2: 6, 3: 7}[self.model]
         return gs, gp[:P]
 
     # -- test hooks --------------------------------------------------------------

@@ -18,12 +18,16 @@ from paper_2011_04747_amd import workloads as W
 def _make(model, sigma, scal):
     if model == "tp06":
         w = W.adjoint_slab(shape=(9, 7, 5), t_end=6.0, n_sensors=20)
+    elif model == "tp06types":
+        # endocardial, M and epicardial columns of a small transmural sheet
+        w = W.sheet_transmural_tp06(n_wall=9, n_height=7, t_end=6.0)
+        w.sensors = np.array([1, 12, 22, 31, 40, 50, 62], np.int32)
     else:
         w = W.cable_ms(n_nodes=31, length=0.3, t_end=8.0)
         w.sensors = np.array([3, 10, 20, 29], np.int32)
     w.mesh.sigma = sigma
     p = w.params.copy()
-    if model == "tp06":
+    if model != "ms":
         p[1:6] *= scal[:, None]
     else:
         p *= scal[:, None]
@@ -31,7 +35,7 @@ def _make(model, sigma, scal):
     return w
 
 
-@pytest.mark.parametrize("model", ["ms", "tp06"])
+@pytest.mark.parametrize("model", ["ms", "tp06", "tp06types"])
 def test_oracle_adjoint_matches_finite_differences(oracle_mod, model):
     rng = np.random.default_rng(1)
     w = _make(model, None, np.ones(5))
@@ -71,15 +75,17 @@ def test_oracle_adjoint_matches_finite_differences(oracle_mod, model):
         assert ga == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(gp).max())
 
 
-@pytest.mark.parametrize("model,S,P", [(2, 19, 6), (1, 2, 5), (0, 1, 2)])
+@pytest.mark.parametrize("model,S,P", [(3, 19, 7), (2, 19, 6), (1, 2, 5), (0, 1, 2)])
 @pytest.mark.parametrize("trial", range(6))
 def test_library_substep_vjp_matches_finite_differences(model, S, P, trial):
     from paper_2011_04747_amd import mono
     rng = np.random.default_rng(10 + trial)
     y = W.random_state(model, 1, 100 + trial)[:, 0]
-    if model == 2:
+    if model in (2, 3):
         y[0] = (-85.0, -60.0, -39.9, -41.0, 10.0, 14.99999)[trial]
         p = np.array(W.TP06_PARAM_DEFAULT) * rng.uniform(0.7, 1.3, 6)
+        if model == 3:
+            p = np.append(p, (W.CELL_EPI, W.CELL_ENDO, W.CELL_M)[trial % 3])
     elif model == 1:
         p = np.array(W.MS_PARAM_DEFAULT)
         y[0] = (0.05, 0.08, 0.3, 0.6, 0.9, 0.95)[trial]      # away from v_gate
@@ -101,6 +107,9 @@ def test_library_substep_vjp_matches_finite_differences(model, S, P, trial):
         e = 1e-3 * max(abs(y[a]), 1e-4)
         fd = d4(lambda x: f(x, p), y, a, e)
         assert l_in[a] == pytest.approx(fd, rel=2e-6, abs=1e-7 * np.abs(l_in).max()), a
+    if model == 3:
+        assert gp[6] == 0.0          # the cell type is a label
+        P = 6
     for b in range(P):
         e = 1e-3 * max(abs(p[b]), 1e-4)
         fd = d4(lambda x: f(y, x), p, b, e)

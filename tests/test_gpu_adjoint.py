@@ -34,6 +34,11 @@ def _problem(kind):
     elif kind == "tp06":
         w = W.adjoint_slab(shape=(23, 19, 7), t_end=12.0, n_sensors=64)
         base = -80.0
+    elif kind == "tp06types":
+        # endocardial, M and epicardial layers (per-node cell type row)
+        w = W.sheet_transmural_tp06(n_wall=41, n_height=13, t_end=15.0)
+        w.sensors = np.sort(rng.choice(w.mesh.n_nodes, 50, replace=False)).astype(np.int32)
+        base = -80.0
     else:
         w = W.batched_sheets(n_inst=4, side_lo=15, side_hi=33, t_end=10.0)
         w.sensors = np.sort(rng.choice(w.mesh.n_nodes, 60, replace=False)).astype(np.int32)
@@ -66,7 +71,7 @@ def _gpu_grad(torch, w, target, kt, prec, ckpt):
     return L, gs, gp, s
 
 
-@pytest.mark.parametrize("kind", ["ms", "tp06", "batched"])
+@pytest.mark.parametrize("kind", ["ms", "tp06", "batched", "tp06types"])
 def test_adjoint_fp64_matches_oracle(torch, kind):
     w, target = _problem(kind)
     Lo, gso, gpo, kt = _oracle_grad(w, target)
@@ -98,7 +103,7 @@ def test_adjoint_checkpoint_interval_does_not_change_gradients(torch):
             assert L == ref[0] and (gs == ref[1]).all() and (gp == ref[2]).all()
 
 
-@pytest.mark.parametrize("kind", ["tp06", "batched"])
+@pytest.mark.parametrize("kind", ["tp06", "batched", "tp06types"])
 def test_adjoint_fp32_against_fp64_oracle(torch, kind):
     w, target = _problem(kind)
     Lo, gso, gpo, kt = _oracle_grad(w, target)

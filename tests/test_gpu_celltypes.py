@@ -87,8 +87,17 @@ def test_cell_type_row_is_validated(torch):
         mono.Sim.from_workload(w, "f64")
 
 
-def test_no_adjoint_for_cell_types(torch):
-    w = W.sheet_transmural_tp06(n_wall=9, n_height=5, t_end=1.0)
+def test_cell_type_gradient_entry_is_zero(torch):
+    """The type row is a label: mono_backward reports 0 for it while the
+    conductance rows get nonzero gradients (the FP64 values against the
+    oracle are in test_gpu_adjoint)."""
+    w = W.sheet_transmural_tp06(n_wall=21, n_height=7, t_end=8.0)
+    sens = np.arange(0, w.mesh.n_nodes, 5, dtype=np.int32)
+    target = np.full((w.n_steps, sens.size), -80.0)
     s = mono.Sim.from_workload(w, "f64")
-    with pytest.raises(mono.MonoError, match="EUNSUPPORTED"):
-        s.forward_taped(4, w.dt)
+    s.set_sensors(sens, target)
+    s.forward_taped(w.n_steps, w.dt, 4)
+    _, gp = s.backward()
+    torch.cuda.synchronize()
+    assert gp.shape == (7,) and gp[6] == 0.0
+    assert np.all(gp[1:6] != 0.0)
