@@ -46,6 +46,8 @@ def _traffic(kernel, workload, launch):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (copy-calibrated), or None when absent, taken on another workload
     or launch shape, or when the kernel's sources have changed since."""
+    if workload is None:
+        return None
     suffix = "" if workload == "slab" else f"_{workload}"
     p = os.path.join(ROOT, "profiles", f"traffic_{kernel}{suffix}.json")
     if not os.path.exists(p):
@@ -176,6 +178,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--layout", default="auto", choices=["auto", "ell", "stencil"])
     ap.add_argument("--workload", default="slab", choices=["slab", "batched", "tets"])
+    ap.add_argument("--order", default="rcm", choices=["rcm", "morton", "random", "grid"],
+                    help="node order of the tetrahedral slab")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--cpu-steps-1t", type=int, default=3)
@@ -201,14 +205,18 @@ def main():
         wl_name = ("slab_tp06_3d_ischemic 201x201x51 (2,060,451 nodes), Q1 hexes, dx=0.01 cm, "
                    "dt=0.1 ms, S1+S2")
     elif args.workload == "tets":
-        w = W.slab_ischemic_tets(precision="f32")
+        w = W.slab_ischemic_tets(precision="f32", order=args.order)
+        order_name = {"rcm": "RCM", "morton": "Morton (Z-order)", "random": "shuffled",
+                      "grid": "grid"}[args.order]
         wl_name = ("slab_tp06_3d_ischemic_tets 201x201x51 (2,060,451 nodes, "
-                   f"{w.mesh.n_elems:,} linear tetrahedra), RCM node order, dx=0.01 cm, "
+                   f"{w.mesh.n_elems:,} linear tetrahedra), {order_name} node order, dx=0.01 cm, "
                    "dt=0.1 ms, S1+S2")
     else:
         w = W.batched_sheets(precision="f32")
         wl_name = (f"batched_tp06_2d: 64 sheets, sides U{{50..400}} seed 4, "
                    f"{w.mesh.n_nodes} nodes, log-normal sigma, dt=0.1 ms")
+    # the committed traffic counters of the tetrahedral slab were taken in RCM order
+    traffic_key = args.workload if args.workload != "tets" or args.order == "rcm" else None
     n = w.mesh.n_nodes
     stream = torch.cuda.Stream()
     sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
@@ -326,14 +334,14 @@ def main():
                  "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
                  "avg_us": d_us, "avg_us_per_launch_events": d_event_us,
-                 "traffic": _traffic("diffusion", args.workload, launch)}
+                 "traffic": _traffic("diffusion", traffic_key, launch)}
     diff_roof["frac"] = diff_roof["achieved"] / HBM_PEAK_GBS
     react_roof = {"kernel": "k_ionic<float,TP06>", "bound": "alu",
                   "achieved": react_flops / (r_us * 1e-6) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                   "unit": "TFLOP/s", "ops_per_substep": ops, "substeps_per_launch": ksum / kt_steps,
                   "wavefront_efficiency": ksum / kwave if kwave else None, "avg_us": r_us,
                   "avg_us_per_launch_events": r_event_us,
-                  "traffic": _traffic("reaction", args.workload, launch)}
+                  "traffic": _traffic("reaction", traffic_key, launch)}
     react_roof["frac"] = react_roof["achieved"] / FP32_VECTOR_PEAK_TFLOPS
     dominant = react_roof if react_total >= diff_total else diff_roof
     roofline = {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}

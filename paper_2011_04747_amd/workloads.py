@@ -187,11 +187,38 @@ def structured_simplices(shape: Tuple[int, ...], h: float):
     return xyz, np.concatenate(tets).astype(np.int32), ETYPE_TET4
 
 
+def _spread_bits(v: np.ndarray, dim: int) -> np.ndarray:
+    """Insert dim-1 zero bits after each of the low 63 // dim bits of v."""
+    v = v.astype(np.uint64)
+    out = np.zeros_like(v)
+    for b in range(63 // dim):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(dim * b)
+    return out
+
+
+def morton_codes(xyz: np.ndarray) -> np.ndarray:
+    """Z-order (Morton) keys of points: the coordinates scaled by one factor
+    (the largest side of the bounding box, so the curve is the same along
+    every axis) to the integer range of their share of 63 bits, bits
+    interleaved (x lowest)."""
+    n, dim = xyz.shape
+    bits = 63 // dim
+    lo = xyz.min(axis=0)
+    span = float((xyz.max(axis=0) - lo).max()) or 1.0
+    q = np.floor((xyz - lo) / span * (2.0 ** bits - 1)).astype(np.uint64)
+    key = np.zeros(n, np.uint64)
+    for d in range(dim):
+        key |= _spread_bits(q[:, d], dim) << np.uint64(d)
+    return key
+
+
 def renumber(xyz: np.ndarray, conn: np.ndarray, order: str, seed: int = 0):
     """Node renumbering of a mesh: "grid" keeps it, "random" shuffles it
     (seeded), "rcm" shuffles and then applies reverse Cuthill-McKee on the
     node graph (the bandwidth-reducing order an unstructured mesh would be
-    stored in).  Returns (xyz, conn, new_of_old)."""
+    stored in), "morton" shuffles and then sorts the nodes along the Z-order
+    curve of their coordinates (a locality order that needs no graph).
+    Returns (xyz, conn, new_of_old)."""
     n = xyz.shape[0]
     if order == "grid":
         return xyz, conn, np.arange(n)
@@ -210,8 +237,15 @@ def renumber(xyz: np.ndarray, conn: np.ndarray, order: str, seed: int = 0):
         pos = np.empty(n, np.int64)
         pos[rcm] = np.arange(n)
         new_of_old = pos[new_of_old]
+    elif order == "morton":
+        key = np.empty(n, np.uint64)
+        key[new_of_old] = morton_codes(xyz)            # key of each shuffled index
+        zs = np.argsort(key, kind="stable")            # shuffled index at new position
+        pos = np.empty(n, np.int64)
+        pos[zs] = np.arange(n)
+        new_of_old = pos[new_of_old]
     elif order != "random":
-        raise ValueError("order must be grid, random or rcm")
+        raise ValueError("order must be grid, random, rcm or morton")
     xyz2 = np.empty_like(xyz)
     xyz2[new_of_old] = xyz
     return xyz2, new_of_old[conn].astype(np.int32), new_of_old

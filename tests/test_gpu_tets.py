@@ -59,7 +59,7 @@ def _run_pair(torch, w, n_steps, prec, every):
     return o, s, levels
 
 
-@pytest.mark.parametrize("order", ["grid", "random", "rcm"])
+@pytest.mark.parametrize("order", ["grid", "random", "rcm", "morton"])
 def test_tet_slab_fp64_parity(torch, order):
     w = W.slab_ischemic_tets(shape=(13, 11, 7), order=order, t_end=30.0, precision="f64")
     o, s, levels = _run_pair(torch, w, w.n_steps, "f64", every=100)
@@ -81,8 +81,8 @@ def test_tri_sheet_fp64_parity(torch):
 
 
 def test_tet_slab_fp32_bounds_and_relabelling(torch):
-    """FP32 on the RCM-ordered slab against the FP64 oracle, and the random
-    and RCM orders giving the grid order's potentials node for node (FP64,
+    """FP32 on the RCM-ordered slab against the FP64 oracle, and the random,
+    RCM and Morton orders giving the grid order's potentials node for node (FP64,
     different summation orders, 1e-6 of 100 mV)."""
     from oracle.oracle import Oracle
     w = W.slab_ischemic_tets(shape=(13, 11, 7), order="rcm", t_end=30.0, precision="f32")
@@ -99,7 +99,7 @@ def test_tet_slab_fp32_bounds_and_relabelling(torch):
     # relabelling: same seeds, so the same permutation is reproduced
     xyz, conn, _ = W.structured_simplices((13, 11, 7), 0.01)
     ref = None
-    for order in ("grid", "random", "rcm"):
+    for order in ("grid", "random", "rcm", "morton"):
         _, _, new = W.renumber(xyz, conn, order, seed=7)
         wv = W.slab_ischemic_tets(shape=(13, 11, 7), order=order, t_end=30.0, precision="f64")
         sv = mono.Sim.from_workload(wv, "f64")

@@ -526,14 +526,29 @@ def test_linear_fields_energy_exact_on_distorted_simplices(oracle_mod, dim):
 
 
 def test_renumbering_is_a_relabelling(oracle_mod):
-    """The random and RCM orders of the tetrahedral slab relabel nodes only:
-    K and the lumped mass permute with them."""
+    """The random, RCM and Morton orders of the tetrahedral slab relabel nodes
+    only: K and the lumped mass permute with them."""
     xyz, conn, et = W.structured_simplices((5, 4, 3), 0.2)
     De = np.broadcast_to(np.diag([1.0, 0.5, 0.25]) * 1e-3, (conn.shape[0], 3, 3)).copy()
     K0, m0 = oracle_mod.Oracle(W.Mesh(3, xyz, et, conn, De)).dense_K()
-    for order in ("random", "rcm"):
+    for order in ("random", "rcm", "morton"):
         x2, c2, new = W.renumber(xyz, conn, order, seed=3)
         assert sorted(new.tolist()) == list(range(xyz.shape[0]))
         K, m = oracle_mod.Oracle(W.Mesh(3, x2, et, c2, De)).dense_K()
         assert np.allclose(K[np.ix_(new, new)], K0, rtol=0, atol=1e-15)
         assert np.allclose(m[new], m0, rtol=1e-15, atol=0)
+
+
+def test_morton_order_is_the_z_curve():
+    """On a 2^a x 2^b grid the Z-order visits the 2x2 (2x2x2) blocks whole:
+    x varies fastest inside a block, then y (then z), recursively."""
+    for shape in ((4, 4), (8, 4), (4, 4, 4)):
+        xyz, conn, _ = W.structured_grid(shape, 1.0)
+        x2, _, _ = W.renumber(xyz, conn, "morton", seed=5)
+        q = np.rint(x2).astype(np.int64)
+        d = len(shape)
+        key = np.zeros(len(q), np.int64)
+        for b in range(3):                     # interleave by hand, x lowest
+            for a in range(d):
+                key |= ((q[:, a] >> b) & 1) << (d * b + a)
+        assert (np.diff(key) > 0).all()
