@@ -65,6 +65,41 @@ def _traffic(kernel, workload, launch):
     return t["bytes_per_launch"]
 
 
+def full_run(w, stream, launch, layout):
+    """The workload's whole simulated interval from t = 0 (every phase: the
+    S1 front crossing resting tissue, plateau, repolarisation, S2 and
+    re-entry), graph-replayed and timed with HIP events on the simulation's
+    stream; then the same run again with the substep statistics on for the
+    mean k and the wavefront efficiency of the reaction."""
+    import torch
+    from paper_2011_04747_amd import mono
+    steps = w.n_steps
+    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    sim.set_launch(**launch)
+    sim.step(steps, w.dt, flags=mono.STEP_CAPTURE)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(steps, w.dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    lat = sim.get(mono.FIELD_LAT)
+    sim.close()
+    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    sim.set_launch(**launch)
+    sim.stats_enable(True)
+    sim.step(steps, w.dt)
+    ksum, kwave, node_steps, ksat = sim.stats()
+    sim.close()
+    return {"steps": steps, "simulated_ms": steps * w.dt, "ms": ms,
+            "node_updates_per_s": w.mesh.n_nodes * steps / (ms * 1e-3),
+            "mean_k": ksum / max(1, node_steps), "wave_efficiency": ksum / max(1, kwave),
+            "k_at_kmax_frac": ksat / max(1, node_steps),
+            "activated_frac": float((lat >= 0).mean())}
+
+
 def cpu_baseline(w, steps, steps_1t):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the workload:
     `steps` outer steps on all threads, then `steps_1t` more on one thread."""
@@ -187,6 +222,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip timing the workload's whole simulated interval")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -368,6 +405,10 @@ def main():
                     "lat_max_ms": float(np.abs(l32 - l64)[both].max()) if both.any() else None,
                     "activated_equal": bool(((l32 > 0) == (l64 > 0)).all())}
 
+    full = None
+    if not args.no_full_run and args.workload == "slab":
+        full = full_run(w, stream, launch, layout)
+
     adjoint = None
     if not args.no_adjoint and args.workload == "slab":
         adjoint = adjoint_leg(stream, not args.no_accuracy, not args.no_tune)
@@ -390,7 +431,7 @@ def main():
                       "k_histogram": {str(k): int(c) for k, c in enumerate(khist.tolist()) if c},
                       "node_ms_per_s": n * w.dt * args.steps / (ms * 1e-3),
                       "repeats_ms": [t[0] for t in times],
-                      "wall_s": wall},
+                      "wall_s": wall, "full_run": full},
            "roofline": roofline,
            "kernels": {"diffusion": diff_roof, "reaction": react_roof,
                        "ms_per_step": {"diffusion": diff_total, "reaction": react_total}},
