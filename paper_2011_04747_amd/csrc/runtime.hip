@@ -144,11 +144,19 @@ struct mono_sim {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool g_valid = false;
+  // the same chunk captured with the stimulus test switched off, replayed
+  // for chunks in which no stimulus window can open (the diffusion kernels
+  // then skip reading the device clock for the window test)
+  hipGraph_t graph_q = nullptr;
+  hipGraphExec_t gexec_q = nullptr;
+  bool quiet = false;              // set while capturing graph_q
   // graph of a shorter run (the remainder of a step count that graph_steps
   // does not divide)
   hipGraph_t graph_r = nullptr;
   hipGraphExec_t gexec_r = nullptr;
   int64_t g_r_steps = 0;
+  hipGraph_t graph_rq = nullptr;   // its capture without the stimulus test
+  hipGraphExec_t gexec_rq = nullptr;
   LaunchCfg lc;
   // debug
   KTraceArgs kt{};
@@ -191,11 +199,19 @@ void drop_graph(mono_sim* s) {
   s->gexec = nullptr;
   s->graph = nullptr;
   s->g_valid = false;
+  if (s->gexec_q) (void)hipGraphExecDestroy(s->gexec_q);
+  if (s->graph_q) (void)hipGraphDestroy(s->graph_q);
+  s->gexec_q = nullptr;
+  s->graph_q = nullptr;
   if (s->gexec_r) (void)hipGraphExecDestroy(s->gexec_r);
   if (s->graph_r) (void)hipGraphDestroy(s->graph_r);
   s->gexec_r = nullptr;
   s->graph_r = nullptr;
   s->g_r_steps = 0;
+  if (s->gexec_rq) (void)hipGraphExecDestroy(s->gexec_rq);
+  if (s->graph_rq) (void)hipGraphDestroy(s->graph_rq);
+  s->gexec_rq = nullptr;
+  s->graph_rq = nullptr;
 }
 
 // upload n_host doubles into a device array of the simulation's precision
@@ -344,7 +360,7 @@ DiffArgs<T> diff_args(mono_sim* s, int pass_in, int half, int m, int64_t g) {
   a.inst_off = s->d_inst_off;
   a.l = s->d_l;
   a.dt_ad = s->d_dtad;
-  a.stim_mask = s->d_mask;
+  a.stim_mask = s->quiet ? nullptr : s->d_mask;
   a.stim = s->stim;
   a.stim.L = 0;
   if (s->n_inst == 1 && !s->l.empty() && s->l[0] > 0) {
@@ -515,8 +531,41 @@ mono_status ensure_graph(mono_sim* s) {
   HIP_TRY(hipStreamEndCapture(s->stream, &g));
   s->graph = g;
   HIP_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+  if (s->stim.n > 0) {
+    s->quiet = true;
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      enqueue(s, s->lc.graph_steps);
+      e = hipStreamEndCapture(s->stream, &g);
+    }
+    s->quiet = false;
+    HIP_TRY(e);
+    s->graph_q = g;
+    HIP_TRY(hipGraphInstantiate(&s->gexec_q, s->graph_q, nullptr, nullptr, 0));
+  }
   s->g_valid = true;
   return MONO_OK;
+}
+
+// True when no stimulus can be open on any diffusion substep of the outer
+// steps [step0, step0 + count): single instance, by the integer substep
+// windows the kernels test; several instances (per-instance substep
+// lengths), by time with a margin of one outer step on either side.
+bool chunk_is_quiet(const mono_sim* s, int64_t step0, int64_t count) {
+  if (s->n_inst == 1 && !s->l.empty() && s->l[0] > 0) {
+    const int L = s->l[0];
+    const int64_t lo = 2 * step0 * (int64_t)L, hi = 2 * (step0 + count) * (int64_t)L;
+    for (int q = 0; q < s->stim.n; ++q) {
+      const int64_t on = first_substep_from(s->stim.t_on[q], s->dt, L, s->dt_ad[0]);
+      const int64_t end = first_substep_from(s->stim.t_end[q], s->dt, L, s->dt_ad[0]);
+      if (on < end && on < hi && end > lo) return false;
+    }
+    return true;
+  }
+  const double t0 = (double)(step0 - 1) * s->dt, t1 = (double)(step0 + count + 1) * s->dt;
+  for (int q = 0; q < s->stim.n; ++q)
+    if (s->stim.t_on[q] < t1 && s->stim.t_end[q] > t0) return false;
+  return true;
 }
 
 // Graph of `steps` outer steps for the remainder of a run (cached while the
@@ -525,8 +574,12 @@ mono_status ensure_rem_graph(mono_sim* s, int64_t steps) {
   if (s->g_r_steps == steps && s->gexec_r) return MONO_OK;
   if (s->gexec_r) (void)hipGraphExecDestroy(s->gexec_r);
   if (s->graph_r) (void)hipGraphDestroy(s->graph_r);
+  if (s->gexec_rq) (void)hipGraphExecDestroy(s->gexec_rq);
+  if (s->graph_rq) (void)hipGraphDestroy(s->graph_rq);
   s->gexec_r = nullptr;
   s->graph_r = nullptr;
+  s->gexec_rq = nullptr;
+  s->graph_rq = nullptr;
   s->g_r_steps = 0;
   HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
   enqueue(s, steps);
@@ -534,6 +587,18 @@ mono_status ensure_rem_graph(mono_sim* s, int64_t steps) {
   HIP_TRY(hipStreamEndCapture(s->stream, &g));
   s->graph_r = g;
   HIP_TRY(hipGraphInstantiate(&s->gexec_r, s->graph_r, nullptr, nullptr, 0));
+  if (s->stim.n > 0) {
+    s->quiet = true;
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      enqueue(s, steps);
+      e = hipStreamEndCapture(s->stream, &g);
+    }
+    s->quiet = false;
+    HIP_TRY(e);
+    s->graph_rq = g;
+    HIP_TRY(hipGraphInstantiate(&s->gexec_rq, s->graph_rq, nullptr, nullptr, 0));
+  }
   s->g_r_steps = steps;
   return MONO_OK;
 }
@@ -1304,7 +1369,9 @@ mono_status mono_step(mono_sim* s, int64_t n_steps, double dt, uint32_t flags) {
     st = ensure_graph(s);
     if (st != MONO_OK) return st;
     while (left >= chunk) {
-      HIP_TRY(hipGraphLaunch(s->gexec, s->stream));
+      const int64_t step0 = s->step + (n_steps - left);
+      const bool q = s->gexec_q && chunk_is_quiet(s, step0, chunk);
+      HIP_TRY(hipGraphLaunch(q ? s->gexec_q : s->gexec, s->stream));
       left -= chunk;
     }
   }
@@ -1314,7 +1381,8 @@ mono_status mono_step(mono_sim* s, int64_t n_steps, double dt, uint32_t flags) {
     } else {
       st = ensure_rem_graph(s, left);
       if (st != MONO_OK) return st;
-      HIP_TRY(hipGraphLaunch(s->gexec_r, s->stream));
+      const bool q = s->gexec_rq && chunk_is_quiet(s, s->step + (n_steps - left), left);
+      HIP_TRY(hipGraphLaunch(q ? s->gexec_rq : s->gexec_r, s->stream));
     }
   }
   HIP_TRY(hipGetLastError());

@@ -389,6 +389,34 @@ def test_graph_remainders_and_capture_only(torch):
         assert (a.get(f) == b.get(f)).all()
 
 
+@pytest.mark.parametrize("which", ["slab", "batch"])
+def test_quiet_chunks_equal_eager(torch, which):
+    """Graph chunks in which no stimulus window can open replay a capture
+    without the window test; stimuli opening and closing inside chunks, on
+    chunk edges and between them give eager stepping's bits."""
+    if which == "slab":
+        w = W.slab_ischemic(shape=(21, 17, 7), t_end=20.0)
+        nodes = w.stimuli[0].nodes
+    else:
+        w = W.batched_sheets(n_inst=3, side_lo=12, side_hi=24, t_end=20.0)
+        nodes = w.stimuli[0].nodes
+    amp = w.stimuli[0].amplitude
+    # windows: inside the 2nd chunk, starting exactly on a chunk edge
+    # (step 16 = 1.6 ms), spanning an edge, and late in the run
+    w.stimuli = [W.Stimulus(nodes, 0.25, 0.5, amp), W.Stimulus(nodes, 1.6, 0.3, amp),
+                 W.Stimulus(nodes, 3.1, 0.2, amp), W.Stimulus(nodes, 9.55, 1.0, amp)]
+    for prec in ("f32", "f64"):
+        a = mono.Sim.from_workload(w, prec)
+        b = mono.Sim.from_workload(w, prec)
+        a.set_launch(graph_steps=8)
+        for n in (40, 24, 56):
+            a.step(n, w.dt)
+        b.step(120, w.dt, flags=mono.STEP_EAGER)
+        for f in (mono.FIELD_V, mono.FIELD_LAT, mono.FIELD_K):
+            assert (a.get(f) == b.get(f)).all(), (prec, f)
+        assert (a.get(mono.FIELD_LAT) >= 0).any()
+
+
 # ---------------------------------------------------------------------------
 # edge cases and failure handling
 # ---------------------------------------------------------------------------
