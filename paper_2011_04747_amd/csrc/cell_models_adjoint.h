@@ -124,7 +124,6 @@ __host__ __device__ void tp06_substep_vjp(const T* y, const T* p, T h, bool clam
   const T rtf = T(kRTF), frt = T(kFRT);
   const T EK = rtf * xlog(xdiv(Ko, Ki));
   const T ENa = rtf * xlog(xdiv(T(kNao), Nai));
-  const T ECa = T(0.5) * rtf * xlog(xdiv(T(kCao), Cai));
   const T nKs = Ko + T(kPKNa * kNao), dKs = Ki + T(kPKNa) * Nai;
   const T EKs = rtf * xlog(xdiv(nKs, dKs));
   const T sqKo = xsqrt(Ko * T(1.0 / 5.4));

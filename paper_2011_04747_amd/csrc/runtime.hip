@@ -798,11 +798,31 @@ mono_status capture_graph(mono_sim* s, F body, hipGraphExec_t* out) {
   return MONO_OK;
 }
 
+// Segment graphs of full and remainder length, each also captured with the
+// stimulus mask switched off (the *q members, when the simulation has
+// stimuli) for segments in which no stimulus window can open.
 struct GraphPair {
-  hipGraphExec_t full = nullptr, rest = nullptr;
+  hipGraphExec_t full = nullptr, rest = nullptr, fullq = nullptr, restq = nullptr;
   ~GraphPair() {
-    if (full) (void)hipGraphExecDestroy(full);
-    if (rest) (void)hipGraphExecDestroy(rest);
+    for (hipGraphExec_t g : {full, rest, fullq, restq})
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+  template <class MK>
+  mono_status capture(mono_sim* s, MK make, int64_t n_steps, int64_t C) {
+    const int64_t rest_n = n_steps % C;
+    mono_status st = MONO_OK;
+    for (int quiet = 0; quiet < (s->stim.n > 0 ? 2 : 1) && st == MONO_OK; ++quiet) {
+      s->quiet = quiet != 0;
+      if (n_steps >= C) st = capture_graph(s, make(C), quiet ? &fullq : &full);
+      if (st == MONO_OK && rest_n) st = capture_graph(s, make(rest_n), quiet ? &restq : &rest);
+    }
+    s->quiet = false;
+    return st;
+  }
+  hipGraphExec_t pick(const mono_sim* s, int64_t step0, int64_t cn, int64_t C) const {
+    const bool q = chunk_is_quiet(s, step0, cn);
+    if (cn == C) return (q && fullq) ? fullq : full;
+    return (q && restq) ? restq : rest;
   }
 };
 
@@ -813,7 +833,6 @@ template <typename T>
 mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
   const int64_t C = s->ckpt_every;
   const int64_t nck = (n_steps + C - 1) / C;
-  const int64_t rest = n_steps % C;
   GraphPair gp;
   auto segment = [s](int64_t cn) {
     return [s, cn]() {
@@ -821,14 +840,12 @@ mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
       launch_advance_clock(s->d_base, cn, s->stream);
     };
   };
-  mono_status st = MONO_OK;
-  if (n_steps >= C) st = capture_graph(s, segment(C), &gp.full);
-  if (st == MONO_OK && rest) st = capture_graph(s, segment(rest), &gp.rest);
+  mono_status st = gp.capture(s, segment, n_steps, C);
   if (st != MONO_OK) return st;
   for (int64_t c = 0; c < nck; ++c) {
     HIP_TRY(save_state(s, s->d_ckpt[c]));
     const int64_t cn = std::min(C, n_steps - c * C);
-    HIP_TRY(hipGraphLaunch(cn == C ? gp.full : gp.rest, s->stream));
+    HIP_TRY(hipGraphLaunch(gp.pick(s, s->step, cn, C), s->stream));
     s->step += cn;
   }
   HIP_TRY(save_state(s, s->d_final));
@@ -853,7 +870,6 @@ template <typename T>
 mono_status backward_t(mono_sim* s) {
   const int64_t C = s->ckpt_every, N = s->tape_steps;
   const int64_t nck = (N + C - 1) / C;
-  const int64_t rest = N % C;
   const int L = s->l_max, S = s->S;
   const size_t Np = s->Np;
   T* const vsub = (T*)s->d_seg_vsub;
@@ -908,15 +924,13 @@ mono_status backward_t(mono_sim* s) {
     };
   };
   GraphPair gp;
-  mono_status st = MONO_OK;
-  if (N >= C) st = capture_graph(s, segment(C), &gp.full);
-  if (st == MONO_OK && rest) st = capture_graph(s, segment(rest), &gp.rest);
+  mono_status st = gp.capture(s, segment, N, C);
   if (st != MONO_OK) return st;
   for (int64_t c = nck - 1; c >= 0; --c) {
     const int64_t t0 = c * C, cn = std::min(C, N - t0);
     HIP_TRY(load_state(s, s->d_ckpt[c], vsub));
     launch_set_clock(s->d_base, s->tape_step0 + t0, s->stream);
-    HIP_TRY(hipGraphLaunch(cn == C ? gp.full : gp.rest, s->stream));
+    HIP_TRY(hipGraphLaunch(gp.pick(s, s->tape_step0 + t0, cn, C), s->stream));
   }
   HIP_TRY(hipGetLastError());
   // leave the simulation where the taped forward run ended
