@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--layout", default="auto", choices=["auto", "ell", "stencil"])
     ap.add_argument("--workload", default="slab", choices=["slab", "batched", "tets"])
+    ap.add_argument("--init", default="rest", choices=["rest", "paced"],
+                    help="initial state of the slab: published values or paced steady state")
     ap.add_argument("--order", default="rcm", choices=["rcm", "morton", "random", "grid"],
                     help="node order of the tetrahedral slab")
     ap.add_argument("--no-tune", action="store_true")
@@ -238,9 +240,11 @@ def main():
     layout = {"auto": mono.LAYOUT_AUTO, "ell": mono.LAYOUT_ELL,
               "stencil": mono.LAYOUT_STENCIL}[args.layout]
     if args.workload == "slab":
-        w = W.slab_ischemic(precision="f32")
+        w = W.slab_ischemic(precision="f32", init=args.init)
         wl_name = ("slab_tp06_3d_ischemic 201x201x51 (2,060,451 nodes), Q1 hexes, dx=0.01 cm, "
-                   "dt=0.1 ms, S1+S2")
+                   "dt=0.1 ms, S1+S2" +
+                   (", paced initial state (400 beats at 1000 ms)" if args.init == "paced"
+                    else ""))
     elif args.workload == "tets":
         w = W.slab_ischemic_tets(precision="f32", order=args.order)
         order_name = {"rcm": "RCM", "morton": "Morton (Z-order)", "random": "shuffled",

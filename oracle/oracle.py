@@ -145,7 +145,8 @@ class Oracle:
 
     @classmethod
     def from_workload(cls, w, **kw):
-        return cls(w.mesh, w.model, w.params, None, w.dt0, w.lat_threshold, w.stimuli, **kw)
+        return cls(w.mesh, w.model, w.params, w.init_state, w.dt0, w.lat_threshold, w.stimuli,
+                   **kw)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -237,7 +237,7 @@ class Sim:
     def from_workload(cls, w, precision: Optional[str] = None, stream=None,
                       layout: int = LAYOUT_AUTO, with_stimuli: bool = True):
         s = cls(w.mesh, precision or w.precision, stream, layout)
-        s.set_cell_model(w.model, w.params, None, w.dt0)
+        s.set_cell_model(w.model, w.params, w.init_state, w.dt0)
         s.set_lat_threshold(w.lat_threshold)
         if with_stimuli:
             for st in w.stimuli:

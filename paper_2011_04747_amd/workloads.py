@@ -113,6 +113,7 @@ class Workload:
     lat_threshold: float
     sensors: Optional[np.ndarray] = None
     extra: dict = dataclasses.field(default_factory=dict)
+    init_state: Optional[np.ndarray] = None   # (n_states, n_nodes) SoA, None = published
 
     @property
     def n_steps(self) -> int:
@@ -377,11 +378,28 @@ def ischemic_zone(xyz: np.ndarray, size_xy: Tuple[float, float], z_mid: float,
     return (u / semi[0]) ** 2 + (v / semi[1]) ** 2 + (dz_ / semi[2]) ** 2 <= 1.0
 
 
+def tp06_paced_state() -> dict:
+    """The TP06 states at the end of diastole after 400 beats at a cycle
+    length of 1000 ms, for normal tissue and for the ischemic zone's
+    parameters ({"normal": (19,), "ischemic": (19,)}), as stored by
+    tests/golden/pace_tp06.py (FP64 CPU oracle)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "tests", "golden", "tp06_paced.json")
+    with open(path) as f:
+        d = json.load(f)
+    return {k: np.asarray(d[k]["state"], dtype=np.float64) for k in ("normal", "ischemic")}
+
+
 def slab_ischemic(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,
                   D_t: float = 0.0003, t_end: float = 1000.0, dt: float = 0.1,
                   s2_time: float = 320.0, precision: str = "f32",
-                  amp: Optional[float] = None) -> Workload:
-    """3D TP06 slab with an ischemic ellipsoid, S1 at x=0 and cross-field S2."""
+                  amp: Optional[float] = None, init: str = "rest") -> Workload:
+    """3D TP06 slab with an ischemic ellipsoid, S1 at x=0 and cross-field S2.
+    init "rest": the model's published initial state everywhere; "paced":
+    the paced steady state of normal and of ischemic tissue
+    (tp06_paced_state), the protocol of the paper's tissue runs."""
     thickness = (shape[2] - 1) * dx
     mesh = _slab(shape, dx, D_l, D_t, thickness)
     xyz = mesh.xyz
@@ -396,9 +414,15 @@ def slab_ischemic(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,
     s2n = np.nonzero((xyz[:, 0] <= 0.25 * Lx + 1e-12) &
                      (xyz[:, 1] <= 0.5 * Ly + 1e-12))[0].astype(np.int32)
     s2 = Stimulus(s2n, s2_time, 1.0, a)
+    y0 = None
+    if init == "paced":
+        ps = tp06_paced_state()
+        y0 = np.where(isc[None, :], ps["ischemic"][:, None], ps["normal"][:, None])
+    elif init != "rest":
+        raise ValueError("init must be rest or paced")
     return Workload("slab_tp06_3d_ischemic", mesh, MODEL_TP06, p, [s1, s2], dt,
                     t_end, 0.01, precision, -40.0,
-                    extra={"ischemic_nodes": int(isc.sum())})
+                    extra={"ischemic_nodes": int(isc.sum()), "init": init}, init_state=y0)
 
 
 def slab_ischemic_tets(shape=(201, 201, 51), dx: float = 0.01, D_l: float = 0.0012,

@@ -262,6 +262,20 @@ def test_slab_tp06_fp64_parity(torch, layout):
     assert ((lo > 0) == (lg > 0)).all() and (lo > 0).sum() > 500
 
 
+def test_slab_paced_init_fp64_parity(torch):
+    """Paced steady-state initial states (normal and ischemic tissue)
+    through the same split step."""
+    w = W.slab_ischemic(shape=(23, 19, 11), t_end=25.0, init="paced")
+    w.stimuli = w.stimuli[:1]
+    o, s, levels, nflip = run_pair(torch, w, w.n_steps, every=50)
+    _assert_f64_levels(w, levels)
+    for j in (1, 2, 3, 5, 8, 12):
+        a, b = o.state(j), s.state(j)
+        assert np.abs(a - b).max() <= 1e-9 * max(np.abs(a).max(), 1e-3), j
+    lo, lg = o.get(2), s.get(mono.FIELD_LAT)
+    assert ((lo > 0) == (lg > 0)).all() and (lo > 0).sum() > 500
+
+
 def test_batched_fp64_parity_and_standalone_equality(torch):
     w = W.batched_sheets(n_inst=5, side_lo=20, side_hi=44, t_end=30.0)
     o, s, levels, nflip = run_pair(torch, w, w.n_steps, every=100)
