@@ -47,21 +47,23 @@ struct RowPattern<13> {  // centres 0, nx, nxy-nx, nxy, nxy+nx, then their negat
   __device__ static constexpr int bd(int p) { return p == 0 ? -1 : 1 - (p - 1) % 3; }
 };
 
-// value of the next (d = 1) or previous (d = -1) lane of the wavefront
+// value of the next (d = 1) or previous (d = -1) lane of the wavefront; the
+// lane with no such neighbour reads 0 (bound_ctrl set: no zero-initialised
+// destination needed)
 template <int D, typename T>
 __device__ __forceinline__ T lane_shift(T v) {
   if constexpr (D == 0) {
     return v;
   } else if constexpr (sizeof(T) == 4) {
     const int x = __builtin_amdgcn_update_dpp(0, __float_as_int(v), D > 0 ? 0x130 : 0x138, 0xf,
-                                              0xf, false);
+                                              0xf, true);
     return __int_as_float(x);
   } else {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), D > 0 ? 0x130 : 0x138,
-                                               0xf, 0xf, false);
+                                               0xf, 0xf, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), D > 0 ? 0x130 : 0x138, 0xf,
-                                               0xf, false);
+                                               0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
   }
 }

@@ -312,6 +312,16 @@ __global__ __launch_bounds__(BLOCK) void k_diff_classes(DiffArgs<T> a) {
 // kWaveRows rows; the loads of all groups are issued before any group is
 // computed.
 // ---------------------------------------------------------------------------
+// One potential by a raw buffer load at byte offset off (0 outside the
+// buffer's range).
+template <typename T>
+__device__ __forceinline__ T ld_raw(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 template <typename T, int P, int BLOCK, int ITER>
 __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __restrict__ ctab,
                                                      const int32_t* __restrict__ wcls) {
@@ -345,16 +355,21 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
     for (int k = 1; k < 5; ++k) ctr[4 + k] = -ctr[k];
   }
   // every lane (halo lanes included) loads the centre rows of every group;
-  // all lanes stay active through the shifts
+  // all lanes stay active through the shifts.  Raw buffer loads over the n
+  // potentials: an index outside [0, n) (before the first or past the last
+  // row) reads 0 with no clamp arithmetic; such a value only ever meets a
+  // zero weight (no element joins a row to a node across the grid's ends).
+  const __amdgpu_buffer_rsrc_t vres =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.Vin, (short)0, n * ES, 0x00020000);
+  int cb[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) cb[k] = ctr[k] * ES;
   T vc[ITER][NC];
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
-    const int i = (int)((g0 + it) * WR) + lane - 1;
+    const int ib = ((int)((g0 + it) * WR) + lane - 1) * ES;
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int j = min(max(i + ctr[k], 0), n - 1);
-      vc[it][k] = ld_bytes(a.Vin, (uint32_t)(j * ES));
-    }
+    for (int k = 0; k < NC; ++k) vc[it][k] = ld_raw<T>(vres, ib + cb[k]);
   }
   const double dt_ad = a.dt_ad[0];
   const T hT = (T)dt_ad;
