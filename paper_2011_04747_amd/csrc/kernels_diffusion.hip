@@ -380,14 +380,10 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
     if (g >= ngroups) break;
     const int i = (int)(g * WR) + lane - 1;
     const bool produce = lane >= 1 && lane <= WR && i < n;
-    T vl[NC], vr[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      vl[k] = lane_shift<1>(vc[it][k]);
-      vr[k] = lane_shift<-1>(vc[it][k]);
-    }
+    // the shifts are taken where each neighbour is used (once per path), so
+    // the compiler can fold each into the subtraction that consumes it
     auto pick = [&](int k, int d) -> T {
-      return d > 0 ? vl[k] : (d < 0 ? vr[k] : vc[it][k]);
+      return d > 0 ? lane_shift<1>(vc[it][k]) : (d < 0 ? lane_shift<-1>(vc[it][k]) : vc[it][k]);
     };
     const T vi = vc[it][0];
     T acc = T(0), mv;
