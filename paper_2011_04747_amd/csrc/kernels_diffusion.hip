@@ -171,41 +171,53 @@ __global__ __launch_bounds__(BLOCK) void k_diff_ell(DiffArgs<T> a) {
 // move as RPL-wide vector accesses; the neighbour gathers stay scalar.
 // P = 0 reads the number of offsets at run time.  Padding rows (n <= i < Np)
 // have zero edges, zero 1/m and zero potential, so they are computed as 0.
-template <typename T, int P, bool BATCHED, int BLOCK, int RPL>
+// NARROW: every row index and byte offset within one row array fits 32 bits
+// (Np * sizeof(T) < 2^31), so indices are 32-bit and the loads take a
+// uniform base plus a 32-bit offset (no 64-bit address arithmetic per
+// neighbour).  Same loads, clamps and sums either way.
+template <typename T, int P, bool BATCHED, int BLOCK, int RPL, bool NARROW>
 __global__ __launch_bounds__(BLOCK) void k_diff_stencil(DiffArgs<T> a) {
+  using I = typename std::conditional<NARROW, int, int64_t>::type;
   const int64_t nlanes = (a.n + RPL - 1) / RPL;
   const int64_t nb = (nlanes + BLOCK - 1) / BLOCK;
   const int64_t lane = row_block(nb, a.xcd) * BLOCK + threadIdx.x;
-  const int64_t i0 = lane * RPL;
-  if (i0 >= a.n) return;
+  if (lane * RPL >= a.n) return;
+  const I i0 = (I)(lane * RPL);
   const int np = P > 0 ? P : a.P;
-  const int64_t last = a.n - 1;
+  const I last = (I)(a.n - 1);
+  auto ld = [](const T* base, I j) -> T {
+    if constexpr (NARROW)
+      return ld_bytes(base, (uint32_t)j * (uint32_t)sizeof(T));
+    else
+      return base[j];
+  };
   T vi[RPL], acc[RPL];
   vload<RPL>(a.Vin + i0, vi);
   int q[RPL];
-  int64_t first[RPL];
+  I first[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
     q[r] = BATCHED ? a.inst[i0 + r] : 0;
-    first[r] = BATCHED ? a.inst_off[q[r]] : 0;
+    first[r] = BATCHED ? (I)a.inst_off[q[r]] : I(0);
     acc[r] = T(0);
   }
   auto edge = [&](int p) {
+    const T* ep = a.e + (int64_t)p * a.Np;
     T wf[RPL];
-    vload<RPL>(a.e + (int64_t)p * a.Np + i0, wf);
+    vload<RPL>(ep + i0, wf);
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-      const int64_t i = i0 + r;
-      const int64_t o = a.off[(int64_t)q[r] * np + p];
-      const int64_t jf = i + o;
-      const int64_t jb = i - o;
-      const int64_t jbc = jb >= first[r] ? jb : first[r];
+      const I i = i0 + r;
+      const I o = (I)a.off[q[r] * np + p];
+      const I jf = i + o;
+      const I jb = i - o;
+      const I jbc = jb >= first[r] ? jb : first[r];
       // loaded unconditionally (jbc is always a row of this instance), so
       // that no branch holds the slots' loads apart
-      const T wbl = a.e[(int64_t)p * a.Np + jbc];
+      const T wbl = ld(ep, jbc);
       const T wb = (jb >= first[r]) ? wbl : T(0);
-      const T vf = a.Vin[jf <= last ? jf : last];
-      const T vb = a.Vin[jbc];
+      const T vf = ld(a.Vin, jf <= last ? jf : last);
+      const T vb = ld(a.Vin, jbc);
       acc[r] += wf[r] * (vf - vi[r]);
       acc[r] += wb * (vb - vi[r]);
     }
@@ -220,7 +232,7 @@ __global__ __launch_bounds__(BLOCK) void k_diff_stencil(DiffArgs<T> a) {
   vload<RPL>(a.minv + i0, mv);
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    const int64_t i = i0 + r;
+    const int64_t i = (int64_t)i0 + r;
     if (BATCHED && a.m >= a.l[q[r]]) {
       out[r] = vi[r];
       continue;
@@ -462,7 +474,10 @@ template <typename T, int P, bool BATCHED, int BLOCK, int RPL>
 static void launch_stencil_k(const DiffArgs<T>& a, hipStream_t s) {
   const int64_t nlanes = (a.n + RPL - 1) / RPL;
   const dim3 grid((unsigned)((nlanes + BLOCK - 1) / BLOCK));
-  launch_step_kernel(k_diff_stencil<T, P, BATCHED, BLOCK, RPL>, grid, dim3(BLOCK), s, a);
+  if (a.Np * (int64_t)sizeof(T) < (int64_t(1) << 31))
+    launch_step_kernel(k_diff_stencil<T, P, BATCHED, BLOCK, RPL, true>, grid, dim3(BLOCK), s, a);
+  else
+    launch_step_kernel(k_diff_stencil<T, P, BATCHED, BLOCK, RPL, false>, grid, dim3(BLOCK), s, a);
 }
 
 template <typename T, int P, bool BATCHED, int BLOCK>
