@@ -133,11 +133,13 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t i, T* 
 // key), and lane t then advances the t-th node of that order, so a wavefront
 // mixes substep counts only where two keys meet.  Each node's arithmetic is
 // the same either way, so both give the same bits.
-// Occupancy floor for the register allocator: 7 wavefronts per SIMD (at most
-// 72 registers) for FP32, where the TP06 substep fits without spilling; no
-// floor in FP64.
+// Occupancy floor for the register allocator: 8 wavefronts per SIMD (at most
+// 64 registers) for FP32, so that four 512-lane workgroups fill a compute
+// unit; the TP06 substep then spills a few values outside its loop, which
+// costs less than the fourth workgroup gains (7 per SIMD, 72 registers, no
+// spill, fits only three).  No floor in FP64.
 template <typename T>
-constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 7 : 1;
+constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 8 : 1;
 
 template <typename T, class M, int BLOCK, bool SORT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kIonWavesPerEU<T>)))
