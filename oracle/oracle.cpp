@@ -833,6 +833,8 @@ void reaction(Sim* s, int64_t nstep) {
 // Jacobian of one substep at (y, p): J[i][j] = d y'_i / d (y_j for j < S,
 // p_{j-S} for j >= S), by forward-mode derivatives through the model code.
 constexpr int kJac = 26;   // 19 states + 7 parameters (TP06 with cell types), the largest model
+constexpr int kMaxStates = 19, kMaxParams = 7;
+static_assert(kJac >= kMaxStates + kMaxParams, "Jacobian width must hold every model's states and parameters");
 void substep_jacobian(int model, const double* y, const double* p, double h, int S, int P,
                       double* J) {
   DualN<kJac> yd[19], pd[8];
@@ -1237,7 +1239,7 @@ int orc_backward(void* h, double* grad_sigma, double* grad_params) {
     for (int64_t i = 0; i < n; ++i) {
       const int k = s->tape_k[t * n + i];
       const double hsub = s->dt / k;
-      double p[8], J[19 * 25], li[19];
+      double p[8], J[kMaxStates * kJac], li[kMaxStates];
       std::vector<double> ys((size_t)k * S);   // substep start states
       for (int b = 0; b < P; ++b) p[b] = s->params[(int64_t)b * n + i];
       for (int a = 0; a < S; ++a) ys[a] = entry[(int64_t)a * n + i];

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB selects another build of the same source (the sanitizer build)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 F_V, F_VPREV, F_LAT, F_K, F_STATE0 = 0, 1, 2, 3, 16
 DAETI, OSTAR, OST = 0, 1, 2
