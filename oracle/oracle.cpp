@@ -1317,6 +1317,11 @@ int orc_reaction_nodes(void* h, int64_t nstep, int64_t nrows, const int64_t* row
 }
 
 // --- cell-level helpers ------------------------------------------------------
+// The instantaneous-buffering maps of TP06's calcium pools, exposed so that
+// the free-from-total root can be checked against its defining relation.
+double orc_free_from_total(double total, double B, double K) { return free_from_total(total, B, K); }
+double orc_total_from_free(double c, double B, double K) { return total_from_free(c, B, K); }
+
 int orc_model_nstates(int model) { return model_nstates(model); }
 int orc_model_nparams(int model) { return model_nparams(model); }
 

@@ -59,6 +59,9 @@ def lib():
         L.orc_set_vclamp.argtypes = [vp, C.c_int]
         L.orc_model_nstates.argtypes = [C.c_int]
         L.orc_model_nparams.argtypes = [C.c_int]
+        for f in (L.orc_free_from_total, L.orc_total_from_free):
+            f.restype = C.c_double
+            f.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_model_init.argtypes = [C.c_int, _dp]
         L.orc_cell_advance.argtypes = [C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int]
         L.orc_cell_rates.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _ip]
@@ -315,6 +318,15 @@ def tp06_currents(params, y):
     out = np.zeros(17)
     _check(lib().orc_tp06_currents(_f64(params), _f64(y), out))
     return dict(zip(TP06_CURRENTS, out))
+
+
+def buffer_free_from_total(total, B, K):
+    """Free concentration of an instantaneously buffered pool (TP06 calcium)."""
+    return lib().orc_free_from_total(float(total), float(B), float(K))
+
+
+def buffer_total_from_free(c, B, K):
+    return lib().orc_total_from_free(float(c), float(B), float(K))
 
 
 def k_rule(dvdt, k_max):
