@@ -65,12 +65,17 @@ def _traffic(kernel, workload, launch):
     return t["bytes_per_launch"]
 
 
-def full_run(w, stream, launch, layout):
+LEVEL_EVERY = 1000     # outer steps between compared levels of the whole run (100 ms)
+
+
+def full_run(w, stream, launch, layout, with_accuracy):
     """The workload's whole simulated interval from t = 0 (every phase: the
     S1 front crossing resting tissue, plateau, repolarisation, S2 and
     re-entry), graph-replayed and timed with HIP events on the simulation's
     stream; then the same run again with the substep statistics on for the
-    mean k and the wavefront efficiency of the reaction."""
+    mean k and the wavefront efficiency of the reaction, stopping every
+    100 ms to read the potential; and (with_accuracy) the same levels from
+    the FP64 path for the accuracy of the FP32 run over the whole interval."""
     import torch
     from paper_2011_04747_amd import mono
     steps = w.n_steps
@@ -87,22 +92,185 @@ def full_run(w, stream, launch, layout):
     ms = ev0.elapsed_time(ev1)
     lat = sim.get(mono.FIELD_LAT)
     sim.close()
-    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
-    sim.set_launch(**launch)
+    marks = list(range(LEVEL_EVERY, steps + 1, LEVEL_EVERY))
+    if not marks or marks[-1] != steps:
+        marks.append(steps)
+
+    def levels(prec, stats):
+        sm = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream, layout=layout)
+        if prec == "f32":
+            sm.set_launch(**launch)
+        if stats:
+            sm.stats_enable(True)
+        out, done = [], 0
+        for m in marks:
+            sm.step(m - done, w.dt)
+            done = m
+            out.append(sm.get(mono.FIELD_V))
+        st = sm.stats() if stats else None
+        lt = sm.get(mono.FIELD_LAT)
+        sm.close()
+        return out, lt, st
+
+    v32, lat32, (ksum, kwave, node_steps, ksat) = levels("f32", True)
+    res = {"level_run_equals_timed_run": bool(np.array_equal(lat32, lat)), "steps": steps, "simulated_ms": steps * w.dt, "ms": ms,
+           "node_updates_per_s": w.mesh.n_nodes * steps / (ms * 1e-3),
+           "mean_k": ksum / max(1, node_steps), "wave_efficiency": ksum / max(1, kwave),
+           "k_at_kmax_frac": ksat / max(1, node_steps),
+           "activated_frac": float((lat >= 0).mean())}
+    if with_accuracy:
+        v64, lat64, _ = levels("f64", False)
+        rms = [float(np.sqrt(np.mean((a - b) ** 2))) for a, b in zip(v32, v64)]
+        pre = [r for m, r in zip(marks, rms) if m * w.dt <= 300.0 + 1e-9]
+        both = (lat32 >= 0) & (lat64 >= 0)
+        res["accuracy"] = {
+            "reference": "FP64 path of the same kernels over the same run (FP64 parity with the "
+                         "oracle is tested on this slab's geometry at dx 0.05 cm over 0-350 ms)",
+            "levels_ms": [m * w.dt for m in marks],
+            "v_rms_mV_per_level": rms,
+            "v_rms_mV_0_300ms": float(np.sqrt(np.mean(np.square(pre)))) if pre else None,
+            "v_rms_mV_whole_run": float(np.sqrt(np.mean(np.square(rms)))),
+            "v_max_mV_whole_run": float(max(np.abs(a - b).max() for a, b in zip(v32, v64))),
+            "lat_max_ms": float(np.abs(lat32 - lat64)[both].max()) if both.any() else None,
+            "activated_equal": bool(((lat32 >= 0) == (lat64 >= 0)).all())}
+    return res
+
+
+def time_window(w, prec, stream, steps, warmup, repeats, layout, tune):
+    """K outer steps after W warm-up steps of workload w in precision prec,
+    graph-replayed and timed with events on the simulation's stream `repeats`
+    times from the same state (median); then the same window once more with
+    the substep statistics on (mean k), and the diffusion substep timed in a
+    graph of back-to-back substeps."""
+    import torch
+    from paper_2011_04747_amd import mono
+    sim = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream, layout=layout)
+    sim.step(warmup, w.dt)
+    launch = sim.launch()
+    if tune and prec == "f32":
+        from paper_2011_04747_amd import autotune
+        launch = autotune.tune(sim, w.dt)
+    sim.step(steps, w.dt, flags=mono.STEP_CAPTURE)
+    info = sim.info()
+    fields = [mono.FIELD_VPREV, mono.FIELD_LAT] + \
+        [mono.FIELD_STATE0 + j for j in range(info["n_states"])]
+    snap = (info["step"], {f: sim.get(f) for f in fields})
+
+    def restore():
+        for f, v in snap[1].items():
+            sim.set(f, v)
+        sim.set_time_level(snap[0])
+
+    times = []
+    for r in range(max(1, repeats)):
+        if r:
+            restore()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sim.step(steps, w.dt)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    ms = sorted(times)[len(times) // 2]
+    restore()
     sim.stats_enable(True)
     sim.step(steps, w.dt)
-    ksum, kwave, node_steps, ksat = sim.stats()
+    ksum, _, node_steps, _ = sim.stats()
+    sim.stats_enable(False)
+    L = max(sim.info(q)["l"] for q in range(info["n_instances"]))
+    d_us = 1e3 * sim.time_diffusion(64 * 2 * L)
     sim.close()
-    return {"steps": steps, "simulated_ms": steps * w.dt, "ms": ms,
-            "node_updates_per_s": w.mesh.n_nodes * steps / (ms * 1e-3),
-            "mean_k": ksum / max(1, node_steps), "wave_efficiency": ksum / max(1, kwave),
-            "k_at_kmax_frac": ksat / max(1, node_steps),
-            "activated_frac": float((lat >= 0).mean())}
+    n = w.mesh.n_nodes
+    return {"ms": ms, "repeats_ms": times, "node_updates_per_s": n * steps / (ms * 1e-3),
+            "ms_per_step": ms / steps, "mean_k": ksum / max(1, node_steps),
+            "substeps_per_step": ksum / steps, "diffusion_us": d_us, "L": L,
+            "reaction_us": 1e3 * ms / steps - 2 * L * d_us, "info": info, "launch": launch}
+
+
+def _diff_row_bytes(info, launch, es):
+    """Algorithmic HBM bytes per row of one diffusion substep (value size es)."""
+    from paper_2011_04747_amd import mono
+    P = info["ell_width"]
+    by_class = (info["layout"] == mono.LAYOUT_STENCIL and info["row_classes"] > 0
+                and launch.get("diff_classes", 1))
+    if by_class:
+        b = 2 * es + 2                 # V in, V out, class id
+    elif info["layout"] == mono.LAYOUT_STENCIL:
+        b = (P + 3) * es               # own edges, 1/m, V in, V out
+    else:
+        b = P * (es + 4) + 2 * es      # (value, column) per slot, V in, V out
+    if info["n_instances"] > 1:
+        b += 4                         # instance id of the row
+    return b
+
+
+def _model_ops():
+    """Operation count of one TP06 substep at the library's initial state."""
+    from paper_2011_04747_amd import mono
+    from paper_2011_04747_amd import workloads as W
+    tiny = mono.Sim.from_workload(W.sheet_tp06(n=2, t_end=0.1), "f64")
+    rest = [float(tiny.get(mono.FIELD_STATE0 + j)[0]) for j in range(tiny.info()["n_states"])]
+    tiny.close()
+    ops = mono.model_flops(W.MODEL_TP06, rest, W.TP06_PARAM_DEFAULT)
+    return ops, ops["add"] + ops["mul"] + ops["div"] + ops["exp"] + ops["log"] + ops["sqrt"]
+
+
+def other_leg(kind, w, prec, stream, args, layout, name):
+    """Throughput of another workload (or precision) over the same window,
+    with the roofline of its diffusion and reaction kernels."""
+    r = time_window(w, prec, stream, args.steps, args.warmup, 3, layout, not args.no_tune)
+    info, launch = r["info"], r["launch"]
+    es = 8 if prec == "f64" else 4
+    row_b = _diff_row_bytes(info, launch, es)
+    _, f_model = _model_ops()
+    flops = r["substeps_per_step"] * f_model
+    peak = FP64_VECTOR_PEAK_TFLOPS if prec == "f64" else FP32_VECTOR_PEAK_TFLOPS
+    out = {"workload": name, "dtype": prec, "nodes": w.mesh.n_nodes, "steps": args.steps,
+           "warmup": args.warmup, "value": r["node_updates_per_s"], "unit": "node-updates/s",
+           "ms_per_step": r["ms_per_step"], "repeats_ms": r["repeats_ms"], "launch": launch,
+           "l": r["L"], "mean_k": r["mean_k"],
+           "diffusion": {"avg_us": r["diffusion_us"], "bytes_per_row": row_b,
+                         "achieved_GBs": w.mesh.n_nodes * row_b / (r["diffusion_us"] * 1e-6) / 1e9,
+                         "frac_hbm": w.mesh.n_nodes * row_b / (r["diffusion_us"] * 1e-6) / 1e9
+                         / HBM_PEAK_GBS,
+                         "ms_per_step": 2 * r["L"] * r["diffusion_us"] * 1e-3},
+           "reaction": {"avg_us": r["reaction_us"],
+                        "achieved_TFLOPs": flops / (r["reaction_us"] * 1e-6) / 1e12,
+                        "peak_TFLOPs": peak,
+                        "frac": flops / (r["reaction_us"] * 1e-6) / 1e12 / peak}}
+    return out
+
+
+def _host_cpu():
+    """CPU model, physical cores and logical CPUs of this host (lscpu)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    def num(k):
+        try:
+            return int(info.get(k, ""))
+        except ValueError:
+            return None
+    cores = (num("Core(s) per socket") or 0) * (num("Socket(s)") or 0) or None
+    return {"cpu_model": info.get("Model name"), "physical_cores": cores,
+            "logical_cpus": num("CPU(s)"), "affinity_cpus": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(w, steps, steps_1t):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the workload:
-    `steps` outer steps on all threads, then `steps_1t` more on one thread."""
+    `steps` outer steps on all threads, then `steps_1t` more on one thread.
+    The oracle is compiled -O3 -march=native for this host first."""
+    from oracle import build as oracle_build
+    from oracle import oracle as oracle_mod
+    oracle_mod.use_library(oracle_build.build_native())
     from oracle.oracle import Oracle, get_threads, set_threads
     o = Oracle.from_workload(w)
     o.prepare(w.dt)
@@ -113,7 +281,8 @@ def cpu_baseline(w, steps, steps_1t):
     out = {"value": w.mesh.n_nodes * steps / el, "unit": "node-updates/s", "cores": threads,
            "kind": "oracle",
            "sample": f"full {w.mesh.n_nodes}-node slab, FP64, first {steps} outer steps "
-                     f"from t=0 (assembly excluded), {el:.1f} s"}
+                     f"from t=0 (assembly excluded), {el:.1f} s, {threads} OpenMP threads",
+           "build": "g++ -O3 -march=native -ffp-contract=off -fopenmp", "host": _host_cpu()}
     if steps_1t > 0:
         set_threads(1)
         t0 = time.perf_counter()
@@ -155,17 +324,23 @@ def adjoint_leg(stream, with_accuracy, tune=True):
         launch = autotune.tune(s, w.dt)
         s.close()
 
-    def run(prec, taped, ktrace=None):
+    def run(prec, taped, ktrace=None, sched=("uniform", 0), round_init=False):
         s = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream)
         if launch and prec == "f32":
             s.set_launch(**launch)
         s.set_sensors(w.sensors, target)
+        if round_init:
+            # the FP32 run's initial state (every value rounded to FP32), in FP64
+            for j in range(s.info()["n_states"]):
+                s.set(mono.FIELD_STATE0 + j,
+                      s.get(mono.FIELD_STATE0 + j).astype(np.float32).astype(np.float64))
         if ktrace is not None:
             mode, buf = ktrace
             if mode == 1:
                 s.ktrace(1, buf.data_ptr(), None, n_steps, 0)
             else:
                 s.ktrace(2, None, buf.data_ptr(), n_steps, 0)
+        s.set_checkpointing(*sched)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if not taped:
@@ -177,32 +352,64 @@ def adjoint_leg(stream, with_accuracy, tune=True):
             t1 = time.perf_counter()
             gs, gp = s.backward()
             t2 = time.perf_counter()
-            out = (t1 - t0, t2 - t1, loss, gs, gp)
+            out = (t1 - t0, t2 - t1, loss, gs, gp, s.checkpoint_info())
         s.close()
         return out
 
     run("f32", False)                      # warm-up (graph capture, code load)
     t_fwd = run("f32", False)[0]
-    t_tf, t_bw, loss, gs, gp = run("f32", True)
+    t_tf, t_bw, loss, gs, gp, ci = run("f32", True)
+    names = ("gNa", "gCaL", "gKr", "gKs", "gK1")
     res = {"workload": f"adjoint_tp06_3d 101x101x26 ({w.mesh.n_nodes} nodes), {ns} sensors, "
                        f"{n_steps} steps, checkpoint every {ck}, FP32",
            "launch": launch, "forward_s": t_fwd, "taped_forward_s": t_tf, "backward_s": t_bw,
            "adjoint_over_forward": (t_tf + t_bw) / t_fwd, "loss": loss,
            "grad_sigma_l2": float(np.linalg.norm(gs)),
-           "grad_scalings": {k: float(gp[i]) for i, k in
-                             enumerate(("gNa", "gCaL", "gKr", "gKs", "gK1"), start=1)}}
+           "grad_scalings": {k: float(gp[i]) for i, k in enumerate(names, start=1)},
+           "checkpointing": {"uniform": {"snapshots": ci["snapshots"],
+                                         "snapshot_MB": ci["snapshot_bytes"] / 1e6,
+                                         "tape_MB": ci["tape_bytes"] / 1e6,
+                                         "segment_advances": ci["advances"]}}}
+    # binomial checkpointing in a few snapshot buffers: same gradients,
+    # less memory, forward advances in the reverse sweep
+    for slots in (8, 3):
+        tb_tf, tb_bw, lb, gsb, gpb, cib = run("f32", True, sched=("binomial", slots))
+        res["checkpointing"][f"binomial_{slots}"] = {
+            "snapshots": cib["snapshots"], "snapshot_MB": cib["snapshot_bytes"] / 1e6,
+            "tape_MB": cib["tape_bytes"] / 1e6, "segment_advances": cib["advances"],
+            "taped_forward_s": tb_tf, "backward_s": tb_bw,
+            "adjoint_over_forward": (tb_tf + tb_bw) / t_fwd,
+            "gradients_equal_uniform": bool(lb == loss and np.array_equal(gsb, gs)
+                                            and np.array_equal(gpb, gp))}
     if with_accuracy:
         # same k decisions in both precisions: record the FP32 run's, replay in FP64
         kt = torch.zeros((n_steps, w.mesh.n_nodes), dtype=torch.uint8, device="cuda")
-        _, _, loss, gs, gp = run("f32", True, (1, kt))
-        _, _, loss64, gs64, gp64 = run("f64", True, (2, kt))
+        _, _, loss, gs, gp, _ = run("f32", True, (1, kt))
+        _, _, loss64, gs64, gp64, _ = run("f64", True, (2, kt))
+        # conditioning: the FP64 adjoint from the FP32-rounded initial state
+        _, _, loss64r, gs64r, gp64r, _ = run("f64", True, (2, kt), round_init=True)
         del kt
+
+        def rel(a, b):
+            return {k: float(abs(a[i] - b[i]) / abs(b[i])) for i, k in enumerate(names, start=1)}
         res["fp32_vs_fp64"] = {
             "note": "FP64 adjoint of the same kernels replaying the FP32 run's k decisions",
             "grad_sigma_cosine": float(np.dot(gs, gs64) / (np.linalg.norm(gs) * np.linalg.norm(gs64))),
             "grad_sigma_rel_l2": float(np.linalg.norm(gs - gs64) / np.linalg.norm(gs64)),
             "grad_scalings_max_rel": float(np.max(np.abs(gp[1:] - gp64[1:]) / np.abs(gp64[1:]).max())),
+            "grad_scalings_rel": rel(gp, gp64),
+            "grad_scalings_cosine": float(np.dot(gp[1:], gp64[1:]) /
+                                          (np.linalg.norm(gp[1:]) * np.linalg.norm(gp64[1:]))),
             "loss_rel": float(abs(loss - loss64) / loss64)}
+        res["fp64_conditioning"] = {
+            "note": "FP64 adjoint from the initial state rounded to FP32 against FP64 from the "
+                    "exact one (same k decisions): the change an FP32-sized perturbation of the "
+                    "input alone makes",
+            "grad_scalings_max_rel": float(np.max(np.abs(gp64r[1:] - gp64[1:]) /
+                                                  np.abs(gp64[1:]).max())),
+            "grad_scalings_rel": rel(gp64r, gp64),
+            "grad_sigma_rel_l2": float(np.linalg.norm(gs64r - gs64) / np.linalg.norm(gs64)),
+            "loss_rel": float(abs(loss64r - loss64) / loss64)}
     return res
 
 
@@ -226,6 +433,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-full-run", action="store_true",
                     help="skip timing the workload's whole simulated interval")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the FP64, batched and tetrahedral windows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -411,11 +620,29 @@ def main():
 
     full = None
     if not args.no_full_run and args.workload == "slab":
-        full = full_run(w, stream, launch, layout)
+        full = full_run(w, stream, launch, layout, not args.no_accuracy)
 
     adjoint = None
     if not args.no_adjoint and args.workload == "slab":
         adjoint = adjoint_leg(stream, not args.no_accuracy, not args.no_tune)
+
+    # the same window in FP64, and the batched and tetrahedral workloads
+    legs = None
+    if not args.no_legs and args.workload == "slab":
+        legs = {}
+        legs["fp64"] = other_leg("fp64", w, "f64", stream, args, layout,
+                                 wl_name + ", FP64 state and operator")
+        wb = W.batched_sheets(precision="f32")
+        legs["batched"] = other_leg("batched", wb, "f32", stream, args, mono.LAYOUT_AUTO,
+                                    f"batched_tp06_2d: 64 sheets, sides U{{50..400}} seed 4, "
+                                    f"{wb.mesh.n_nodes} nodes, log-normal sigma, dt=0.1 ms")
+        del wb
+        wt = W.slab_ischemic_tets(precision="f32", order="rcm")
+        legs["tets"] = other_leg("tets", wt, "f32", stream, args, mono.LAYOUT_AUTO,
+                                 "slab_tp06_3d_ischemic_tets 201x201x51 (2,060,451 nodes, "
+                                 f"{wt.mesh.n_elems:,} linear tetrahedra), RCM node order, "
+                                 "dt=0.1 ms, S1+S2")
+        del wt
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -439,7 +666,7 @@ def main():
            "roofline": roofline,
            "kernels": {"diffusion": diff_roof, "reaction": react_roof,
                        "ms_per_step": {"diffusion": diff_total, "reaction": react_total}},
-           "accuracy": accuracy, "adjoint": adjoint, "cpu_baseline": cpu}
+           "accuracy": accuracy, "adjoint": adjoint, "legs": legs, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -338,12 +338,40 @@ mono_status mono_set_sensors(mono_sim *sim, int32_t n, const int32_t *nodes, con
 mono_status mono_sample_sensors(mono_sim *sim, int64_t n_steps, double dt, double *out);
 
 /* Advance n_steps outer steps from the current time level like mono_step,
- * keeping a snapshot of the state every ckpt_every steps (uniform
- * checkpointing: memory ~ (n_steps/ckpt_every) states plus a ckpt_every-step
- * tape), and return the loss (FP64).  Synchronising.  Needs k_max <= 16.
- * EUNSUPPORTED with a clamped potential. */
+ * keeping snapshots of the state at segment starts (segments of ckpt_every
+ * steps), and return the loss (FP64).  Synchronising.  Needs k_max <= 16.
+ * EUNSUPPORTED with a clamped potential.  Memory: the snapshots (see
+ * mono_set_checkpointing) plus a tape of one segment (ckpt_every steps of
+ * diffusion inputs, reaction-entry states and substep counts). */
 mono_status mono_forward_taped(mono_sim *sim, int64_t n_steps, double dt, int32_t ckpt_every,
                                double *loss);
+
+/* Checkpoint schedule of the next mono_forward_taped (not in the paper,
+ * which has no adjoint: the reverse sweep needs the state at the start of
+ * every segment it reverses).
+ *  MONO_CKPT_UNIFORM (default): a snapshot at every segment start; the
+ *      reverse sweep recomputes each segment once (for its tape).
+ *  MONO_CKPT_BINOMIAL: at most max_snapshots (>= 2) snapshot buffers, the
+ *      run's start included; states in between are recomputed by forward
+ *      advances of whole segments from an earlier snapshot, in the order
+ *      that minimises the number of advances over recursive splits
+ *      (binomial checkpointing, Griewank & Walther's revolve).  Gradients
+ *      are bitwise those of the uniform schedule: every segment is reversed
+ *      from the same state, in the same order.
+ * EINVAL for another schedule or fewer than 2 snapshots. */
+enum { MONO_CKPT_UNIFORM = 0, MONO_CKPT_BINOMIAL = 1 };
+mono_status mono_set_checkpointing(mono_sim *sim, int32_t schedule, int32_t max_snapshots);
+
+/* Figures of the last taped run's schedule into out[6]: {schedule, snapshot
+ * buffers, segments, whole-segment forward advances of the last
+ * mono_backward, snapshot bytes, segment tape bytes}.  ESTATE before a taped
+ * run. */
+mono_status mono_checkpoint_info(mono_sim *sim, int64_t *out);
+
+/* The number of whole-segment forward advances the binomial plan needs to
+ * reverse n_segments with max_snapshots buffers (host only, no device).
+ * EINVAL for fewer than 2 buffers when n_segments > 1. */
+mono_status mono_checkpoint_plan(int64_t n_segments, int32_t max_snapshots, int64_t *advances);
 
 /* Gradient of the last taped run's loss by a reverse sweep that recomputes
  * each segment from its checkpoint (the k each node took and l are held
@@ -358,7 +386,9 @@ mono_status mono_backward(mono_sim *sim, double *grad_sigma, double *grad_params
 /* Test hooks.  `what`:
  *  MONO_DEBUG_KTRACE: arg -> mono_ktrace (device buffers n_steps x n_nodes,
  *      uint8, row = step - base_step): record the k each node picks and/or
- *      replay k from a given trace instead of the rule.
+ *      replay k from a given trace instead of the rule.  A replayed entry is
+ *      clamped to [1, k_max] (and recorded as clamped in MONO_FIELD_K and in
+ *      the adjoint's tape); steps outside the trace use the rule.
  *  MONO_DEBUG_VCLAMP: arg -> int32 (1 = the reaction leaves V unchanged).
  *  MONO_DEBUG_FORCE_L: arg -> int32 (l override for every instance, 0 = off).
  *  MONO_DEBUG_STATS: arg -> int64[4] {sum of k over nodes and steps, sum over

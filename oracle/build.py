@@ -4,8 +4,14 @@
 UndefinedBehaviorSanitizer into oracle/liboracle_san.so instead; the tests
 load it in a child process with the sanitizer runtimes preloaded (see
 `sanitizer_env`) and `ORACLE_LIB` pointing at it.
+
+`build_native()` builds it with -march=native for the host it runs on (the
+CPU baseline times that build), into a file named for the host's CPU so a
+build made on one machine is never loaded on another.
 """
+import hashlib
 import os
+import platform
 import subprocess
 import sys
 
@@ -14,16 +20,46 @@ SRC = os.path.join(HERE, "oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 LIB_SAN = os.path.join(HERE, "liboracle_san.so")
 
-# -O3 -march=native: the CPU baseline times this build on the host it runs on.
-# -ffp-contract=off keeps every multiply and add separately rounded, as written.
-OPT = ["-O3", "-march=native"]
+# The checker build targets a baseline x86-64 so that it loads on any host the
+# tests run on; the timed build adds -march=native on its own host.
+# -ffp-contract=off keeps every multiply and add separately rounded, as written
+# (so both builds give the same bits).
+OPT = ["-O3", "-march=x86-64-v2"]
+OPT_NATIVE = ["-O3", "-march=native"]
 SAN = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
        "-fno-sanitize-recover=all"]
 
 
-def build(verbose: bool = False, sanitize: bool = False) -> str:
-    out = LIB_SAN if sanitize else LIB
-    cmd = (["g++"] + (SAN if sanitize else OPT) +
+def _cpu_tag() -> str:
+    """Short fingerprint of this host's CPU model and instruction-set flags."""
+    model, flags = platform.processor(), ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and not model:
+                    model = line.split(":", 1)[1].strip()
+                if line.startswith("flags"):
+                    flags = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return hashlib.sha256((model + "|" + flags).encode()).hexdigest()[:12]
+
+
+def native_lib_path() -> str:
+    return os.path.join(HERE, f"liboracle_native_{_cpu_tag()}.so")
+
+
+def build_native(verbose: bool = False) -> str:
+    """-O3 -march=native build for this host (built once per CPU, then reused)."""
+    out = native_lib_path()
+    if not os.path.exists(out):
+        _compile(OPT_NATIVE, out, verbose)
+    return out
+
+
+def _compile(flags, out, verbose):
+    cmd = (["g++"] + flags +
            ["-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
             "-o", out + ".tmp", SRC])
     if verbose:
@@ -31,6 +67,10 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    return _compile(SAN if sanitize else OPT, LIB_SAN if sanitize else LIB, verbose)
 
 
 def sanitizer_env(base=None) -> dict:

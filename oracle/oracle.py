@@ -26,6 +26,14 @@ _lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _bp = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
 
 
+def use_library(path):
+    """Load another build of the same source (before the first call)."""
+    global LIB_PATH
+    if _lib is not None and os.path.abspath(path) != os.path.abspath(LIB_PATH):
+        raise RuntimeError("the oracle library is already loaded from " + LIB_PATH)
+    LIB_PATH = path
+
+
 def lib():
     global _lib
     if _lib is None:

@@ -34,7 +34,16 @@ class AdjointProblem:
         self.precision = precision
         self.stream = stream
         # optional device uint8 tensor (n_steps x n_nodes): hold the reaction
-        # substep counts to a given trace (for comparisons at fixed decisions)
+        # substep counts to a given trace (for comparisons at fixed decisions);
+        # the library clamps each entry to [1, k_max]
+        if replay_k is not None:
+            n = w.mesh.n_nodes
+            if (getattr(replay_k, "dtype", None) is None or str(replay_k.dtype) != "torch.uint8"
+                    or not replay_k.is_cuda or not replay_k.is_contiguous()
+                    or replay_k.dim() != 2 or replay_k.shape[0] < self.n_steps
+                    or replay_k.shape[1] != n):
+                raise ValueError(f"replay_k must be a contiguous uint8 CUDA tensor of shape "
+                                 f"(>= {self.n_steps}, {n})")
         self.replay_k = replay_k
         self.sim = None
 

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmono.so")
-SOURCES = ["assembly.cpp", "flops.cpp", "kernels_diffusion.hip", "kernels_ionic.hip",
+SOURCES = ["assembly.cpp", "checkpoint_plan.cpp", "flops.cpp", "kernels_diffusion.hip", "kernels_ionic.hip",
            "kernels_adjoint.hip", "runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

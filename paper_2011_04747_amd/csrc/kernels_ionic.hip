@@ -99,8 +99,11 @@ __device__ __forceinline__ int decide_k(const IonArgs<T>& a, int64_t i, int64_t 
     if (r >= 0 && r < a.kt.rec_steps) a.kt.rec[r * a.n + i] = (uint8_t)k;
   }
   if (a.kt.mode & 2) {
+    // a replayed count is clamped to [1, k_max] like a decided one (a trace
+    // entry of 0 would give h = dt/0, and the adjoint replays at most k_max
+    // substeps per node)
     const int64_t r = step - a.kt.rep_base;
-    if (r >= 0 && r < a.kt.rep_steps) k = a.kt.rep[r * a.n + i];
+    if (r >= 0 && r < a.kt.rep_steps) k = min(max((int)a.kt.rep[r * a.n + i], 1), a.k_max);
   }
   a.lastk[i] = (uint8_t)k;
   return k;

@@ -10,9 +10,11 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
+#include "checkpoint_plan.h"
 #include "mono_internal.h"
 
 using namespace mono;
@@ -179,7 +181,12 @@ struct mono_sim {
   bool taped = false;
   int64_t tape_step0 = 0, tape_steps = 0;
   int ckpt_every = 0;
-  std::vector<void*> d_ckpt;       // state snapshots at segment starts
+  // checkpoint schedule of the next taped run: uniform (a snapshot at every
+  // segment start) or binomial within ckpt_max_slots snapshot buffers
+  int ckpt_schedule = MONO_CKPT_UNIFORM, ckpt_max_slots = 0;
+  CkptPlan plan;                   // the binomial plan of the taped run
+  int64_t ckpt_advances = 0;       // segment advances of the last reverse sweep
+  std::vector<void*> d_ckpt;       // state snapshots (segment starts)
   void* d_final = nullptr;         // state after the taped run
   void* d_seg_vsub = nullptr;      // ckpt_every x 2 l_max x Np
   void* d_seg_entry = nullptr;     // ckpt_every x S x Np
@@ -700,16 +707,24 @@ SensorArgs sensor_args(mono_sim* s, int64_t g) {
 }
 
 // One outer step with clock offset g that also stores the loss at reaction
-// entry (loss) and/or samples the sensors there (sample).
+// entry (loss) and/or samples the sensors there (sample).  recompute: a
+// repeat of a step already taken (checkpoint advances of the reverse sweep),
+// which leaves the APD trackers and the k statistics alone.
 template <typename T>
-void enqueue_loss_step(mono_sim* s, int64_t g, bool loss, double* sample = nullptr) {
+void enqueue_loss_step(mono_sim* s, int64_t g, bool loss, double* sample = nullptr,
+                       bool recompute = false) {
   const int L = s->l_max;
   for (int m = 0; m < L; ++m)
     launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->lc, s->stream);
   T* Vmid = (T*)s->d_V[L & 1];
   if (loss && s->ns > 0) launch_sensor_loss<T>(Vmid, sensor_args(s, g), s->stream);
   if (sample) launch_sensor_sample<T>(Vmid, s->d_sens, s->ns, sample, s->stream);
-  launch_ionic<T>(s->model, ion_args<T>(s, Vmid, g), s->lc, s->stream);
+  IonArgs<T> ia = ion_args<T>(s, Vmid, g);
+  if (recompute) {
+    ia.apd = nullptr;
+    ia.stats = nullptr;
+  }
+  launch_ionic<T>(s->model, ia, s->lc, s->stream);
   for (int m = 0; m < L; ++m)
     launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
 }
@@ -842,8 +857,27 @@ mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
   };
   mono_status st = gp.capture(s, segment, n_steps, C);
   if (st != MONO_OK) return st;
+  // snapshot buffer of each segment start (-1: not stored): every start in
+  // the uniform schedule; the binomial plan's first splits otherwise
+  std::vector<int> slot_at(nck, -1);
+  if (s->ckpt_schedule == MONO_CKPT_UNIFORM) {
+    for (int64_t c = 0; c < nck; ++c) slot_at[c] = (int)c;
+  } else {
+    const CkptPlan& p = s->plan;
+    int64_t first = 0, k = nck;
+    int f = p.width - 1, slot = 0;
+    slot_at[0] = 0;
+    while (k > 1) {
+      const int64_t m = p.splitA[p.idx(k, f)];
+      if (m == 0) break;
+      first += m;
+      k -= m;
+      --f;
+      slot_at[first] = ++slot;
+    }
+  }
   for (int64_t c = 0; c < nck; ++c) {
-    HIP_TRY(save_state(s, s->d_ckpt[c]));
+    if (slot_at[c] >= 0) HIP_TRY(save_state(s, s->d_ckpt[slot_at[c]]));
     const int64_t cn = std::min(C, n_steps - c * C);
     HIP_TRY(hipGraphLaunch(gp.pick(s, s->step, cn, C), s->stream));
     s->step += cn;
@@ -926,9 +960,84 @@ mono_status backward_t(mono_sim* s) {
   GraphPair gp;
   mono_status st = gp.capture(s, segment, N, C);
   if (st != MONO_OK) return st;
-  for (int64_t c = nck - 1; c >= 0; --c) {
-    const int64_t t0 = c * C, cn = std::min(C, N - t0);
-    HIP_TRY(load_state(s, s->d_ckpt[c], vsub));
+  // the schedule: segments reversed from the last to the first, each from a
+  // snapshot buffer; in the binomial schedule, forward advances of whole
+  // segments refill buffers in between
+  struct Act {
+    bool advance;
+    int64_t c;     // segment reversed, or first segment advanced over
+    int64_t m;     // segments advanced
+    int from, to;  // snapshot buffers (reverse: `from` only; -1: the live state)
+  };
+  std::vector<Act> acts;
+  if (s->ckpt_schedule == MONO_CKPT_UNIFORM) {
+    for (int64_t c = nck - 1; c >= 0; --c) acts.push_back({false, c, 0, (int)c, -1});
+  } else {
+    const CkptPlan& p = s->plan;
+    std::function<void(int64_t, int64_t, int, int)> revF = [&](int64_t first, int64_t k, int slot,
+                                                                int f) {
+      if (k == 1) {
+        acts.push_back({false, first, 0, slot, -1});
+        return;
+      }
+      const int64_t m = p.splitF[p.idx(k, f)];
+      if (k - m == 1) {
+        // advance to the last segment and reverse it from the live state
+        acts.push_back({true, first, m, slot, -1});
+        acts.push_back({false, first + m, 0, -1, -1});
+      } else {
+        acts.push_back({true, first, m, slot, slot + 1});
+        revF(first + m, k - m, slot + 1, f - 1);
+      }
+      revF(first, m, slot, f);
+    };
+    std::function<void(int64_t, int64_t, int, int)> revA = [&](int64_t first, int64_t k, int slot,
+                                                                int f) {
+      if (k == 1) {
+        acts.push_back({false, first, 0, slot, -1});
+        return;
+      }
+      const int64_t m = p.splitA[p.idx(k, f)];
+      if (m == 0) return revF(first, k, slot, f);
+      revA(first + m, k - m, slot + 1, f - 1);
+      revF(first, m, slot, f);
+    };
+    revA(0, nck, 0, p.width - 1);
+  }
+  // forward advances of whole segments (never the last, possibly shorter,
+  // one): plain outer steps, the clock advanced on the device
+  GraphPair adv;
+  bool have_adv = false;
+  s->ckpt_advances = 0;
+  for (const Act& a : acts) {
+    if (a.advance && !have_adv) {
+      auto plain = [s](int64_t cn) {
+        return [s, cn]() {
+          for (int64_t t = 0; t < cn; ++t) enqueue_loss_step<T>(s, t, false, nullptr, true);
+          launch_advance_clock(s->d_base, cn, s->stream);
+        };
+      };
+      st = adv.capture(s, plain, C, C);
+      if (st != MONO_OK) return st;
+      have_adv = true;
+    }
+    if (a.advance) {
+      HIP_TRY(load_state(s, s->d_ckpt[a.from]));
+      launch_set_clock(s->d_base, s->tape_step0 + a.c * C, s->stream);
+      for (int64_t q = 0; q < a.m; ++q)
+        HIP_TRY(hipGraphLaunch(adv.pick(s, s->tape_step0 + (a.c + q) * C, C, C), s->stream));
+      if (a.to >= 0) HIP_TRY(save_state(s, s->d_ckpt[a.to]));
+      s->ckpt_advances += a.m;
+      continue;
+    }
+    const int64_t t0 = a.c * C, cn = std::min(C, N - t0);
+    if (a.from >= 0) {
+      HIP_TRY(load_state(s, s->d_ckpt[a.from], vsub));
+    } else {
+      // the live state is the segment's start: its potential to the tape's
+      // first slot, the other rows stay where the recompute reads them
+      HIP_TRY(hipMemcpyAsync(vsub, s->d_V[0], Np * s->es, hipMemcpyDeviceToDevice, s->stream));
+    }
     launch_set_clock(s->d_base, s->tape_step0 + t0, s->stream);
     HIP_TRY(hipGraphLaunch(gp.pick(s, s->tape_step0 + t0, cn, C), s->stream));
   }
@@ -1687,11 +1796,17 @@ mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t 
   free_tape(s);
   const int64_t C = std::min<int64_t>(ckpt_every, n_steps);
   const int64_t nck = (n_steps + C - 1) / C;
+  int64_t nslots = nck;
+  if (s->ckpt_schedule == MONO_CKPT_BINOMIAL) {
+    nslots = std::min<int64_t>(s->ckpt_max_slots, nck);
+    if (!make_ckpt_plan(nck, (int)nslots, s->plan))
+      return fail(MONO_EUNSUPPORTED, "no binomial plan for this many segments and snapshots");
+  }
   const size_t snap = snapshot_bytes(s);
   const size_t nblk = (size_t)((s->n + 255) / 256);
-  s->d_ckpt.assign(nck, nullptr);
+  s->d_ckpt.assign(nslots, nullptr);
   bool ok = true;
-  for (int64_t c = 0; c < nck && ok; ++c) ok = !dalloc((char**)&s->d_ckpt[c], snap);
+  for (int64_t c = 0; c < nslots && ok; ++c) ok = !dalloc((char**)&s->d_ckpt[c], snap);
   ok = ok && !dalloc((char**)&s->d_final, snap) &&
        !dalloc((char**)&s->d_seg_vsub, (size_t)C * 2 * s->l_max * s->Np * s->es) &&
        !dalloc((char**)&s->d_seg_entry, (size_t)C * s->S * s->Np * s->es) &&
@@ -1712,6 +1827,44 @@ mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t 
   if (st != MONO_OK) return st;
   s->taped = true;
   return check_flag(s);
+}
+
+mono_status mono_set_checkpointing(mono_sim* s, int32_t schedule, int32_t max_snapshots) {
+  if (!s) return fail(MONO_EINVAL, "NULL simulation");
+  if (schedule == MONO_CKPT_UNIFORM) {
+    s->ckpt_schedule = schedule;
+    s->ckpt_max_slots = 0;
+    return MONO_OK;
+  }
+  if (schedule != MONO_CKPT_BINOMIAL || max_snapshots < 2)
+    return fail(MONO_EINVAL, "schedule must be uniform, or binomial with at least 2 snapshots");
+  s->ckpt_schedule = schedule;
+  s->ckpt_max_slots = max_snapshots;
+  return MONO_OK;
+}
+
+mono_status mono_checkpoint_info(mono_sim* s, int64_t* out) {
+  if (!s || !out) return fail(MONO_EINVAL, "NULL argument");
+  if (!s->taped) return fail(MONO_ESTATE, "call mono_forward_taped first");
+  const int64_t C = s->ckpt_every;
+  const int L = s->l_max;
+  out[0] = s->ckpt_schedule;
+  out[1] = (int64_t)s->d_ckpt.size();
+  out[2] = (s->tape_steps + C - 1) / C;
+  out[3] = s->ckpt_advances;
+  out[4] = (int64_t)(s->d_ckpt.size() * snapshot_bytes(s));
+  out[5] = (int64_t)((size_t)C * (2 * L + s->S) * s->Np * s->es + (size_t)C * s->n);
+  return MONO_OK;
+}
+
+mono_status mono_checkpoint_plan(int64_t n_segments, int32_t max_snapshots, int64_t* advances) {
+  if (!advances || n_segments < 1) return fail(MONO_EINVAL, "bad argument");
+  CkptPlan p;
+  const int64_t slots = std::min<int64_t>(max_snapshots, n_segments);
+  if (!make_ckpt_plan(n_segments, (int)slots, p))
+    return fail(MONO_EINVAL, "no plan (fewer than 2 snapshots, or too large a table)");
+  *advances = p.advances();
+  return MONO_OK;
 }
 
 mono_status mono_backward(mono_sim* s, double* grad_sigma, double* grad_params) {

@@ -24,6 +24,7 @@ DEBUG_KTRACE, DEBUG_VCLAMP, DEBUG_FORCE_L, DEBUG_STATS, DEBUG_STATS_ENABLE = 1, 
 DEBUG_KTIMES = 6
 DEBUG_TIME_DIFFUSION = 7
 STEP_EAGER, STEP_TIMED, STEP_CAPTURE = 1, 2, 4
+CKPT_UNIFORM, CKPT_BINOMIAL = 0, 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSUPPORTED",
           -6: "ENONFINITE"}
@@ -37,7 +38,8 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_model_flops", "mono_set_launch", "mono_get_launch",
            "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
            "mono_forward_taped", "mono_backward", "mono_sample_sensors", "mono_set_allocator",
-           "mono_track_apd", "mono_nrmse")
+           "mono_track_apd", "mono_nrmse", "mono_set_checkpointing", "mono_checkpoint_info",
+           "mono_checkpoint_plan")
 
 
 class MonoError(RuntimeError):
@@ -146,6 +148,9 @@ def lib():
             "mono_set_allocator": [ALLOC_FN, FREE_FN, vp],
             "mono_track_apd": [vp, i32],
             "mono_nrmse": [vp, vp, i64, vp],
+            "mono_set_checkpointing": [vp, i32, i32],
+            "mono_checkpoint_info": [vp, vp],
+            "mono_checkpoint_plan": [i64, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -353,6 +358,19 @@ class Sim:
                                         out.ctypes.data))
         return float(out[0])
 
+    def set_checkpointing(self, schedule="uniform", max_snapshots=0):
+        """Checkpoint schedule of the next forward_taped: "uniform" or
+        "binomial" within max_snapshots snapshot buffers."""
+        code = {"uniform": CKPT_UNIFORM, "binomial": CKPT_BINOMIAL}[schedule]
+        _check(lib().mono_set_checkpointing(self.h, code, int(max_snapshots)))
+
+    def checkpoint_info(self):
+        out = np.zeros(6, np.int64)
+        _check(lib().mono_checkpoint_info(self.h, out.ctypes.data))
+        return {"schedule": ("uniform", "binomial")[int(out[0])], "snapshots": int(out[1]),
+                "segments": int(out[2]), "advances": int(out[3]),
+                "snapshot_bytes": int(out[4]), "tape_bytes": int(out[5])}
+
     def backward(self, n_params=None):
         """(dL/dsigma per node, derivative for a common multiplier of each parameter row)."""
         gs = np.zeros(self.n)
@@ -402,3 +420,10 @@ class Sim:
         out[0] = float(repetitions)
         _check(lib().mono_debug(self.h, DEBUG_TIME_DIFFUSION, out))
         return out[1]
+
+
+def checkpoint_plan_advances(n_segments, max_snapshots):
+    """Whole-segment forward advances of the binomial checkpoint plan (host)."""
+    out = np.zeros(1, np.int64)
+    _check(lib().mono_checkpoint_plan(int(n_segments), int(max_snapshots), out.ctypes.data))
+    return int(out[0])

@@ -115,3 +115,19 @@ def test_nrmse_of_eq4():
     assert mono.nrmse(uh, u) == pytest.approx(ref, rel=1e-12)
     assert mono.nrmse(u, u) == 0.0
     assert np.isnan(mono.nrmse(np.full(3, 5.0), np.full(3, 5.0)))
+
+
+def test_adjoint_problem_rejects_bad_replay_trace():
+    """The autograd problem checks a replayed k-trace before the library sees
+    its pointer: dtype, device, contiguity and shape."""
+    import torch
+    from paper_2011_04747_amd.adjoint import AdjointProblem
+    from paper_2011_04747_amd import workloads as W
+    w = W.adjoint_slab(shape=(5, 4, 3), t_end=1.0, n_sensors=4)
+    tgt = np.zeros((w.n_steps, 4))
+    for bad in (torch.zeros((w.n_steps, w.mesh.n_nodes), dtype=torch.uint8),      # host
+                torch.zeros((w.n_steps, w.mesh.n_nodes), dtype=torch.int32),
+                torch.zeros((w.n_steps, w.mesh.n_nodes + 1), dtype=torch.uint8),
+                torch.zeros((w.n_steps - 1, w.mesh.n_nodes), dtype=torch.uint8)):
+        with pytest.raises(ValueError):
+            AdjointProblem(w, tgt, w.n_steps, replay_k=bad)

@@ -186,3 +186,53 @@ def test_autograd_function(torch):
     want = np.array([gpo[r] / cr for r, cr in zip(TP06_SCALING_ROWS, c)])
     got = scal.grad.cpu().numpy()
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+
+
+def test_adjoint_with_out_of_range_replayed_k(torch):
+    """Trace entries of 0 and 200 are replayed as 1 and k_max by the forward
+    and the adjoint alike: the gradients equal those of the clamped trace."""
+    w, target = _problem("tp06")
+    n, steps = w.mesh.n_nodes, w.n_steps
+    raw = np.random.default_rng(12).integers(1, 11, size=(steps, n)).astype(np.uint8)
+    raw[:, ::5] = 0
+    raw[:, 2::5] = 200
+    res = []
+    for kt in (raw, np.clip(raw, 1, 10)):
+        L, gs, gp, s = _gpu_grad(torch, w, target, kt, "f64", 4)
+        s.close()
+        res.append((L, gs, gp))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+
+
+@pytest.mark.parametrize("kind,ckpt", [("tp06", 2), ("ms", 3), ("batched", 1)])
+def test_binomial_checkpointing_equals_uniform(torch, kind, ckpt):
+    """Binomial checkpointing within a few snapshot buffers gives the uniform
+    schedule's loss and gradients bit for bit, with the number of segment
+    advances of its plan, and the state is left where the taped run ended."""
+    w, target = _problem(kind)
+    _, _, _, kt = _oracle_grad(w, target)
+    nseg = -(-w.n_steps // ckpt)
+    ref = None
+    for sched, slots in (("uniform", 0), ("binomial", 2), ("binomial", 3),
+                         ("binomial", 5), ("binomial", nseg - 1), ("binomial", nseg + 3)):
+        s = mono.Sim.from_workload(w, "f64" if kind != "batched" else "f32")
+        rep = torch.from_numpy(np.ascontiguousarray(kt)).cuda()
+        s.ktrace(2, None, rep.data_ptr(), kt.shape[0], 0)
+        s.set_sensors(w.sensors, target)
+        s.set_checkpointing(sched, slots)
+        L = s.forward_taped(w.n_steps, w.dt, ckpt)
+        v_end = s.get(mono.FIELD_V)
+        gs, gp = s.backward()
+        info = s.checkpoint_info()
+        assert info["segments"] == nseg
+        assert (s.get(mono.FIELD_V) == v_end).all()
+        if sched == "uniform":
+            assert info["advances"] == 0 and info["snapshots"] == nseg
+            ref = (L, gs, gp)
+        else:
+            assert info["snapshots"] == min(slots, nseg)
+            assert info["advances"] == mono.checkpoint_plan_advances(nseg, slots)
+            assert L == ref[0]
+            assert np.array_equal(gs, ref[1]) and np.array_equal(gp, ref[2]), (sched, slots)
+        s.close()

@@ -333,8 +333,21 @@ def full_slab():
     return w, _oracle(w)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_full_slab_single_phases_sampled(torch, full_slab, prec):
+def _slab_tuned_launch():
+    import json
+    import os
+    f = os.path.join(os.path.dirname(mono.__file__), "tuned",
+                     "gfx950_f32_stencil13_m2_n2060451_i1_nnz54541351.json")
+    with open(f) as fh:
+        return json.load(fh)["launch"]
+
+
+@pytest.mark.parametrize("prec,launch", [("f64", "default"), ("f32", "default"),
+                                         ("f64", "tuned"), ("f32", "tuned")])
+def test_full_slab_single_phases_sampled(torch, full_slab, prec, launch):
+    """One diffusion substep and one reaction step of the full 2,060,451-node
+    slab, in the default launch shape and in the committed tuned one (the
+    shape the benchmark times), sampled row by row against the oracle."""
     w, o = full_slab
     n = w.mesh.n_nodes
     o.prepare(w.dt)
@@ -342,6 +355,8 @@ def test_full_slab_single_phases_sampled(torch, full_slab, prec):
     rng = np.random.default_rng(12)
     vprev = y0[0] - rng.uniform(-1.5, 1.5, n) * rng.choice([0.0, 0.01, 0.1, 1.0], n)
     s = mono.Sim.from_workload(w, prec)
+    if launch == "tuned":
+        s.set_launch(**_slab_tuned_launch())
     s.prepare(w.dt)
     rows = np.unique(np.concatenate([rng.integers(0, n, 3000), [0, 1, 200, n - 1, n - 2],
                                      np.arange(n - 300, n)]))
@@ -493,6 +508,21 @@ def test_determinism_two_runs_bitwise(torch):
 # ---------------------------------------------------------------------------
 # launch shapes and the autotuner
 # ---------------------------------------------------------------------------
+def _tuned_launches():
+    """The launch shapes committed in the tuning cache (the ones the benchmark
+    and the adjoint leg run with)."""
+    import glob
+    import json
+    import os
+    d = os.path.join(os.path.dirname(mono.__file__), "tuned")
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "*.json"))):
+        with open(f) as fh:
+            out.append(json.load(fh)["launch"])
+    assert out
+    return out
+
+
 @pytest.mark.parametrize("which", ["slab", "batch", "cable"])
 def test_launch_shapes_do_not_change_results(torch, which):
     if which == "slab":
@@ -510,7 +540,8 @@ def test_launch_shapes_do_not_change_results(torch, which):
                 dict(react_sort=1, react_block=1024, graph_steps=64),
                 dict(react_sort=0, react_block=1024, graph_steps=64, diff_classes=0),
                 dict(diff_classes=0, diff_rows_per_lane=2, diff_block=128),
-                dict(diff_wave_rows=0, diff_rows_per_lane=4, diff_block=512)):
+                dict(diff_wave_rows=0, diff_rows_per_lane=4, diff_block=512),
+                *_tuned_launches()):
         s = mono.Sim.from_workload(w, "f32")
         if cfg:
             s.set_launch(**cfg)
@@ -669,3 +700,33 @@ def test_torch_caching_allocator_owns_device_memory(torch):
         assert torch.cuda.memory_allocated() == base
     finally:
         mono.set_allocator()
+
+
+def test_replayed_k_is_clamped(torch):
+    """A replayed trace entry of 0 or above k_max runs (and is recorded) as 1
+    or k_max: the run equals one replaying the clamped trace bit for bit."""
+    w = W.sheet_tp06(n=23, t_end=3.0)
+    n, steps = w.mesh.n_nodes, w.n_steps
+    g = np.random.default_rng(11)
+    raw = g.integers(1, 11, size=(steps, n)).astype(np.uint8)
+    raw[:, ::7] = 0
+    raw[:, 3::7] = 200
+    kmax = None
+    out = []
+    for trace in (raw, None):
+        s = mono.Sim.from_workload(w, "f64")
+        s.prepare(w.dt)
+        kmax = s.info()["k_max"]
+        if trace is None:
+            trace = np.clip(raw, 1, kmax)
+        rep = torch.from_numpy(np.ascontiguousarray(trace)).cuda()
+        s.ktrace(2, None, rep.data_ptr(), steps, 0)
+        s.step(steps, w.dt)
+        out.append((s.get(mono.FIELD_V), s.get(mono.FIELD_K),
+                    [s.get(mono.FIELD_STATE0 + j) for j in range(1, s.info()["n_states"])]))
+        s.close()
+    assert kmax == 10
+    assert (out[0][1] == np.clip(raw[-1], 1, kmax)).all()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][2], out[1][2]):
+        assert np.array_equal(a, b)
