@@ -337,6 +337,19 @@ mono_status mono_set_sensors(mono_sim *sim, int32_t n, const int32_t *nodes, con
  * Synchronising; the targets given with the sensors are not used. */
 mono_status mono_sample_sensors(mono_sim *sim, int64_t n_steps, double dt, double *out);
 
+/* mono_sample_sensors for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same samples, staged in a static
+ * device buffer of the library (4 MiB per GPU, held until the process ends)
+ * instead of a per-call allocation.  No allocation of any kind.  Limits and
+ * errors: n_steps x sensors <= 524288 (EINVAL beyond); the simulation must
+ * already be prepared for this dt (mono_prepare or an earlier step with the
+ * same dt; ESTATE otherwise).  Every call on one GPU shares that GPU's
+ * buffer: calls that overlap on one GPU (several threads, or several
+ * simulations on different streams) race and must be serialised by the
+ * caller.  Synchronising. */
+mono_status mono_sample_sensors_noalloc(mono_sim *sim, int64_t n_steps, double dt, double *out);
+
 /* Advance n_steps outer steps from the current time level like mono_step,
  * keeping snapshots of the state at segment starts (segments of ckpt_every
  * steps), and return the loss (FP64).  Synchronising.  Needs k_max <= 16.

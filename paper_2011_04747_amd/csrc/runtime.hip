@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1777,6 +1778,67 @@ mono_status mono_sample_sensors(mono_sim* s, int64_t n_steps, double dt, double*
   if (!e) e = hipMemcpyAsync(out, dbuf, (size_t)n_steps * s->ns * 8, hipMemcpyDeviceToHost, s->stream);
   if (!e) e = hipStreamSynchronize(s->stream);
   dfree(dbuf);
+  if (e) return fail(MONO_EDEVICE, hipGetErrorString(e));
+  s->step += n_steps;
+  return check_flag(s);
+}
+
+}  // extern "C"
+
+namespace {
+// Staging of mono_sample_sensors_noalloc: a file-scope device array (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel or a copy: it takes the address
+// of this device's copy from hipGetSymbolAddress once per device and uses
+// that pointer.
+constexpr int64_t kNoAllocSamples = (int64_t)1 << 19;   // doubles (4 MiB)
+__device__ __align__(256) double scratch[kNoAllocSamples];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device ordinal, nullptr until looked up
+
+// Address of the current device's copy of `scratch`.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+mono_status mono_sample_sensors_noalloc(mono_sim* s, int64_t n_steps, double dt, double* out) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (n_steps < 0 || (n_steps > 0 && !out)) return fail(MONO_EINVAL, "bad argument");
+  if (s->ns <= 0) return fail(MONO_ESTATE, "no sensors set");
+  if (n_steps * (int64_t)s->ns > kNoAllocSamples)
+    return fail(MONO_EINVAL, "n_steps x sensors exceeds the 524288 samples of the static buffer");
+  if (s->latched) return fail(MONO_ESTATE, "simulation latched after a non-finite potential");
+  // a change of dt would rebuild the per-instance tables: not here
+  if (s->dt != dt) return fail(MONO_ESTATE, "call mono_prepare with this dt first");
+  double* buf = nullptr;
+  HIP_TRY(scratch_address(&buf));
+  // every sample slot of the n_steps x sensors written is set by the sample
+  // kernel before it is copied, so nothing needs clearing
+  if (s->prec == MONO_F64)
+    sample_steps<double>(s, n_steps, buf);
+  else
+    sample_steps<float>(s, n_steps, buf);
+  hipError_t e = hipGetLastError();
+  if (!e && n_steps > 0)
+    e = hipMemcpyAsync(out, buf, (size_t)n_steps * s->ns * 8, hipMemcpyDeviceToHost, s->stream);
+  if (!e) e = hipStreamSynchronize(s->stream);
   if (e) return fail(MONO_EDEVICE, hipGetErrorString(e));
   s->step += n_steps;
   return check_flag(s);

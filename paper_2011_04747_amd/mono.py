@@ -39,7 +39,7 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
            "mono_forward_taped", "mono_backward", "mono_sample_sensors", "mono_set_allocator",
            "mono_track_apd", "mono_nrmse", "mono_set_checkpointing", "mono_checkpoint_info",
-           "mono_checkpoint_plan")
+           "mono_checkpoint_plan", "mono_sample_sensors_noalloc")
 
 
 class MonoError(RuntimeError):
@@ -151,6 +151,7 @@ def lib():
             "mono_set_checkpointing": [vp, i32, i32],
             "mono_checkpoint_info": [vp, vp],
             "mono_checkpoint_plan": [i64, i32, vp],
+            "mono_sample_sensors_noalloc": [vp, i64, dbl, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -350,6 +351,14 @@ class Sim:
         """Step and return V at the sensors at reaction entry (n_steps x n_sensors)."""
         out = np.zeros((int(n_steps), int(n_sensors)))
         _check(lib().mono_sample_sensors(self.h, int(n_steps), float(dt), out.ctypes.data))
+        return out
+
+    def sample_sensors_noalloc(self, n_steps, dt, n_sensors):
+        """sample_sensors staged in the library's static device buffer (no
+        device allocation; n_steps x n_sensors <= 524288)."""
+        out = np.zeros((int(n_steps), int(n_sensors)))
+        _check(lib().mono_sample_sensors_noalloc(self.h, int(n_steps), float(dt),
+                                                 out.ctypes.data))
         return out
 
     def forward_taped(self, n_steps, dt, ckpt_every=50):
