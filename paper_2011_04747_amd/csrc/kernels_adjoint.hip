@@ -294,9 +294,11 @@ __global__ __launch_bounds__(256) void k_adj_ionic(AdjIonArgs<T> a) {
   bool live = i < a.n;
   if constexpr (SORT) {
     __shared__ int slot_node[256];
-    wg_order_by_key<256, kAdjMaxK + 1>(live ? min((int)a.k[i], kAdjMaxK) : -1, slot_node);
+    const bool ordered =
+        wg_order_by_key<256, kAdjMaxK + 1>(live ? min((int)a.k[i], kAdjMaxK) : -1,
+                                           kAdjMaxK + 1, slot_node);
     live = (int64_t)threadIdx.x < a.n - b0;
-    if (live) i = b0 + slot_node[threadIdx.x];
+    if (live && ordered) i = b0 + slot_node[threadIdx.x];
   }
   double gpd[M::P];
   for (int b = 0; b < M::P; ++b) gpd[b] = 0.0;

@@ -109,24 +109,88 @@ __device__ __forceinline__ int decide_k(const IonArgs<T>& a, int64_t i, int64_t 
   return k;
 }
 
-template <typename T, class M>
-__device__ __forceinline__ void load_cell(const IonArgs<T>& a, int64_t i, T* y, T* p) {
-  y[0] = a.V[i];
-  for (int s = 1; s < M::S; ++s) y[s] = a.st[(int64_t)(s - 1) * a.Np + i];
-  for (int q = 0; q < M::P; ++q)
-    p[q] = (a.par_pernode >> q & 1u) ? a.par[(int64_t)q * a.Np + i] : a.par_uniform[q];
+// Loads and stores of the state, parameter and potential rows of the node at
+// byte offset boff from the workgroup's first node b0.  Fast form (off32):
+// through buffer resources whose base (row 0 at node b0) sits in scalar
+// registers, with the row as a 32-bit scalar offset and the node as a 32-bit
+// lane offset, so an access takes no per-lane address arithmetic and nothing
+// address-like stays live across the substep loop; the host selects it when
+// every row offset fits in 32 bits.  General form: 64-bit indices.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T ld_row(__amdgpu_buffer_rsrc_t r, uint32_t boff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t r, uint32_t boff, uint32_t soff,
+                                       T v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, boff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((__vector_size__(8))) unsigned int, v), r, boff, soff, 0);
 }
 
 template <typename T, class M>
-__device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t i, T* y, const T* p,
-                                             int k) {
-  if (a.tape_st)
-    for (int s = 1; s < M::S; ++s) a.tape_st[(int64_t)(s - 1) * a.Np + i] = y[s];
+__device__ __forceinline__ void load_cell(const IonArgs<T>& a, int64_t b0, uint32_t lane, T* y,
+                                          T* p) {
+  if (a.off32) {
+    const uint32_t boff = lane * (uint32_t)sizeof(T);
+    const uint32_t rs = (uint32_t)(a.Np * (int64_t)sizeof(T));
+    y[0] = ld_row<T>(rows_rsrc(a.V + b0), boff, 0u);
+    const __amdgpu_buffer_rsrc_t st = rows_rsrc(a.st + b0);
+    for (int s = 1; s < M::S; ++s) y[s] = ld_row<T>(st, boff, (uint32_t)(s - 1) * rs);
+    const __amdgpu_buffer_rsrc_t pr = rows_rsrc(a.par + b0);
+    for (int q = 0; q < M::P; ++q) {
+      // the per-node test is uniform: a uniform parameter stays a scalar
+      T v = a.par_uniform[q];
+      if (a.par_pernode >> q & 1u) v = ld_row<T>(pr, boff, (uint32_t)q * rs);
+      p[q] = v;
+    }
+    return;
+  }
+  const int64_t i = b0 + lane;
+  y[0] = a.V[i];
+  for (int s = 1; s < M::S; ++s) y[s] = a.st[(int64_t)(s - 1) * a.Np + i];
+  for (int q = 0; q < M::P; ++q) {
+    T v = a.par_uniform[q];
+    if (a.par_pernode >> q & 1u) v = a.par[(int64_t)q * a.Np + i];
+    p[q] = v;
+  }
+}
+
+template <typename T, class M>
+__device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t b0, uint32_t lane, T* y,
+                                             const T* p, int k) {
+  const uint32_t boff = lane * (uint32_t)sizeof(T);
+  const uint32_t rs = (uint32_t)(a.Np * (int64_t)sizeof(T));
+  const int64_t i = b0 + lane;
+  if (a.tape_st) {
+    if (a.off32) {
+      const __amdgpu_buffer_rsrc_t tp = rows_rsrc(a.tape_st + b0);
+      for (int s = 1; s < M::S; ++s) st_row<T>(tp, boff, (uint32_t)(s - 1) * rs, y[s]);
+    } else {
+      for (int s = 1; s < M::S; ++s) a.tape_st[(int64_t)(s - 1) * a.Np + i] = y[s];
+    }
+  }
   const T h = (T)(a.clk.dt / (double)k);
   const bool clamp = a.vclamp != 0;
   for (int s = 0; s < k; ++s) M::substep(y, p, h, clamp);
-  (a.Vout ? a.Vout : a.V)[i] = y[0];
-  for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
+  T* const vo = a.Vout ? a.Vout : a.V;
+  if (a.off32) {
+    st_row<T>(rows_rsrc(vo + b0), boff, 0u, y[0]);
+    const __amdgpu_buffer_rsrc_t st = rows_rsrc(a.st + b0);
+    for (int s = 1; s < M::S; ++s) st_row<T>(st, boff, (uint32_t)(s - 1) * rs, y[s]);
+  } else {
+    vo[i] = y[0];
+    for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
+  }
 }
 
 // One node per lane.  SORT = false: the lane that decides node i's k advances
@@ -147,7 +211,8 @@ constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 8 : 1;
 template <typename T, class M, int BLOCK, bool SORT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kIonWavesPerEU<T>)))
 void k_ionic(IonArgs<T> a) {
-  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * BLOCK;
+  const int64_t i = b0 + threadIdx.x;
   const bool live = i < a.n;
   const int64_t step = *a.clk.base + a.clk.g;
   int k = 0;
@@ -155,7 +220,7 @@ void k_ionic(IonArgs<T> a) {
   T p[M::P];
   if (live) {
     if (!SORT || a.dvdt_src != 0) {
-      load_cell<T, M>(a, i, y, p);
+      load_cell<T, M>(a, b0, threadIdx.x, y, p);
       k = decide_k<T, M>(a, i, step, y[0], y, p);
     } else {
       k = decide_k<T, M>(a, i, step, a.V[i], y, p);
@@ -187,28 +252,17 @@ void k_ionic(IonArgs<T> a) {
     __shared__ int slot_node[BLOCK];
     __shared__ unsigned char node_k[BLOCK];
     node_k[threadIdx.x] = (unsigned char)k;   // k <= 255 (k_max is capped there)
-    wg_order_by_key<BLOCK, kSortMaxK + 1>(live ? min(k, kSortMaxK) : -1, slot_node);
-    const int64_t n_here = min((int64_t)BLOCK, a.n - (int64_t)blockIdx.x * BLOCK);
+    // keys 1 .. min(k_max, kSortMaxK) occur
+    const bool ordered = wg_order_by_key<BLOCK, kSortMaxK + 1>(
+        live ? min(k, kSortMaxK) : -1, min(a.k_max, kSortMaxK) + 1, slot_node);
+    const int64_t n_here = min((int64_t)BLOCK, a.n - b0);
     if ((int64_t)threadIdx.x >= n_here) return;
-    // the node's rows addressed from the workgroup's (uniform) first node by
-    // a 32-bit lane offset
-    const int64_t b0 = (int64_t)blockIdx.x * BLOCK;
-    const uint32_t j = (uint32_t)slot_node[threadIdx.x];
-    const int kn = node_k[j];
-    y[0] = (a.V + b0)[j];
-    for (int s = 1; s < M::S; ++s) y[s] = (a.st + (int64_t)(s - 1) * a.Np + b0)[j];
-    for (int c = 0; c < M::P; ++c)
-      p[c] = (a.par_pernode >> c & 1u) ? (a.par + (int64_t)c * a.Np + b0)[j] : a.par_uniform[c];
-    if (a.tape_st)
-      for (int s = 1; s < M::S; ++s) (a.tape_st + (int64_t)(s - 1) * a.Np + b0)[j] = y[s];
-    const T h = (T)(a.clk.dt / (double)kn);
-    const bool clamp = a.vclamp != 0;
-    for (int s = 0; s < kn; ++s) M::substep(y, p, h, clamp);
-    ((a.Vout ? a.Vout : a.V) + b0)[j] = y[0];
-    for (int s = 1; s < M::S; ++s) (a.st + (int64_t)(s - 1) * a.Np + b0)[j] = y[s];
+    const uint32_t j = ordered ? (uint32_t)slot_node[threadIdx.x] : threadIdx.x;
+    load_cell<T, M>(a, b0, j, y, p);
+    advance_cell<T, M>(a, b0, j, y, p, node_k[j]);
   } else {
     if (!live) return;
-    advance_cell<T, M>(a, i, y, p, k);
+    advance_cell<T, M>(a, b0, threadIdx.x, y, p, k);
   }
 }
 
@@ -241,6 +295,7 @@ void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_
     launch_ionic_m<T, MSModel>(a, c, s);
   else if (model == MONO_MODEL_TP06_TYPES)
     launch_ionic_m<T, TP06TypesModel>(a, c, s);
+
   else
     launch_ionic_m<T, TP06Model>(a, c, s);
 }

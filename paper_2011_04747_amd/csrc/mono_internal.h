@@ -209,6 +209,8 @@ struct IonArgs {
   double* apd;               // APD90 trackers (rows of Np: upstroke time,
                              // largest slope, V_max, V_rest, repolarisation
                              // time) or nullptr
+  int off32;                 // every state, parameter and tape row starts
+                             // below 4 GiB from its array (32-bit offsets)
 };
 
 // ---------------------------------------------------------------------------

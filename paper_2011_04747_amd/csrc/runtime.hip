@@ -411,6 +411,10 @@ IonArgs<T> ion_args(mono_sim* s, void* V, int64_t g) {
   a.flag = s->d_flag;
   a.stats = s->stats_on ? s->d_stats : nullptr;
   a.apd = s->d_apd;
+  // the largest row offset of the state and parameter arrays (plus a
+  // workgroup's span) must fit a 32-bit byte offset
+  const int64_t rows = std::max<int64_t>(s->S - 1, kMaxParams);
+  a.off32 = (rows * s->Np + 1024) * (int64_t)sizeof(T) < ((int64_t)1 << 32) ? 1 : 0;
   return a;
 }
 
