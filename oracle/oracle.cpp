@@ -277,17 +277,22 @@ template <int N> DualN<N> sqrt(const DualN<N>& a) {
 // ---------------------------------------------------------------------------
 // M_TP06T is TP06 with the transmural cell type as a seventh parameter
 // (0 epicardial, 1 endocardial, 2 mid-myocardial); M_TP06 is the epicardial
-// cell alone.
-enum { M_LINEAR = 0, M_MS = 1, M_TP06 = 2, M_TP06T = 3 };
+// cell alone.  M_TP06F mixes epicardial myocytes and fibroblasts in one
+// tissue (Sec. 3.2): parameter 6 is the node class (0 myocyte, 1
+// fibroblast), parameters 7 and 8 the rate g_f and reversal potential E_f of
+// the fibroblast's passive membrane.
+enum { M_LINEAR = 0, M_MS = 1, M_TP06 = 2, M_TP06T = 3, M_TP06F = 4 };
+// largest state and parameter counts over the models (buffer sizes)
+constexpr int kMaxStates = 19, kMaxParams = 9;
 
-bool is_tp06(int m) { return m == M_TP06 || m == M_TP06T; }
+bool is_tp06(int m) { return m == M_TP06 || m == M_TP06T || m == M_TP06F; }
 // cell type stored as a parameter value (checked to be 0, 1 or 2 on input)
 int cell_type(double v) { return v == 1.0 ? 1 : (v == 2.0 ? 2 : 0); }
 template <int N>
 int cell_type(const DualN<N>& v) { return cell_type(v.v); }
 int model_nstates(int m) { return m == M_LINEAR ? 1 : (m == M_MS ? 2 : 19); }
 int model_nparams(int m) {
-  return m == M_LINEAR ? 2 : (m == M_MS ? 5 : (m == M_TP06 ? 6 : 7));
+  return m == M_LINEAR ? 2 : (m == M_MS ? 5 : (m == M_TP06 ? 6 : (m == M_TP06T ? 7 : 9)));
 }
 
 // Rates of one cell.  For every state y the model reports either a forward
@@ -309,6 +314,18 @@ void rates_linear(const Num* y, const Num* p, Rates<Num>& r) {
   r.buffered = 0;
   r.is_gate[0] = 0;
   r.rate[0] = -p[0] * (y[0] - p[1]);
+}
+
+// Passive fibroblast of the mixed tissue: dV/dt = -g_f (V - E_f) with
+// p[7] = g_f, p[8] = E_f; its other (TP06-sized) states do not move.
+template <typename Num>
+void rates_fibroblast(const Num* y, const Num* p, Rates<Num>& r) {
+  r.buffered = 0;
+  for (int i = 0; i < 19; ++i) {
+    r.is_gate[i] = 0;
+    r.rate[i] = 0.0;
+  }
+  r.rate[0] = -p[7] * (y[0] - p[8]);
 }
 
 // Mitchell-Schaeffer: dv/dt = h v^2 (1-v)/tau_in - v/tau_out,
@@ -567,6 +584,10 @@ void model_rates(int model, const Num* y, const Num* p, Rates<Num>& r) {
     rates_ms(y, p, r);
   else if (model == M_TP06)
     rates_tp06(y, p, r);
+  else if (model == M_TP06F && cell_type(p[6]) == 1)
+    rates_fibroblast(y, p, r);
+  else if (model == M_TP06F)
+    rates_tp06(y, p, r);
   else
     rates_tp06(y, p, r, cell_type(p[6]));
 }
@@ -819,7 +840,7 @@ void reaction(Sim* s, int64_t nstep) {
   }
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    double y[19], p[8];
+    double y[kMaxStates], p[kMaxParams];
     for (int a = 0; a < S; ++a) y[a] = s->state[a * n + i];
     for (int a = 0; a < P; ++a) p[a] = s->params[a * n + i];
     s->lastk[i] = react_node(s, nstep, i, y, p, s->vprev[i], s->lat[i]);
@@ -832,12 +853,11 @@ void reaction(Sim* s, int64_t nstep) {
 // ---------------------------------------------------------------------------
 // Jacobian of one substep at (y, p): J[i][j] = d y'_i / d (y_j for j < S,
 // p_{j-S} for j >= S), by forward-mode derivatives through the model code.
-constexpr int kJac = 26;   // 19 states + 7 parameters (TP06 with cell types), the largest model
-constexpr int kMaxStates = 19, kMaxParams = 7;
+constexpr int kJac = 28;   // 19 states + 9 parameters (TP06 with fibroblasts), the largest model
 static_assert(kJac >= kMaxStates + kMaxParams, "Jacobian width must hold every model's states and parameters");
 void substep_jacobian(int model, const double* y, const double* p, double h, int S, int P,
                       double* J) {
-  DualN<kJac> yd[19], pd[8];
+  DualN<kJac> yd[19], pd[kMaxParams];
   for (int a = 0; a < S; ++a) {
     yd[a] = DualN<kJac>(y[a]);
     yd[a].d[a] = 1.0;
@@ -1022,7 +1042,7 @@ int orc_get_matrix(void* h, int64_t* rowptr, int32_t* col, double* val, double* 
 int orc_set_model(void* h, int model, int n_params, const double* params,
                   const double* init_state, double dt0, double lat_thr) {
   Sim* s = (Sim*)h;
-  if (model < 0 || model > 3) return fail("unknown model");
+  if (model < 0 || model > 4) return fail("unknown model");
   if (!(dt0 > 0.0)) return fail("dt0 must be positive");
   s->model = model;
   s->S = model_nstates(model);
@@ -1047,10 +1067,15 @@ int orc_set_model(void* h, int model, int n_params, const double* params,
         const double c = params[6 * n + i];
         if (c != 0.0 && c != 1.0 && c != 2.0) return fail("cell type must be 0, 1 or 2");
       }
+    if (model == M_TP06F)
+      for (int64_t i = 0; i < n; ++i) {
+        const double c = params[6 * n + i];
+        if (c != 0.0 && c != 1.0) return fail("node class must be 0 or 1");
+      }
     std::memcpy(s->params.data(), params, sizeof(double) * s->P * n);
   } else {
     const double ms[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
-    const double tp6[7] = {5.4, 1, 1, 1, 1, 1, 0};
+    const double tp6[9] = {5.4, 1, 1, 1, 1, 1, 0, 0.635, -49.6};
     const double lin[2] = {0.0, 0.0};
     for (int a = 0; a < s->P; ++a) {
       double v = model == M_MS ? ms[a] : (is_tp06(model) ? tp6[a] : lin[a]);
@@ -1239,7 +1264,7 @@ int orc_backward(void* h, double* grad_sigma, double* grad_params) {
     for (int64_t i = 0; i < n; ++i) {
       const int k = s->tape_k[t * n + i];
       const double hsub = s->dt / k;
-      double p[8], J[kMaxStates * kJac], li[kMaxStates];
+      double p[kMaxParams], J[kMaxStates * kJac], li[kMaxStates];
       std::vector<double> ys((size_t)k * S);   // substep start states
       for (int b = 0; b < P; ++b) p[b] = s->params[(int64_t)b * n + i];
       for (int a = 0; a < S; ++a) ys[a] = entry[(int64_t)a * n + i];
@@ -1307,7 +1332,7 @@ int orc_reaction_nodes(void* h, int64_t nstep, int64_t nrows, const int64_t* row
   for (int64_t r = 0; r < nrows; ++r) {
     const int64_t i = rows[r];
     if (i < 0 || i >= s->n) return fail("node out of range");
-    double yy[19], p[8];
+    double yy[kMaxStates], p[kMaxParams];
     for (int a = 0; a < s->S; ++a) yy[a] = y[a * nrows + r];
     for (int a = 0; a < s->P; ++a) p[a] = s->params[a * s->n + i];
     k_out[r] = react_node(s, nstep, i, yy, p, vprev[r], lat[r]);

@@ -33,11 +33,19 @@ MODEL_LINEAR = 0
 MODEL_MS = 1
 MODEL_TP06 = 2
 MODEL_TP06_TYPES = 3    # TP06 with a per-node transmural cell type (7th row)
+MODEL_TP06_FIBRO = 4    # TP06 myocytes and passive fibroblasts (class, g_f, E_f rows)
 
 # transmural cell types of MODEL_TP06_TYPES
 CELL_EPI = 0
 CELL_ENDO = 1
 CELL_M = 2
+# node classes of MODEL_TP06_FIBRO
+NODE_MYOCYTE = 0
+NODE_FIBROBLAST = 1
+# passive fibroblast membrane: rate g_f = G_f / C_f [1/ms] and reversal
+# potential E_f [mV] (rows 7 and 8 of MODEL_TP06_FIBRO)
+FIBRO_PARAM_NAMES = ("g_f", "E_f")
+FIBRO_PARAM_DEFAULT = (0.635, -49.6)
 
 ETYPE_LINE2 = 2
 ETYPE_TRI3 = 3
@@ -306,6 +314,15 @@ def tp06_types_params(types: np.ndarray) -> np.ndarray:
     return np.vstack([tp06_params(types.size), types.astype(np.float64)[None, :]])
 
 
+def tp06_fibro_params(classes: np.ndarray) -> np.ndarray:
+    """Parameter rows of MODEL_TP06_FIBRO: the TP06 defaults, the node class
+    (NODE_MYOCYTE or NODE_FIBROBLAST) and the fibroblast membrane rows."""
+    classes = np.asarray(classes)
+    n = classes.size
+    return np.vstack([tp06_params(n), classes.astype(np.float64)[None, :],
+                      _default_params(FIBRO_PARAM_DEFAULT, n)])
+
+
 def ms_params(n_nodes: int) -> np.ndarray:
     return _default_params(MS_PARAM_DEFAULT, n_nodes)
 
@@ -491,6 +508,41 @@ def sheet_transmural_tp06(n_wall: int = 151, n_height: int = 51, dx: float = 0.0
     a = STIM_AMP_TP06_PLANAR if amp is None else amp
     return Workload("sheet_transmural_tp06_2d", mesh, MODEL_TP06_TYPES, tp06_types_params(types),
                     [_planar_s1(xyz, a, t_on=t_on)], dt, t_end, 0.01, precision, -40.0)
+
+
+def sheet_fibrotic_tp06(n: int = 251, dx: float = 0.02, d0m: float = 0.002,
+                        d0f: float = 0.00066, ratio: float = 0.25, fib_frac: float = 0.10,
+                        seed: int = 7, s1_time: float = 50.0, s2_time: float = 200.0,
+                        t_end: float = 500.0, dt: float = 0.1, precision: str = "f64",
+                        amp: Optional[float] = None) -> Workload:
+    """The 2D fibrotic sheet of Sec. 3.2: a square sheet (5 x 5 cm at the
+    defaults: 251 x 251 nodes at h = 200 um, the coarsest mesh of Table 1),
+    fibres along x, a fraction fib_frac of the nodes drawn uniformly at random
+    (seeded) as fibroblasts (passive membrane, MODEL_TP06_FIBRO), the rest
+    epicardial TP06 myocytes; conductivity d0m between myocytes and d0f in
+    every element that holds a fibroblast node (between fibroblasts and
+    between myocytes and fibroblasts), transverse ratio `ratio`; cross-field
+    protocol: S1 on the left edge at s1_time, S2 over the lower left quarter
+    x <= L/4, y <= L/2 at s2_time, 1 ms each."""
+    xyz, conn, et = structured_grid((n, n), dx)
+    rng = np.random.default_rng(seed)
+    nn = n * n
+    fib = np.zeros(nn, bool)
+    fib[rng.choice(nn, int(round(fib_frac * nn)), replace=False)] = True
+    has_fib = fib[conn].any(axis=1)
+    d0 = np.where(has_fib, d0f, d0m)
+    f = angle_fibres(np.zeros(conn.shape[0]), 2)
+    De = np.einsum("e,eij->eij", d0, fibre_tensor(f, 1.0, ratio))
+    mesh = Mesh(2, xyz, et, conn, De, grid_shape=(n, n))
+    classes = np.where(fib, NODE_FIBROBLAST, NODE_MYOCYTE)
+    a = STIM_AMP_TP06_PLANAR if amp is None else amp
+    L = (n - 1) * dx
+    s1 = _planar_s1(xyz, a, t_on=s1_time)
+    s2n = np.nonzero((xyz[:, 0] <= 0.25 * L + 1e-12) & (xyz[:, 1] <= 0.5 * L + 1e-12))[0]
+    s2 = Stimulus(s2n.astype(np.int32), s2_time, 1.0, a)
+    return Workload("sheet_fibrotic_tp06_2d", mesh, MODEL_TP06_FIBRO, tp06_fibro_params(classes),
+                    [s1, s2], dt, t_end, 0.01, precision, -40.0,
+                    extra={"fibroblasts": int(fib.sum())})
 
 
 def batched_sheets(n_inst: int = 64, side_lo: int = 50, side_hi: int = 400,
