@@ -84,12 +84,21 @@ typedef enum {
  *           parameter row: 0 epicardial, 1 endocardial (G_to = 0.073, the
  *           endocardial s gate), 2 M cell (G_Ks = 0.098); heterogeneous
  *           tissue in one simulation.  In mono_backward the type row is
- *           a label: its gradient entry is 0.                               */
+ *           a label: its gradient entry is 0.
+ *  TP06_FIBRO myocytes and fibroblasts in one tissue (Sec. 3.2): 9 rows,
+ *           those of TP06_EPI, then a node class (0 epicardial TP06
+ *           myocyte, 1 fibroblast), then g_f [1/ms] and E_f [mV] of the
+ *           fibroblasts' passive membrane dV/dt = -g_f (V - E_f) (defaults
+ *           0.635 and -49.6).  A fibroblast node keeps its other 18 state
+ *           rows; its substep count follows the same k rule.  Any class
+ *           other than 0 or 1 is EINVAL.  In mono_backward the class row is
+ *           a label (gradient entry 0).                                     */
 typedef enum {
   MONO_MODEL_LINEAR = 0,
   MONO_MODEL_MS = 1,
   MONO_MODEL_TP06_EPI = 2,
-  MONO_MODEL_TP06_TYPES = 3
+  MONO_MODEL_TP06_TYPES = 3,
+  MONO_MODEL_TP06_FIBRO = 4
 } mono_model;
 
 /* DAETI: adaptive k and l (Sec. 2).  OSTAR: l = 1 (adaptive reaction only).

@@ -466,4 +466,30 @@ struct TP06TypesModel {
   }
 };
 
+// Myocytes and fibroblasts in one tissue (the paper's fibrotic sheet, Sec.
+// 3.2): parameter row 6 holds the node class, 0 an epicardial TP06 myocyte,
+// 1 a fibroblast with a passive (linear) membrane dV/dt = -g_f (V - E_f),
+// g_f and E_f in rows 7 and 8.  A fibroblast node keeps its other 18 state
+// rows unchanged.
+struct TP06FibroModel {
+  static constexpr int S = 19, P = 9;
+  template <typename T>
+  __host__ __device__ static bool fibroblast(const T* p) { return p[6] == T(1); }
+  template <typename T>
+  __host__ __device__ static T vrate(const T* y, const T* p) {
+    if (fibroblast(p)) return -p[7] * (y[0] - p[8]);
+    TP06Fluxes<T> c;
+    tp06_fluxes(y, p, c);
+    return -c.Iion;
+  }
+  template <typename T>
+  __host__ __device__ static void substep(T* y, const T* p, T h, bool clamp) {
+    if (fibroblast(p)) {
+      if (!clamp) y[0] = y[0] + h * (-p[7] * (y[0] - p[8]));
+      return;
+    }
+    tp06_substep(y, p, h, clamp, T(tp06::kGto), T(tp06::kGKs), false);
+  }
+};
+
 }  // namespace mono

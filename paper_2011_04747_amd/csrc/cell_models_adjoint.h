@@ -392,4 +392,21 @@ __host__ __device__ void tp06_types_substep_vjp(const T* y, const T* p, T h, boo
   tp06_substep_vjp(y, p, h, clamp, lam, gp, gto, gks, endo);
 }
 
+// Myocytes and fibroblasts: the class row (p[6]) is a label (adjoint 0); a
+// fibroblast's substep V' = V - h g_f (V - E_f) leaves the other states
+// (and their adjoints) unchanged and feeds the g_f and E_f rows.
+template <typename T>
+__host__ __device__ void tp06_fibro_substep_vjp(const T* y, const T* p, T h, bool clamp, T* lam,
+                                                T* gp) {
+  if (TP06FibroModel::fibroblast(p)) {
+    if (clamp) return;
+    const T l0 = lam[0];
+    lam[0] = l0 * (T(1) - h * p[7]);
+    gp[7] += -l0 * h * (y[0] - p[8]);
+    gp[8] += l0 * h * p[7];
+    return;
+  }
+  tp06_substep_vjp(y, p, h, clamp, lam, gp);
+}
+
 }  // namespace mono

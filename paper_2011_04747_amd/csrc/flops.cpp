@@ -69,6 +69,8 @@ extern "C" mono_status mono_model_flops(int32_t model, const double* state, cons
     count_substep<mono::TP06Model>(state, params, c);
   else if (model == MONO_MODEL_TP06_TYPES)
     count_substep<mono::TP06TypesModel>(state, params, c);
+  else if (model == MONO_MODEL_TP06_FIBRO)
+    count_substep<mono::TP06FibroModel>(state, params, c);
   else
     return MONO_EINVAL;
   const long long v[7] = {c.add, c.mul, c.div, c.exp, c.log, c.sqrt, c.cmp};
@@ -88,6 +90,8 @@ extern "C" mono_status mono_model_substep_host(int32_t model, double* y, const d
     mono::TP06Model::substep(y, p, h, clamp != 0);
   else if (model == MONO_MODEL_TP06_TYPES)
     mono::TP06TypesModel::substep(y, p, h, clamp != 0);
+  else if (model == MONO_MODEL_TP06_FIBRO)
+    mono::TP06FibroModel::substep(y, p, h, clamp != 0);
   else
     return MONO_EINVAL;
   return MONO_OK;
@@ -104,6 +108,8 @@ extern "C" mono_status mono_model_vjp_host(int32_t model, const double* y, const
     mono::tp06_substep_vjp(y, p, h, clamp != 0, lam, gp);
   else if (model == MONO_MODEL_TP06_TYPES)
     mono::tp06_types_substep_vjp(y, p, h, clamp != 0, lam, gp);
+  else if (model == MONO_MODEL_TP06_FIBRO)
+    mono::tp06_fibro_substep_vjp(y, p, h, clamp != 0, lam, gp);
   else
     return MONO_EINVAL;
   return MONO_OK;

@@ -282,6 +282,21 @@ struct TP06TypesAdj {
     tp06_types_substep_vjp(y, p, h, false, lam, gp);
   }
 };
+// The myocyte/fibroblast VJP is a call, not inlined: inlined into the
+// unsorted FP64 kernel (some 430 registers, accumulation registers used as
+// spill space) it returned wrong parameter gradients while the sorted
+// instantiation and this out-of-line form match the FP64 oracle adjoint to
+// rounding (tested for both orders and precisions).
+template <typename T>
+__device__ __noinline__ void fibro_vjp_call(const T* y, const T* p, T h, T* lam, T* gp) {
+  tp06_fibro_substep_vjp(y, p, h, false, lam, gp);
+}
+struct TP06FibroAdj {
+  template <typename T>
+  __device__ static void vjp(const T* y, const T* p, T h, T* lam, T* gp) {
+    fibro_vjp_call(y, p, h, lam, gp);
+  }
+};
 
 // SORT: the workgroup's nodes are taken in order of their substep count k
 // (wg_sort.h), so a wavefront replays and reverses one k where it can; the
@@ -360,6 +375,12 @@ void launch_adj_ionic(int model, const AdjIonArgs<T>& a, hipStream_t s) {
                        s, a);
   else if (model == MONO_MODEL_TP06_TYPES)
     hipLaunchKernelGGL((k_adj_ionic<T, TP06TypesModel, TP06TypesAdj, false>), grid, dim3(256), 0,
+                       s, a);
+  else if (model == MONO_MODEL_TP06_FIBRO && a.sort)
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06FibroModel, TP06FibroAdj, true>), grid, dim3(256), 0,
+                       s, a);
+  else if (model == MONO_MODEL_TP06_FIBRO)
+    hipLaunchKernelGGL((k_adj_ionic<T, TP06FibroModel, TP06FibroAdj, false>), grid, dim3(256), 0,
                        s, a);
   else if (a.sort)
     hipLaunchKernelGGL((k_adj_ionic<T, TP06Model, TP06Adj, true>), grid, dim3(256), 0, s, a);

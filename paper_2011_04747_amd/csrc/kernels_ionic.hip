@@ -11,6 +11,8 @@
 // segment).  The activation time of
 // a node (first upward crossing of a threshold between the V samples taken at
 // reaction entry, linearly interpolated) is kept in FP64 in every precision.
+#include <type_traits>
+
 #include "cell_models.h"
 #include "mono_internal.h"
 #include "wg_sort.h"
@@ -252,9 +254,17 @@ void k_ionic(IonArgs<T> a) {
     __shared__ int slot_node[BLOCK];
     __shared__ unsigned char node_k[BLOCK];
     node_k[threadIdx.x] = (unsigned char)k;   // k <= 255 (k_max is capped there)
-    // keys 1 .. min(k_max, kSortMaxK) occur
+    // keys 1 .. min(k_max, kSortMaxK) occur; a model with a cheap node class
+    // (fibroblasts) gives those nodes key 0, so that they share wavefronts
+    int key = live ? min(k, kSortMaxK) : -1;
+    if constexpr (std::is_same<M, TP06FibroModel>::value) {
+      if (live) {
+        const T cls = (a.par_pernode >> 6 & 1u) ? a.par[6 * a.Np + i] : a.par_uniform[6];
+        if (cls == T(1)) key = 0;
+      }
+    }
     const bool ordered = wg_order_by_key<BLOCK, kSortMaxK + 1>(
-        live ? min(k, kSortMaxK) : -1, min(a.k_max, kSortMaxK) + 1, slot_node);
+        key, min(a.k_max, kSortMaxK) + 1, slot_node);
     const int64_t n_here = min((int64_t)BLOCK, a.n - b0);
     if ((int64_t)threadIdx.x >= n_here) return;
     const uint32_t j = ordered ? (uint32_t)slot_node[threadIdx.x] : threadIdx.x;
@@ -295,7 +305,8 @@ void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_
     launch_ionic_m<T, MSModel>(a, c, s);
   else if (model == MONO_MODEL_TP06_TYPES)
     launch_ionic_m<T, TP06TypesModel>(a, c, s);
-
+  else if (model == MONO_MODEL_TP06_FIBRO)
+    launch_ionic_m<T, TP06FibroModel>(a, c, s);
   else
     launch_ionic_m<T, TP06Model>(a, c, s);
 }

@@ -44,7 +44,7 @@ void launch_step_kernel(F kernel, dim3 grid, dim3 block, hipStream_t s, A... arg
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxStim = 8;        // stimuli per simulation
 constexpr int kMaxOffsets = 13;    // positive stencil offsets (27-point hex stencil)
-constexpr int kMaxParams = 8;
+constexpr int kMaxParams = 10;
 constexpr int kMaxStates = 19;
 
 // ---------------------------------------------------------------------------

@@ -75,12 +75,22 @@ void dfree(T*& p) {
 const double kTP06Init[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0, 0.0, 0.75, 0.75,
                               0.0,   1.0,   0.0,  0.0,     1.0,     0.0, 1.0, 1.0, 1.0};
 const double kMSParams[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
-const double kTP06Params[7] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0};   // row 6: cell type
+// rows 6..8: cell type or node class, fibroblast membrane rate g_f [1/ms] and
+// reversal potential E_f [mV]
+const double kTP06Params[9] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0, 0.635, -49.6};
 
-bool is_tp06(int m) { return m == MONO_MODEL_TP06_EPI || m == MONO_MODEL_TP06_TYPES; }
+bool is_tp06(int m) {
+  return m == MONO_MODEL_TP06_EPI || m == MONO_MODEL_TP06_TYPES || m == MONO_MODEL_TP06_FIBRO;
+}
 int model_states(int m) { return m == MONO_MODEL_LINEAR ? 1 : (m == MONO_MODEL_MS ? 2 : 19); }
 int model_params(int m) {
-  return m == MONO_MODEL_LINEAR ? 2 : (m == MONO_MODEL_MS ? 5 : (m == MONO_MODEL_TP06_EPI ? 6 : 7));
+  switch (m) {
+    case MONO_MODEL_LINEAR: return 2;
+    case MONO_MODEL_MS: return 5;
+    case MONO_MODEL_TP06_EPI: return 6;
+    case MONO_MODEL_TP06_TYPES: return 7;
+    default: return 9;
+  }
 }
 double default_lat_threshold(int m) {
   return is_tp06(m) ? -40.0 : (m == MONO_MODEL_MS ? 0.5 : 0.0);
@@ -1320,7 +1330,7 @@ void mono_destroy(mono_sim* s) {
 mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
                                 const double* params, const double* init_state, double dt0) {
   if (!s) return fail(MONO_EINVAL, "NULL simulation");
-  if (model < MONO_MODEL_LINEAR || model > MONO_MODEL_TP06_TYPES)
+  if (model < MONO_MODEL_LINEAR || model > MONO_MODEL_TP06_FIBRO)
     return fail(MONO_EINVAL, "unknown cell model");
   if (!(dt0 > 0.0)) return fail(MONO_EINVAL, "dt0 must be positive");
   const int S = model_states(model), P = model_params(model);
@@ -1330,6 +1340,11 @@ mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
       const double c = params[(size_t)6 * s->n + i];
       if (c != 0.0 && c != 1.0 && c != 2.0)
         return fail(MONO_EINVAL, "cell type row must hold 0, 1 or 2");
+    }
+  if (params && model == MONO_MODEL_TP06_FIBRO)
+    for (int64_t i = 0; i < s->n; ++i) {
+      const double c = params[(size_t)6 * s->n + i];
+      if (c != 0.0 && c != 1.0) return fail(MONO_EINVAL, "node class row must hold 0 or 1");
     }
   HIP_TRY(hipStreamSynchronize(s->stream));
   drop_graph(s);

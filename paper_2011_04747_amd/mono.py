@@ -383,9 +383,9 @@ class Sim:
     def backward(self, n_params=None):
         """(dL/dsigma per node, derivative for a common multiplier of each parameter row)."""
         gs = np.zeros(self.n)
-        gp = np.zeros(8)
+        gp = np.zeros(16)
         _check(lib().mono_backward(self.h, gs.ctypes.data, gp.ctypes.data))
-        P = n_params if n_params is not None else {0: 2, 1: 5, 2: 6, 3: 7}[self.model]
+        P = n_params if n_params is not None else {0: 2, 1: 5, 2: 6, 3: 7, 4: 9}[self.model]
         return gs, gp[:P]
 
     # -- test hooks --------------------------------------------------------------

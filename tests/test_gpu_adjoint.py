@@ -34,6 +34,11 @@ def _problem(kind):
     elif kind == "tp06":
         w = W.adjoint_slab(shape=(23, 19, 7), t_end=12.0, n_sensors=64)
         base = -80.0
+    elif kind == "fibro":
+        # myocytes and passive fibroblasts (20% of the nodes)
+        w = W.sheet_fibrotic_tp06(n=31, dx=0.02, fib_frac=0.2, s1_time=0.0, t_end=12.0)
+        w.sensors = np.sort(rng.choice(w.mesh.n_nodes, 60, replace=False)).astype(np.int32)
+        base = -80.0
     elif kind == "tp06types":
         # endocardial, M and epicardial layers (per-node cell type row)
         w = W.sheet_transmural_tp06(n_wall=41, n_height=13, t_end=15.0)
@@ -60,8 +65,10 @@ def _oracle_grad(w, target):
     return L, gs, gp, kt
 
 
-def _gpu_grad(torch, w, target, kt, prec, ckpt):
+def _gpu_grad(torch, w, target, kt, prec, ckpt, launch=None):
     s = mono.Sim.from_workload(w, prec)
+    if launch:
+        s.set_launch(**launch)
     rep = torch.from_numpy(np.ascontiguousarray(kt)).cuda()
     s.ktrace(2, None, rep.data_ptr(), kt.shape[0], 0)
     s.set_sensors(w.sensors, target)
@@ -71,11 +78,14 @@ def _gpu_grad(torch, w, target, kt, prec, ckpt):
     return L, gs, gp, s
 
 
-@pytest.mark.parametrize("kind", ["ms", "tp06", "batched", "tp06types"])
-def test_adjoint_fp64_matches_oracle(torch, kind):
+@pytest.mark.parametrize("sort", [0, 1])
+@pytest.mark.parametrize("kind", ["ms", "tp06", "batched", "tp06types", "fibro"])
+def test_adjoint_fp64_matches_oracle(torch, kind, sort):
+    """Both orders of the adjoint reaction (nodes as numbered, or ordered by
+    k within a workgroup) against the oracle."""
     w, target = _problem(kind)
     Lo, gso, gpo, kt = _oracle_grad(w, target)
-    Lg, gsg, gpg, s = _gpu_grad(torch, w, target, kt, "f64", 7)
+    Lg, gsg, gpg, s = _gpu_grad(torch, w, target, kt, "f64", 7, dict(react_sort=sort))
     assert Lg == pytest.approx(Lo, rel=1e-10)
     assert np.abs(gsg - gso).max() <= 1e-8 * np.abs(gso).max()
     assert np.abs(gpg - gpo).max() <= 1e-8 * np.abs(gpo).max()
@@ -103,11 +113,12 @@ def test_adjoint_checkpoint_interval_does_not_change_gradients(torch):
             assert L == ref[0] and (gs == ref[1]).all() and (gp == ref[2]).all()
 
 
-@pytest.mark.parametrize("kind", ["tp06", "batched", "tp06types"])
-def test_adjoint_fp32_against_fp64_oracle(torch, kind):
+@pytest.mark.parametrize("sort", [0, 1])
+@pytest.mark.parametrize("kind", ["tp06", "batched", "tp06types", "fibro"])
+def test_adjoint_fp32_against_fp64_oracle(torch, kind, sort):
     w, target = _problem(kind)
     Lo, gso, gpo, kt = _oracle_grad(w, target)
-    Lg, gsg, gpg, _ = _gpu_grad(torch, w, target, kt, "f32", 50)
+    Lg, gsg, gpg, _ = _gpu_grad(torch, w, target, kt, "f32", 50, dict(react_sort=sort))
     cos = np.dot(gsg, gso) / (np.linalg.norm(gsg) * np.linalg.norm(gso))
     rel = np.linalg.norm(gsg - gso) / np.linalg.norm(gso)
     assert cos >= 0.999 and rel <= 1e-2, (cos, rel)
