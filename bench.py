@@ -401,6 +401,27 @@ def adjoint_leg(stream, with_accuracy, tune=True):
             "grad_scalings_cosine": float(np.dot(gp[1:], gp64[1:]) /
                                           (np.linalg.norm(gp[1:]) * np.linalg.norm(gp64[1:]))),
             "loss_rel": float(abs(loss - loss64) / loss64)}
+        # a loss whose residuals all have one sign (target = the FP64 run's own
+        # potentials minus 5 mV): no cancellation between sensors and times
+        st = mono.Sim.from_workload(w, "f64", stream=stream.cuda_stream)
+        st.set_sensors(w.sensors, np.zeros((0, ns)))
+        own = st.sample_sensors(n_steps, w.dt, ns)
+        st.close()
+        kt = torch.zeros((n_steps, w.mesh.n_nodes), dtype=torch.uint8, device="cuda")
+        saved = target
+        target = own - 5.0
+        _, _, lo32, gso32, gpo32, _ = run("f32", True, (1, kt))
+        _, _, lo64, gso64, gpo64, _ = run("f64", True, (2, kt))
+        target = saved
+        del kt
+        res["fp32_vs_fp64_one_sign_residuals"] = {
+            "note": "target = FP64 potentials at the sensors minus 5 mV, same k decisions; the "
+                    "scaling gradients of the perturbed-conductivity loss are small remainders "
+                    "of sums whose terms change sign (compare their magnitudes with these)",
+            "grad_scalings_rel": rel(gpo32, gpo64),
+            "grad_scalings": {k: float(gpo64[i]) for i, k in enumerate(names, start=1)},
+            "grad_sigma_rel_l2": float(np.linalg.norm(gso32 - gso64) / np.linalg.norm(gso64)),
+            "loss_rel": float(abs(lo32 - lo64) / lo64)}
         res["fp64_conditioning"] = {
             "note": "FP64 adjoint from the initial state rounded to FP32 against FP64 from the "
                     "exact one (same k decisions): the change an FP32-sized perturbation of the "
@@ -435,6 +456,8 @@ def main():
                     help="skip timing the workload's whole simulated interval")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the FP64, batched and tetrahedral windows")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"],
+                    help="arithmetic of the timed window (f64: FP64 state and operator)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -469,7 +492,9 @@ def main():
     traffic_key = args.workload if args.workload != "tets" or args.order == "rcm" else None
     n = w.mesh.n_nodes
     stream = torch.cuda.Stream()
-    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    prec = args.precision
+    es = 8 if prec == "f64" else 4
+    sim = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream, layout=layout)
     launch = sim.launch()
     info = sim.info()
 
@@ -478,7 +503,7 @@ def main():
     # then the graphs the window replays (graph_steps steps and the remainder
     # of K) are captured outside it
     sim.step(args.warmup, w.dt)
-    if not args.no_tune:
+    if not args.no_tune and prec == "f32":
         from paper_2011_04747_amd import autotune
         launch = autotune.tune(sim, w.dt)
     sim.step(args.steps, w.dt, flags=mono.STEP_CAPTURE)
@@ -516,7 +541,7 @@ def main():
     # simulation repeats the warm-up, then runs the K timed steps one launch at
     # a time, each kernel bracketed by HIP events on the simulation's stream;
     # the substep counts k each node took are read back between steps
-    sim = mono.Sim.from_workload(w, "f32", stream=stream.cuda_stream, layout=layout)
+    sim = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream, layout=layout)
     sim.set_launch(**launch)
     sim.step(args.warmup, w.dt)
     sim.kernel_times(reset=True)
@@ -558,14 +583,7 @@ def main():
     P = info["ell_width"]
     by_class = (info["layout"] == mono.LAYOUT_STENCIL and info["row_classes"] > 0
                 and launch.get("diff_classes", 1))
-    if by_class:
-        row_bytes = 4 + 4 + 2        # V in, V out, class id (table rows stay in cache)
-    elif info["layout"] == mono.LAYOUT_STENCIL:
-        row_bytes = (P + 3) * 4      # own edges, 1/m, V in, V out
-    else:
-        row_bytes = P * 8 + 2 * 4    # (value, column) per slot, V in, V out
-    if info["n_instances"] > 1:
-        row_bytes += 4               # instance id of the row
+    row_bytes = _diff_row_bytes(info, launch, es)
     diff_bytes = n * row_bytes
     # op count of one substep at the library's own initial (resting) state,
     # read from a 4-node simulation
@@ -578,31 +596,35 @@ def main():
     diff_total = 2 * L * d_us * 1e-3
     react_total = r_us * 1e-3
     by_rows = by_class and info["grid_rows"] and launch.get("diff_wave_rows", 1)
+    tname = "double" if prec == "f64" else "float"
+    vpeak = FP64_VECTOR_PEAK_TFLOPS if prec == "f64" else FP32_VECTOR_PEAK_TFLOPS
+    # the committed traffic counters were taken in FP32
+    tkey = traffic_key if prec == "f32" else None
     diff_roof = {"kernel": ("k_diff_rows" if by_rows else "k_diff_classes" if by_class else
                             "k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL
-                            else "k_diff_ell") + f"<float,{P}>",
+                            else "k_diff_ell") + f"<{tname},{P}>",
                  "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
                  "avg_us": d_us, "avg_us_per_launch_events": d_event_us,
-                 "traffic": _traffic("diffusion", traffic_key, launch)}
+                 "traffic": _traffic("diffusion", tkey, launch)}
     diff_roof["frac"] = diff_roof["achieved"] / HBM_PEAK_GBS
-    react_roof = {"kernel": "k_ionic<float,TP06>", "bound": "alu",
-                  "achieved": react_flops / (r_us * 1e-6) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+    react_roof = {"kernel": f"k_ionic<{tname},TP06>", "bound": "alu",
+                  "achieved": react_flops / (r_us * 1e-6) / 1e12, "peak": vpeak,
                   "unit": "TFLOP/s", "ops_per_substep": ops, "substeps_per_launch": ksum / kt_steps,
                   "wavefront_efficiency": ksum / kwave if kwave else None, "avg_us": r_us,
                   "avg_us_per_launch_events": r_event_us,
-                  "traffic": _traffic("reaction", traffic_key, launch)}
-    react_roof["frac"] = react_roof["achieved"] / FP32_VECTOR_PEAK_TFLOPS
+                  "traffic": _traffic("reaction", tkey, launch)}
+    react_roof["frac"] = react_roof["achieved"] / vpeak
     dominant = react_roof if react_total >= diff_total else diff_roof
     roofline = {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
     roofline["kernel"] = dominant["kernel"]
-    if dominant is react_roof:
+    if dominant is react_roof and prec == "f32":
         roofline["peak_plain_valu"] = FP32_PLAIN_VALU_PEAK_TFLOPS
         roofline["frac_plain_valu"] = react_roof["achieved"] / FP32_PLAIN_VALU_PEAK_TFLOPS
 
     # accuracy against the FP64 path (itself checked against the FP64 oracle)
     accuracy = None
-    if not args.no_accuracy:
+    if not args.no_accuracy and prec == "f32":
         total = args.warmup + args.steps
         ref = mono.Sim.from_workload(w, "f64", stream=stream.cuda_stream, layout=layout)
         ref.step(total, w.dt)
@@ -618,17 +640,19 @@ def main():
                     "lat_max_ms": float(np.abs(l32 - l64)[both].max()) if both.any() else None,
                     "activated_equal": bool(((l32 > 0) == (l64 > 0)).all())}
 
+    # the other legs accompany the default FP32 run
+    main_run = args.workload == "slab" and prec == "f32"
     full = None
-    if not args.no_full_run and args.workload == "slab":
+    if not args.no_full_run and main_run:
         full = full_run(w, stream, launch, layout, not args.no_accuracy)
 
     adjoint = None
-    if not args.no_adjoint and args.workload == "slab":
+    if not args.no_adjoint and main_run:
         adjoint = adjoint_leg(stream, not args.no_accuracy, not args.no_tune)
 
     # the same window in FP64, and the batched and tetrahedral workloads
     legs = None
-    if not args.no_legs and args.workload == "slab":
+    if not args.no_legs and main_run:
         legs = {}
         legs["fp64"] = other_leg("fp64", w, "f64", stream, args, layout,
                                  wl_name + ", FP64 state and operator")
@@ -650,7 +674,7 @@ def main():
 
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
            "data": "synthetic",
            "config": {"workload": wl_name, "launch": launch,
                       "nodes": n, "nnz": info["nnz"], "l": info["l"], "dt_ad": info["dt_ad"],
