@@ -89,7 +89,7 @@ typedef enum {
  *           those of TP06_EPI, then a node class (0 epicardial TP06
  *           myocyte, 1 fibroblast), then g_f [1/ms] and E_f [mV] of the
  *           fibroblasts' passive membrane dV/dt = -g_f (V - E_f) (defaults
- *           0.635 and -49.6).  A fibroblast node keeps its other 18 state
+ *           0.0216 and -49.6).  A fibroblast node keeps its other 18 state
  *           rows; its substep count follows the same k rule.  Any class
  *           other than 0 or 1 is EINVAL.  In mono_backward the class row is
  *           a label (gradient entry 0).                                     */

@@ -1075,7 +1075,7 @@ int orc_set_model(void* h, int model, int n_params, const double* params,
     std::memcpy(s->params.data(), params, sizeof(double) * s->P * n);
   } else {
     const double ms[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
-    const double tp6[9] = {5.4, 1, 1, 1, 1, 1, 0, 0.635, -49.6};
+    const double tp6[9] = {5.4, 1, 1, 1, 1, 1, 0, 0.0216, -49.6};
     const double lin[2] = {0.0, 0.0};
     for (int a = 0; a < s->P; ++a) {
       double v = model == M_MS ? ms[a] : (is_tp06(model) ? tp6[a] : lin[a]);

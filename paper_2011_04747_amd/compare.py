@@ -16,6 +16,13 @@ eq. (4) against OST.
 
     python -m paper_2011_04747_amd.compare [--n 501] [--dx 0.01] [--t-end 500]
                                            [--precision f64]
+
+With --fibrotic, the same three methods on the fibrotic sheets of Sec. 3.2
+(the six meshes of Table 1, 5 x 5 cm at h = 200 ... 100 um, 10% passive
+fibroblasts, cross-field S1 at 50 ms and S2 at 200 ms): wall time per method
+and mesh, the stable step of eq. (3), and e_LAT / e_APD against OST.
+
+    python -m paper_2011_04747_amd.compare --fibrotic [--t-end 500] [--precision f64]
 """
 from __future__ import annotations
 
@@ -84,14 +91,52 @@ def compare(n: int = 501, dx: float = 0.01, t_end: float = 500.0,
     return res
 
 
+# elements per side of Table 1's meshes (5 cm at h = 200, 180, 160, 140, 120, 100 um)
+TABLE1_ELEMENTS = (250, 277, 312, 357, 416, 500)
+
+
+def compare_fibrotic(t_end: float = 500.0, precision: str = "f64",
+                     elements=TABLE1_ELEMENTS) -> dict:
+    res = {"workload": f"sheet_fibrotic_tp06, 5x5 cm, 10% passive fibroblasts, S1 50 ms, "
+                       f"S2 200 ms, {t_end} ms, {precision}", "meshes": []}
+    for e in elements:
+        w = W.sheet_fibrotic_tp06(n=e + 1, dx=5.0 / e, t_end=t_end, precision=precision)
+        probe = mono.Sim.from_workload(w, precision)
+        dt_s = probe.info()["dt_s"]
+        probe.close()
+        plan = {"OST": (mono.OST, 0.01), "OSTAR": (mono.OSTAR, min(0.1, dt_s)),
+                "DAETI": (mono.DAETI, 0.1)}
+        runs = {name: run_method(w, m, dt, precision) for name, (m, dt) in plan.items()}
+        ref = runs["OST"]
+        row = {"h_um": 5.0e4 / e, "nodes": w.mesh.n_nodes, "elements": w.mesh.n_elems,
+               "fibroblasts": w.extra["fibroblasts"], "dt_s": dt_s, "methods": {}}
+        for name, r in runs.items():
+            m = {"dt": r["dt"], "steps": r["steps"], "l": r["l"], "k_max": r["k_max"],
+                 "wall_s": r["wall_s"], "activated": int((r["lat"] >= 0).sum())}
+            if name != "OST":
+                m["e_lat"] = mono.nrmse(r["lat"], ref["lat"])
+                m["e_apd"] = mono.nrmse(r["apd"], ref["apd"])
+                m["speedup_vs_ost"] = ref["wall_s"] / r["wall_s"]
+            row["methods"][name] = m
+        row["methods"]["DAETI"]["speedup_vs_ostar"] = (runs["OSTAR"]["wall_s"]
+                                                       / runs["DAETI"]["wall_s"])
+        res["meshes"].append(row)
+    return res
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=501)
     ap.add_argument("--dx", type=float, default=0.01)
     ap.add_argument("--t-end", type=float, default=500.0)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--fibrotic", action="store_true",
+                    help="the fibrotic sheets of Table 1 instead of the planar sheet")
     a = ap.parse_args(argv)
-    print(json.dumps(compare(a.n, a.dx, a.t_end, a.precision)), flush=True)
+    if a.fibrotic:
+        print(json.dumps(compare_fibrotic(a.t_end, a.precision)), flush=True)
+    else:
+        print(json.dumps(compare(a.n, a.dx, a.t_end, a.precision)), flush=True)
     return 0
 
 

@@ -77,7 +77,7 @@ const double kTP06Init[19] = {-86.2, 138.3, 7.67, 0.00007, 0.00007, 1.3, 1.0, 0.
 const double kMSParams[5] = {0.3, 6.0, 120.0, 150.0, 0.13};
 // rows 6..8: cell type or node class, fibroblast membrane rate g_f [1/ms] and
 // reversal potential E_f [mV]
-const double kTP06Params[9] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0, 0.635, -49.6};
+const double kTP06Params[9] = {5.4, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0, 0.0216, -49.6};
 
 bool is_tp06(int m) {
   return m == MONO_MODEL_TP06_EPI || m == MONO_MODEL_TP06_TYPES || m == MONO_MODEL_TP06_FIBRO;

@@ -42,10 +42,11 @@ CELL_M = 2
 # node classes of MODEL_TP06_FIBRO
 NODE_MYOCYTE = 0
 NODE_FIBROBLAST = 1
-# passive fibroblast membrane: rate g_f = G_f / C_f [1/ms] and reversal
-# potential E_f [mV] (rows 7 and 8 of MODEL_TP06_FIBRO)
+# passive fibroblast membrane (rows 7 and 8 of MODEL_TP06_FIBRO): rate g_f
+# [1/ms], a 4 nS membrane conductance over the myocytes' 185 pF (the tissue
+# capacitance of the monodomain), and reversal potential E_f [mV]
 FIBRO_PARAM_NAMES = ("g_f", "E_f")
-FIBRO_PARAM_DEFAULT = (0.635, -49.6)
+FIBRO_PARAM_DEFAULT = (0.0216, -49.6)
 
 ETYPE_LINE2 = 2
 ETYPE_TRI3 = 3

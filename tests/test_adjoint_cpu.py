@@ -97,7 +97,7 @@ def test_library_substep_vjp_matches_finite_differences(model, S, P, trial):
             p = np.append(p, (W.CELL_EPI, W.CELL_ENDO, W.CELL_M)[trial % 3])
         if model == 4:
             p = np.append(p, [(W.NODE_MYOCYTE, W.NODE_FIBROBLAST)[trial % 2],
-                              0.635 * rng.uniform(0.7, 1.3), -49.6 * rng.uniform(0.7, 1.3)])
+                              0.0216 * rng.uniform(0.7, 1.3), -49.6 * rng.uniform(0.7, 1.3)])
     elif model == 1:
         p = np.array(W.MS_PARAM_DEFAULT)
         y[0] = (0.05, 0.08, 0.3, 0.6, 0.9, 0.95)[trial]      # away from v_gate

@@ -130,3 +130,21 @@ def test_method_comparison_driver(torch):
         assert np.isfinite(m["e_apd"])
     assert r["methods"]["OST"]["k_max"] == 1 and r["methods"]["OST"]["l"] == 1
     assert r["methods"]["DAETI"]["l"] >= 1
+
+
+def test_fibrotic_comparison_driver(torch):
+    """The three methods on a small fibrotic sheet (Sec. 3.2's protocol on a
+    5 x 5 cm sheet of 101 x 101 nodes): every node activates under every method, the
+    node and element counts follow the mesh, DAETI and OSTAR stay close to
+    OST in activation time, and DAETI takes the adaptive diffusion step."""
+    from paper_2011_04747_amd.compare import compare_fibrotic
+    r = compare_fibrotic(t_end=260.0, precision="f64", elements=(100,))
+    (row,) = r["meshes"]
+    assert row["nodes"] == 101 * 101 and row["elements"] == 100 * 100
+    assert row["fibroblasts"] == round(0.1 * 101 * 101)
+    for name, m in row["methods"].items():
+        assert m["activated"] == row["nodes"], name
+    for name in ("DAETI", "OSTAR"):
+        assert row["methods"][name]["e_lat"] < 0.05, name
+    assert row["methods"]["OST"]["k_max"] == 1
+    assert row["methods"]["DAETI"]["dt"] == 0.1

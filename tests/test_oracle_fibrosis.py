@@ -18,7 +18,7 @@ import pytest
 from paper_2011_04747_amd import workloads as W
 
 
-def _p(cls, g=0.635, E=-49.6):
+def _p(cls, g=W.FIBRO_PARAM_DEFAULT[0], E=W.FIBRO_PARAM_DEFAULT[1]):
     return np.concatenate([np.asarray(W.TP06_PARAM_DEFAULT, float), [cls, g, E]])
 
 
