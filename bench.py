@@ -55,7 +55,7 @@ def _traffic(kernel, workload, launch):
     with open(p) as f:
         t = json.load(f)
     keys = {"diffusion": ("diff_block", "diff_rows_per_lane", "diff_xcd_remap", "diff_classes",
-                          "diff_wave_rows"),
+                          "diff_wave_rows", "diff_fuse", "diff_fuse_planes"),
             "reaction": ("react_block", "react_sort")}[kernel]
     tl = t.get("launch") or {}
     if t.get("bench_workload") != workload or any(tl.get(k) != launch.get(k) for k in keys):
@@ -232,6 +232,7 @@ def other_leg(kind, w, prec, stream, args, layout, name):
            "ms_per_step": r["ms_per_step"], "repeats_ms": r["repeats_ms"], "launch": launch,
            "l": r["L"], "mean_k": r["mean_k"],
            "diffusion": {"avg_us": r["diffusion_us"], "bytes_per_row": row_b,
+                         "launches_per_half_step": info["diff_launches"] or r["L"],
                          "achieved_GBs": w.mesh.n_nodes * row_b / (r["diffusion_us"] * 1e-6) / 1e9,
                          "frac_hbm": w.mesh.n_nodes * row_b / (r["diffusion_us"] * 1e-6) / 1e9
                          / HBM_PEAK_GBS,
@@ -600,13 +601,30 @@ def main():
     vpeak = FP64_VECTOR_PEAK_TFLOPS if prec == "f64" else FP32_VECTOR_PEAK_TFLOPS
     # the committed traffic counters were taken in FP32
     tkey = traffic_key if prec == "f32" else None
-    diff_roof = {"kernel": ("k_diff_rows" if by_rows else "k_diff_classes" if by_class else
-                            "k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL
-                            else "k_diff_ell") + f"<{tname},{P}>",
-                 "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
-                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
-                 "avg_us": d_us, "avg_us_per_launch_events": d_event_us,
-                 "traffic": _traffic("diffusion", tkey, launch)}
+    launches = info["diff_launches"] or L            # diffusion launches per half step
+    fused = launches < L
+    if fused:
+        # L substeps in `launches` launches of the fused kernel: each reads V,
+        # the class ids and writes V once (the substeps in between stay on
+        # chip); its per-substep figure is what L unfused launches would move
+        per_launch_us = d_us * L / launches
+        fused_bytes = n * (2 * es + 2)
+        diff_roof = {"kernel": f"k_diff_fused<{tname},{L // launches}>", "bound": "hbm",
+                     "achieved": fused_bytes / (per_launch_us * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": 2 * es + 2,
+                     "substeps_per_launch": L / launches, "launches_per_half_step": launches,
+                     "avg_us": per_launch_us, "avg_us_per_substep": d_us,
+                     "unfused_equivalent_GBs": diff_bytes / (d_us * 1e-6) / 1e9,
+                     "avg_us_per_launch_events": d_event_us,
+                     "traffic": _traffic("diffusion", tkey, launch)}
+    else:
+        diff_roof = {"kernel": ("k_diff_rows" if by_rows else "k_diff_classes" if by_class else
+                                "k_diff_stencil" if info["layout"] == mono.LAYOUT_STENCIL
+                                else "k_diff_ell") + f"<{tname},{P}>",
+                     "bound": "hbm", "achieved": diff_bytes / (d_us * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "bytes_per_row": row_bytes,
+                     "avg_us": d_us, "avg_us_per_launch_events": d_event_us,
+                     "traffic": _traffic("diffusion", tkey, launch)}
     diff_roof["frac"] = diff_roof["achieved"] / HBM_PEAK_GBS
     react_roof = {"kernel": f"k_ionic<{tname},TP06>", "bound": "alu",
                   "achieved": react_flops / (r_us * 1e-6) / 1e12, "peak": vpeak,

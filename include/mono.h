@@ -165,6 +165,12 @@ typedef struct {
                           diffusion can read rows by class, else 0             */
   int32_t grid_rows;   /* 1 when the stencil offsets are those of a structured
                           grid numbered x fastest (row-sharing diffusion)      */
+  int32_t diff_fused;  /* 1 when the grid is a whole 3D nx x ny x nz block
+                          with no weight past its faces and row ends, so the
+                          fused half-step diffusion (mono_launch.diff_fuse)
+                          can run on it                                       */
+  int32_t diff_launches; /* diffusion launches per half step under the current
+                          launch shape and prepared l (0 before mono_prepare) */
 } mono_info;
 
 /* Assemble K and the row-sum lumped mass M_L of the FE diffusion problem
@@ -261,7 +267,7 @@ mono_status mono_nrmse(const double *u_hat, const double *u, int64_t n, double *
  * and check dt_ad < 2/lambda_est for the last prepared dt. */
 mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
 
-/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32, 0, 1, 1).  Block
+/* Launch shapes of a simulation (defaults: 256, 1, 1, 256, 32, 0, 1, 1, 0, 0).  Block
  * sizes 128, 256 or 512 lanes (the FP32 reaction also 1024); rows per lane of the stencil diffusion kernel
  * 1, 2 or 4 (FP64: 1 or 2; ignored by the ELL layout); XCD remap 0/1 (deal
  * contiguous row ranges to each of the 8 XCDs); graph_steps 1..8192 outer
@@ -274,8 +280,15 @@ mono_status mono_estimate_lambda(mono_sim *sim, int32_t iters);
  * rows per lane (1, 2, 4, 8 or 16, any precision) count the rows each lane
  * sweeps in turn; diff_wave_rows 0/1 (default 1): with row classes on a
  * structured grid (mono_info.grid_rows) a wavefront loads each neighbouring
- * grid row once and passes x-neighbours between lanes.
- * Results do not depend on the shape (bitwise). */
+ * grid row once and passes x-neighbours between lanes; diff_fuse 0/1
+ * (default 0): on a 3D structured grid that takes it (mono_info.diff_fused)
+ * with row classes in use, up to 4 of the l substeps of a half step run in one
+ * launch (temporal blocking: a workgroup marches z through a tile widened by
+ * one node per fused substep on every side, keeping the intermediate levels
+ * in LDS); a half step takes ceil(l / 4) such launches when l >= 2;
+ * diff_fuse_planes 0..4096: z planes each workgroup of that kernel produces
+ * (0 = chosen from the grid so that the launch fills the chip).
+ * Results do not depend on the shape (bitwise, for finite potentials). */
 typedef struct {
   int32_t diff_block;
   int32_t diff_rows_per_lane;
@@ -285,6 +298,8 @@ typedef struct {
   int32_t react_sort;
   int32_t diff_classes;
   int32_t diff_wave_rows;
+  int32_t diff_fuse;
+  int32_t diff_fuse_planes;
 } mono_launch;
 mono_status mono_set_launch(mono_sim *sim, const mono_launch *cfg);
 mono_status mono_get_launch(mono_sim *sim, mono_launch *out);
@@ -424,9 +439,11 @@ mono_status mono_backward(mono_sim *sim, double *grad_sigma, double *grad_params
  *  MONO_DEBUG_TIME_DIFFUSION: arg -> double[2]; arg[0] = an even number R
  *      of repetitions on entry; runs R diffusion substeps (the first
  *      substep of the first half step at the current time level, alternating
- *      between the two potential buffers) captured in one HIP graph, timed
- *      by events around the graph launch, and returns the mean ms per
- *      substep in arg[1].  The potential is advanced by those R substeps:
+ *      between the two potential buffers; where the half steps run fused,
+ *      about R / l first half steps launched as stepping launches them, an
+ *      even number of launches) captured in one HIP graph, timed by events
+ *      around the graph launch, and returns the mean ms per substep in
+ *      arg[1].  The potential is advanced by those R substeps:
  *      for benchmarking simulations only.  Synchronising; needs
  *      mono_prepare. */
 enum {

@@ -4,12 +4,16 @@ Searches, on the simulation it is given and at its current state:
   * diffusion kernel: workgroup size (128/256/512), stencil rows per lane
     (1/2/4; vector loads of the streamed arrays), rows read by class, rows by
     class sharing neighbour rows across lanes (1/2/4 row groups per
-    wavefront), and the XCD row remap;
+    wavefront), and the XCD row remap; on 3D grids that take it, the fused
+    half-step kernel (several substeps per launch) and its z planes per
+    workgroup;
   * reaction kernel: workgroup size, and whether each workgroup orders its
     nodes by substep count k before advancing them;
   * outer steps per captured HIP graph.
 Kernel candidates are timed with the library's per-kernel HIP events
-(MONO_STEP_TIMED), graph sizes by the wall time of whole steps.  The state is
+(MONO_STEP_TIMED): diffusion shapes by their time per outer step (fused and
+unfused launches do different amounts of work each), reaction shapes per
+launch; graph sizes by the wall time of whole steps.  The state is
 saved before and restored after, and launch shapes do not change results, so
 tuning leaves the simulation exactly as it was.  The choice is cached as JSON
 keyed by GPU architecture and problem signature.
@@ -41,7 +45,7 @@ def signature(sim: mono.Sim) -> str:
     i = sim.info()
     lay = "stencil" if i["layout"] == mono.LAYOUT_STENCIL else "ell"
     return (f"{_arch()}_{sim.precision}_{lay}{i['ell_width']}_m{sim.model}_n{sim.n}"
-            f"_i{i['n_instances']}_nnz{i['nnz']}")
+            f"_i{i['n_instances']}_nnz{i['nnz']}" + ("_fz" if i["diff_fused"] else ""))
 
 
 def _snapshot(sim: mono.Sim):
@@ -58,10 +62,11 @@ def _restore(sim: mono.Sim, snap):
 
 
 def _time_kernels(sim, dt, steps):
+    """Diffusion ms per outer step and reaction ms per launch."""
     sim.kernel_times(reset=True)
     sim.step(steps, dt, flags=mono.STEP_TIMED)
     k = sim.kernel_times(reset=True)
-    d = k["diffusion_ms"] / max(1, k["diffusion_launches"])
+    d = k["diffusion_ms"] / steps
     r = k["reaction_ms"] / max(1, k["reaction_launches"])
     return d, r
 
@@ -99,7 +104,7 @@ def tune(sim: mono.Sim, dt: float, steps: int = 8, use_cache: bool = True,
             for xcd in (0, 1):
                 sim.set_launch(diff_block=blk, diff_rows_per_lane=rpl, diff_xcd_remap=xcd,
                                diff_classes=cls, diff_wave_rows=rows, react_block=blk,
-                               react_sort=0)
+                               react_sort=0, diff_fuse=0)
                 _restore(sim, snap)
                 d, r = _time_kernels(sim, dt, steps)
                 trials.append({"diff_block": blk, "classes": cls, "wave_rows": rows, "rpl": rpl,
@@ -113,7 +118,20 @@ def tune(sim: mono.Sim, dt: float, steps: int = 8, use_cache: bool = True,
     best = dict(base)
     best.update(diff_block=best_d[1], diff_rows_per_lane=best_d[2], diff_xcd_remap=best_d[3],
                 diff_classes=best_d[4], diff_wave_rows=best_d[5], react_block=best_r[1],
-                react_sort=0)
+                react_sort=0, diff_fuse=0, diff_fuse_planes=0)
+    # the fused half step (it reads rows by class); z planes per workgroup,
+    # 0 = the library's choice
+    if info["diff_fused"] and info["l"] >= 2:
+        for planes in (0, 4, 8, 16, 32):
+            sim.set_launch(**dict(best, diff_classes=1, diff_fuse=1, diff_fuse_planes=planes))
+            _restore(sim, snap)
+            d, _ = _time_kernels(sim, dt, steps)
+            trials.append({"diff_fuse": 1, "diff_fuse_planes": planes, "diff_ms": d})
+            if verbose:
+                print("tune", trials[-1], flush=True)
+            if d < best_d[0]:
+                best_d = (d,) + best_d[1:]
+                best.update(diff_classes=1, diff_fuse=1, diff_fuse_planes=planes)
     sort_blocks = (256, 512, 1024) if sim.precision == "f32" else (256, 512)
     for blk in sort_blocks:
         sim.set_launch(**dict(best, react_block=blk, react_sort=1))

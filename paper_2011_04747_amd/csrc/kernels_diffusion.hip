@@ -112,6 +112,13 @@ __device__ __forceinline__ uint32_t open_stimuli(const DiffArgs<T>& a, double dt
   }
   return active;
 }
+// The same for substep m of this launch's half step.
+template <typename T>
+__device__ __forceinline__ uint32_t open_stimuli_at(const DiffArgs<T>& a, double dt_ad, int m) {
+  DiffArgs<T> b = a;
+  b.m = m;
+  return open_stimuli(b, dt_ad);
+}
 // summed amplitude of the open stimuli that include node i
 template <typename T>
 __device__ __forceinline__ T stimulus_sum(const DiffArgs<T>& a, uint32_t active, int64_t i) {
@@ -334,6 +341,18 @@ __device__ __forceinline__ T ld_raw(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
+// One potential stored by a raw buffer store at byte offset off (dropped
+// outside the buffer's range).
+template <typename T>
+__device__ __forceinline__ void st_raw(__amdgpu_buffer_rsrc_t r, uint32_t off, T v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((__vector_size__(8))) unsigned int, v), r, (int)off, 0,
+        0);
+}
+
 template <typename T, int P, int BLOCK, int ITER>
 __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __restrict__ ctab,
                                                      const int32_t* __restrict__ wcls) {
@@ -426,6 +445,241 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// L consecutive substeps (m0 .. m0+L-1 of a half step) in one launch, for
+// structured 3D grids with row classes and one instance: temporal blocking.
+// A workgroup owns a tile of 64 - 2L consecutive x, ty = 16 - 2L y rows and
+// tz z planes.  Its 16 wavefronts are the tile's y rows widened by L on each
+// side (a wavefront's lanes cover x - L .. x + 63 - L), and together they
+// march z through the tile's planes widened by L.  Level t (the potential
+// after t of the L substeps) of a plane is computed as soon as level t - 1
+// holds the plane after it: from level t - 1 of the three planes around it,
+// of which each wavefront keeps its own row in registers and shares it with
+// the rows above and below through a ring of three planes per level in LDS;
+// x-neighbours come from adjacent lanes (DPP) as in the row-sharing kernel.
+// Level t is exact on a region one node smaller on every side than level
+// t - 1, so after L levels the tile's own nodes are.  Nodes outside the grid
+// hold 0; the host admits a grid only when no weight joins a node to a
+// position outside it (row ends, faces), so those zeros only ever meet zero
+// weights, as the wrapped neighbours of the row-sharing kernel do.  Every
+// node's arithmetic (weights, order, stimulus) is that of k_diff_rows: for
+// finite potentials the result is the same bits as L launches of it.
+// ---------------------------------------------------------------------------
+constexpr int kFusedClassSweeps = 4;
+
+template <typename T, int L>
+__global__ __launch_bounds__(kFusedRows * 64) void k_diff_fused(DiffArgs<T> a,
+                                                                const T* __restrict__ ctab,
+                                                                FusedGeom g) {
+  constexpr int P = 13;
+  constexpr int NY = kFusedRows;           // wavefronts = y rows of the window
+  constexpr int W = 64;
+  constexpr int PF = 3;                    // planes loaded ahead of their use
+  using RP = RowPattern<P>;
+  __shared__ T ring[L][3][NY][W];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  int b = blockIdx.x;
+  const int xs = b % g.nxs;
+  b /= g.nxs;
+  const int ys = b % g.nys;
+  const int zs = b / g.nys;
+  const int x = xs * (W - 2 * L) - L + lane;
+  const int y = ys * (NY - 2 * L) - L + wv;  // wavefront-uniform
+  const int NZ = g.tz + 2 * L;
+  const int z0 = zs * g.tz - L;
+  const bool xin = x >= 0 && x < g.nx;
+  const bool yin = y >= 0 && y < g.ny;
+  const int nxy = g.nx * g.ny;
+  const double dt_ad = a.dt_ad[0];
+  const T hT = (T)dt_ad;
+  const bool stim = a.stim_mask != nullptr;
+  uint32_t open[L];                        // stimuli open on each substep
+#pragma unroll
+  for (int t = 0; t < L; ++t) open[t] = open_stimuli_at(a, dt_ad, a.m + t);
+  // Loads and the final store go through buffer resources over the n rows:
+  // a node outside the grid takes an offset past the end, which reads 0 and
+  // drops the store, so no access depends on a branch and the loads of later
+  // planes stay in flight across the levels.
+  const int n = (int)a.n;
+  constexpr int ES = (int)sizeof(T);
+  constexpr uint32_t kOut = 0x80000000u;   // past every buffer (n * ES < 2^31)
+  const __amdgpu_buffer_rsrc_t rv =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.Vin, (short)0, n * ES, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ro =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.Vout, (short)0, n * ES, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.cls, (short)0, n * 2, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rm =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.stim_mask, (short)0, stim ? n : 0, 0x00020000);
+  // this lane's node of window plane zz: value, class and stimulus mask
+  auto fetch = [&](int zz, T& v, unsigned short& c, unsigned char& mk) {
+    const int z = z0 + zz;
+    const bool in = zz < NZ && xin && yin && z >= 0 && z < g.nz;
+    const uint32_t i = in ? (uint32_t)(x + g.nx * y + nxy * z) : kOut;
+    v = ld_raw<T>(rv, (int)(in ? i * (uint32_t)ES : kOut));
+    c = __builtin_amdgcn_raw_buffer_load_b16(rc, (int)(in ? 2u * i : kOut), 0, 0);
+    mk = __builtin_amdgcn_raw_buffer_load_b8(rm, (int)i, 0, 0);
+  };
+  // planes s, s+1, s+2 in flight, plane s in slot s % 3 (the march is
+  // unrolled by 3, so no loaded register is ever moved: a move would wait for
+  // its load)
+  T pv[PF];
+  unsigned short pc[PF];
+  unsigned char pm[PF];
+#pragma unroll
+  for (int q = 0; q < PF; ++q) fetch(q, pv[q], pc[q], pm[q]);
+  // own row: level t of plane p in own[t][p % 3]
+  T own[L][3];
+  int cr[L + 1];          // class and stimulus mask of this lane's node at
+  uint32_t mr[L + 1];     // planes s, s-1, ..., s-L
+#pragma unroll
+  for (int t = 0; t < L; ++t) own[t][0] = own[t][1] = own[t][2] = T(0);
+#pragma unroll
+  for (int j = 0; j <= L; ++j) {
+    cr[j] = 0;
+    mr[j] = 0u;
+  }
+  auto plane = [&](int s, auto U) {
+    constexpr int u = decltype(U)::value;   // s % 3
+    // level 0 of plane s, and the load of plane s + 3 into its slot
+#pragma unroll
+    for (int j = L; j > 0; --j) {
+      cr[j] = cr[j - 1];
+      mr[j] = mr[j - 1];
+    }
+    cr[0] = (int)pc[u];
+    mr[0] = (uint32_t)pm[u];
+    own[0][u] = pv[u];
+    ring[0][u][wv][lane] = pv[u];
+    fetch(s + PF, pv[u], pc[u], pm[u]);     // past the window: no access, 0
+    __syncthreads();
+#pragma unroll
+    for (int t = 1; t <= L; ++t) {
+      const int zz = s - t;
+      // ring slots of planes zz - 1, zz, zz + 1
+      const int s0 = (u - t % 3 + 3) % 3, sm = (s0 + 2) % 3, sp = (s0 + 1) % 3;
+      T out = T(0);
+      T vL = T(0);                           // level L: the value and where it goes
+      uint32_t offL = kOut;
+      if (zz >= t && zz < NZ - t && wv >= t && wv < NY - t) {
+        const int z = z0 + zz;
+        const bool in = xin && yin && z >= 0 && z < g.nz;
+        // level t-1 around (zz, this row): the row centres of RowPattern<13>
+        // (0; y+1; z+1 y-1; z+1; z+1 y+1; y-1; z-1 y+1; z-1; z-1 y-1)
+        T vc[9];
+        vc[0] = own[t - 1][s0];
+        vc[1] = ring[t - 1][s0][wv + 1][lane];
+        vc[2] = ring[t - 1][sp][wv - 1][lane];
+        vc[3] = own[t - 1][sp];
+        vc[4] = ring[t - 1][sp][wv + 1][lane];
+        vc[5] = ring[t - 1][s0][wv - 1][lane];
+        vc[6] = ring[t - 1][sm][wv + 1][lane];
+        vc[7] = own[t - 1][sm];
+        vc[8] = ring[t - 1][sm][wv - 1][lane];
+        auto pick = [&](int k, int d) -> T {
+          return d > 0 ? lane_shift<1>(vc[k]) : (d < 0 ? lane_shift<-1>(vc[k]) : vc[k]);
+        };
+        const T vi = vc[0];
+        T df[P], db[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          df[p] = pick(RP::fk(p), RP::fd(p)) - vi;
+          db[p] = pick(RP::bk(p), RP::bd(p)) - vi;
+        }
+        auto sweep = [&](auto w) {
+          T acc = T(0);
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            acc += w[p] * df[p];
+            acc += w[P + p] * db[p];
+          }
+          return acc;
+        };
+        // weights by class: one sweep per class among the nodes this level
+        // keeps, its table row read by scalar loads, each lane taking the
+        // sweep of its own class; lanes left after kFusedClassSweeps classes
+        // read their rows per lane
+        const int c = cr[t];
+        const bool keep = in && lane >= t && lane < W - t;
+        unsigned long long rem = __ballot(keep);
+        T acc = T(0), mv = T(0);
+        for (int q = 0; q < kFusedClassSweeps && rem; ++q) {
+          const int cu = __builtin_amdgcn_readlane(c, __ffsll((long long)rem) - 1);
+          using CT = const __attribute__((address_space(4))) T*;
+          const CT w = (CT)(ctab + (uint32_t)(cu * a.tw));
+          const T r = sweep(w);
+          const T m = w[2 * P];
+          // lanes of this class, taken from the ballot (so that the sweep
+          // keeps its scalar table row)
+          const unsigned long long mm = __ballot(c == cu);
+          const bool mine = (mm >> lane) & 1ull;
+          acc = mine ? r : acc;
+          mv = mine ? m : mv;
+          rem &= ~mm;
+        }
+        if (rem) {
+          const T* w = ctab + (uint32_t)(c * a.tw);
+          const T r = sweep(w);
+          const T m = w[2 * P];
+          const bool left = (rem >> lane) & 1ull;
+          acc = left ? r : acc;
+          mv = left ? m : mv;
+        }
+        T sr = T(0);
+        const uint32_t mk = mr[t] & open[t - 1];
+        if (mk)
+          for (int q = 0; q < a.stim.n; ++q)
+            if (mk & (1u << q)) sr += (T)a.stim.amp[q];
+        const T v = vi + hT * (mv * acc + sr);
+        out = in ? v : T(0);
+        if (t < L) {
+          ring[t][s0][wv][lane] = out;
+        } else {
+          // the tile's own nodes (wv and zz are wavefront-uniform)
+          const bool own_node = in && lane >= L && lane < W - L && wv >= L && wv < NY - L &&
+                                zz >= L && zz < NZ - L;
+          vL = v;
+          offL = own_node ? (uint32_t)(x + g.nx * y + nxy * z) * (uint32_t)ES : kOut;
+        }
+      }
+      if (t < L) {
+        own[t][s0] = out;
+        __syncthreads();
+      } else {
+        // one store per plane and lane, outside the branch (dropped off the
+        // tile), so that every plane issues the same memory operations
+        st_raw<T>(ro, offL, vL);
+      }
+    }
+  };
+  for (int s = 0; s < NZ; s += 3) {
+    plane(s, std::integral_constant<int, 0>{});
+    if (s + 1 < NZ) plane(s + 1, std::integral_constant<int, 1>{});
+    if (s + 2 < NZ) plane(s + 2, std::integral_constant<int, 2>{});
+  }
+}
+
+template <typename T, int L>
+static void launch_fused_k(const DiffArgs<T>& a, const FusedGeom& g, hipStream_t s) {
+  const dim3 grid((unsigned)(g.nxs * g.nys * g.nzs));
+  launch_step_kernel(k_diff_fused<T, L>, grid, dim3(kFusedRows * 64), s, a, a.ctab, g);
+}
+
+template <typename T>
+void launch_diffusion_fused(const DiffArgs<T>& a, int L, const FusedGeom& g, hipStream_t s) {
+  if (a.n <= 0) return;
+  switch (L) {
+    case 2: launch_fused_k<T, 2>(a, g, s); return;
+    case 3: launch_fused_k<T, 3>(a, g, s); return;
+    default: launch_fused_k<T, 4>(a, g, s); return;
+  }
+}
+template void launch_diffusion_fused<float>(const DiffArgs<float>&, int, const FusedGeom&,
+                                            hipStream_t);
+template void launch_diffusion_fused<double>(const DiffArgs<double>&, int, const FusedGeom&,
+                                             hipStream_t);
 
 template <typename T, int P, int BLOCK, int ITER>
 static void launch_rows_k(const DiffArgs<T>& a, hipStream_t s) {

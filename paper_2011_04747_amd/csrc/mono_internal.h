@@ -108,6 +108,8 @@ struct LaunchCfg {
   int react_sort = 0;     // reaction nodes ordered by k within a workgroup
   int diff_classes = 1;   // diffusion from row classes when the mesh has them
   int diff_wave_rows = 1; // class diffusion sharing neighbour rows across lanes
+  int diff_fuse = 0;      // up to 4 substeps of a half step per launch (3D grids)
+  int diff_fuse_planes = 0;  // z planes per workgroup of the fused kernel, 0 = auto
 };
 
 // keys of the in-workgroup ordering of the reaction by k: k = 0..kSortMaxK-1
@@ -117,6 +119,14 @@ constexpr int kSortMaxK = 16;
 // rows produced per wavefront by the row-sharing diffusion (lanes 1..62; lanes
 // 0 and 63 hold the neighbouring rows)
 constexpr int kWaveRows = 62;
+// fused half-step diffusion (structured 3D grids): wavefronts (y rows) per
+// workgroup and the tiling of the grid
+constexpr int kFusedRows = 16;
+struct FusedGeom {
+  int nx, ny, nz;      // grid
+  int ty, tz;          // y rows and z planes each workgroup produces
+  int nxs, nys, nzs;   // workgroups along x, y and z
+};
 constexpr int32_t kNoClass = -1;
 
 struct StimTable {
@@ -292,6 +302,10 @@ void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, 
 
 template <typename T>
 void launch_diffusion(int layout, const DiffArgs<T>& a, const LaunchCfg& c, hipStream_t s);
+// L = 2..4 substeps a.m .. a.m+L-1 of a half step in one launch (3D grid
+// stencils that the host admitted); Vin and Vout must differ.
+template <typename T>
+void launch_diffusion_fused(const DiffArgs<T>& a, int L, const FusedGeom& g, hipStream_t s);
 
 template <typename T>
 void launch_ionic(int model, const IonArgs<T>& a, const LaunchCfg& c, hipStream_t s);

@@ -120,6 +120,9 @@ struct mono_sim {
   int tw = 0, n_classes = 0;
   int row_pattern = 0;             // stencil offsets are grid row triples
   int grid_nx = 0, grid_nxy = 0;   // their y-row and z-plane offsets
+  int grid_ny = 0, grid_nz = 0;    // a 3D grid's rows per plane and planes
+  int fuse_ok = 0;                 // the grid admits the fused half-step diffusion
+  int n_cu = 0;                    // compute units of the device
   int32_t* d_wcls = nullptr;       // per-wavefront class of the row-sharing diffusion
   void* d_minv = nullptr;
   int32_t* d_off = nullptr;
@@ -252,6 +255,31 @@ bool grid_row_pattern(const std::vector<int32_t>& off) {
     return true;
   }
   return false;
+}
+
+// Whether a single-instance 13-offset grid stencil can take the fused
+// half-step diffusion: the n rows are a whole nx x ny x nz grid (32-bit byte
+// offsets), and no nonzero weight joins a node to a position outside the grid
+// (past a row end, a face): the fused kernel holds 0 there.
+bool fused_grid_ok(const StencilHost& sh, int64_t n, int64_t Np, size_t es, int64_t nx,
+                   int64_t nxy) {
+  if (sh.P != 13 || (int64_t)sh.off.size() != 13 || nx < 1 || nxy < nx || nxy % nx ||
+      n % nxy || n * (int64_t)es >= ((int64_t)1 << 31))
+    return false;
+  const int64_t ny = nxy / nx, nz = n / nxy;
+  // grid step of each forward offset (the order of the 13-offset pattern)
+  static const int d[13][3] = {{1, 0, 0},  {-1, 1, 0},  {0, 1, 0},  {1, 1, 0},  {-1, -1, 1},
+                               {0, -1, 1}, {1, -1, 1},  {-1, 0, 1}, {0, 0, 1},  {1, 0, 1},
+                               {-1, 1, 1}, {0, 1, 1},   {1, 1, 1}};
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t x = i % nx, y = (i / nx) % ny, z = i / nxy;
+    for (int p = 0; p < 13; ++p) {
+      const int64_t xj = x + d[p][0], yj = y + d[p][1], zj = z + d[p][2];
+      const bool inside = xj >= 0 && xj < nx && yj >= 0 && yj < ny && zj >= 0 && zj < nz;
+      if (!inside && sh.e[(size_t)p * Np + i] != 0.0) return false;
+    }
+  }
+  return true;
 }
 
 mono_status upload_real(mono_sim* s, void* dst, const double* src, size_t count) {
@@ -428,6 +456,75 @@ IonArgs<T> ion_args(mono_sim* s, void* V, int64_t g) {
   return a;
 }
 
+// Whether the half steps run fused: a grid that takes it, row classes in
+// use, one instance and at least two substeps per half step.
+bool use_fused(const mono_sim* s) {
+  return s->fuse_ok && s->lc.diff_fuse && s->lc.diff_classes && s->d_cls && s->n_inst == 1 &&
+         s->l_max >= 2;
+}
+
+// Diffusion launches per half step: ceil(l / 4) fused launches, else l.
+int diff_launches_per_half(const mono_sim* s) {
+  return use_fused(s) ? (s->l_max + 3) / 4 : s->l_max;
+}
+
+// Tiling of a fused launch of L substeps: 64 - 2L x per workgroup, 16 - 2L y
+// rows, and z planes as set, else the split of z that minimises the planes
+// each compute unit marches (workgroups per compute unit, rounded up, times
+// the planes of one tile with its 2L halo planes).
+FusedGeom fused_geom(const mono_sim* s, int L) {
+  FusedGeom g{};
+  g.nx = s->grid_nx;
+  g.ny = s->grid_ny;
+  g.nz = s->grid_nz;
+  g.ty = kFusedRows - 2 * L;
+  g.nxs = (g.nx + 63 - 2 * L) / (64 - 2 * L);
+  g.nys = (g.ny + g.ty - 1) / g.ty;
+  int tz = s->lc.diff_fuse_planes;
+  if (tz <= 0) {
+    const int64_t xy = (int64_t)g.nxs * g.nys;
+    int64_t best = INT64_MAX;
+    for (int nzs = 1; nzs <= g.nz; ++nzs) {
+      const int t = (g.nz + nzs - 1) / nzs;
+      const int64_t blocks = xy * ((g.nz + t - 1) / t);
+      const int64_t cost = (blocks + s->n_cu - 1) / s->n_cu * (t + 2 * L);
+      if (cost < best) {
+        best = cost;
+        tz = t;
+      }
+    }
+  }
+  g.tz = std::min(tz, g.nz);
+  g.nzs = (g.nz + g.tz - 1) / g.tz;
+  return g;
+}
+
+// One half step's diffusion (half 0 or 1) at clock offset g, reading the
+// potential buffer d_V[cur] and leaving cur at the buffer that holds the
+// result; mark(0) is called before each launch (kernel timing).
+template <typename T, typename Mark>
+void enqueue_half(mono_sim* s, int half, int64_t g, int& cur, Mark&& mark) {
+  const int L = s->l_max;
+  if (use_fused(s)) {
+    const int nch = (L + 3) / 4;
+    int m = 0;
+    for (int c = 0; c < nch; ++c) {
+      const int len = (L - m) / (nch - c);
+      mark(0);
+      launch_diffusion_fused<T>(diff_args<T>(s, cur, half, m, g), len, fused_geom(s, len),
+                                s->stream);
+      cur ^= 1;
+      m += len;
+    }
+    return;
+  }
+  for (int m = 0; m < L; ++m) {
+    mark(0);
+    launch_diffusion<T>(s->layout, diff_args<T>(s, cur, half, m, g), s->lc, s->stream);
+    cur ^= 1;
+  }
+}
+
 // Enqueue `count` outer steps with clock offsets 0..count-1 and advance the
 // device clock by count.  With `ev` non-null every step kernel is launched
 // with a start/stop event pair (appended as {start, stop, class}).
@@ -444,7 +541,6 @@ namespace {
 
 template <typename T>
 void enqueue_steps(mono_sim* s, int64_t count, std::vector<TimedPair>* ev) {
-  const int L = s->l_max;
   size_t next = 0;
   KernelTimer kt{};
   auto mark = [&](int cls) {
@@ -456,16 +552,13 @@ void enqueue_steps(mono_sim* s, int64_t count, std::vector<TimedPair>* ev) {
     g_ktimer = &kt;
   };
   for (int64_t g = 0; g < count; ++g) {
-    for (int m = 0; m < L; ++m) {
-      mark(0);
-      launch_diffusion<T>(s->layout, diff_args<T>(s, m, 0, m, g), s->lc, s->stream);
-    }
+    // the step starts in d_V[0] and, after 2 l substeps or twice the same
+    // number of fused launches, ends there again
+    int cur = 0;
+    enqueue_half<T>(s, 0, g, cur, mark);
     mark(1);
-    launch_ionic<T>(s->model, ion_args<T>(s, s->d_V[L & 1], g), s->lc, s->stream);
-    for (int m = 0; m < L; ++m) {
-      mark(0);
-      launch_diffusion<T>(s->layout, diff_args<T>(s, L + m, 1, m, g), s->lc, s->stream);
-    }
+    launch_ionic<T>(s->model, ion_args<T>(s, s->d_V[cur], g), s->lc, s->stream);
+    enqueue_half<T>(s, 1, g, cur, mark);
   }
   g_ktimer = nullptr;
   launch_advance_clock(s->d_base, count, s->stream);
@@ -510,18 +603,36 @@ mono_status enqueue_timed(mono_sim* s, int64_t count) {
   return MONO_OK;
 }
 
-// R diffusion substeps (first substep of the first half, clock offset 0)
-// alternating between the potential buffers, captured in one graph and timed
-// by events around its launch (after one untimed launch).
+// R diffusion substeps alternating between the potential buffers, captured
+// in one graph and timed by events around its launch (after one untimed
+// launch).  Unfused: R launches of the first substep of the first half step
+// (clock offset 0).  Fused: R / l first half steps (at least one), launched
+// as stepping launches them; the mean is taken over the substeps they run.
 mono_status time_diffusion(mono_sim* s, int64_t R, double& ms_per) {
   HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-  for (int64_t r = 0; r < R; ++r) {
-    if (s->prec == MONO_F64)
-      launch_diffusion<double>(s->layout, diff_args<double>(s, (int)(r & 1), 0, 0, 0), s->lc,
-                               s->stream);
-    else
-      launch_diffusion<float>(s->layout, diff_args<float>(s, (int)(r & 1), 0, 0, 0), s->lc,
-                              s->stream);
+  auto none = [](int) {};
+  int64_t substeps = R;
+  if (use_fused(s)) {
+    // an even number of launches, so that the potential ends in d_V[0]
+    int64_t H = std::max<int64_t>(1, R / s->l_max);
+    if ((H * diff_launches_per_half(s)) & 1) ++H;
+    substeps = H * s->l_max;
+    int cur = 0;
+    for (int64_t h = 0; h < H; ++h) {
+      if (s->prec == MONO_F64)
+        enqueue_half<double>(s, 0, 0, cur, none);
+      else
+        enqueue_half<float>(s, 0, 0, cur, none);
+    }
+  } else {
+    for (int64_t r = 0; r < R; ++r) {
+      if (s->prec == MONO_F64)
+        launch_diffusion<double>(s->layout, diff_args<double>(s, (int)(r & 1), 0, 0, 0), s->lc,
+                                 s->stream);
+      else
+        launch_diffusion<float>(s->layout, diff_args<float>(s, (int)(r & 1), 0, 0, 0), s->lc,
+                                s->stream);
+    }
   }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamEndCapture(s->stream, &g));
@@ -540,7 +651,7 @@ mono_status time_diffusion(mono_sim* s, int64_t R, double& ms_per) {
   if (e1) (void)hipEventDestroy(e1);
   if (ge) (void)hipGraphExecDestroy(ge);
   (void)hipGraphDestroy(g);
-  ms_per = (double)ms / (double)R;
+  ms_per = (double)ms / (double)substeps;
   return st;
 }
 
@@ -1259,6 +1370,17 @@ mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
         if (dalloc(&s->d_wcls, nw)) return bail(fail(MONO_ENOMEM, "device allocation failed"));
         if (hipMemcpy(s->d_wcls, wc.data(), nw * 4, hipMemcpyHostToDevice))
           return bail(fail(MONO_EDEVICE, "upload failed"));
+        if (sh.P == 13 && fused_grid_ok(sh, s->n, s->Np, s->es, s->grid_nx, s->grid_nxy)) {
+          int dev = 0, cus = 0;
+          if (hipGetDevice(&dev) != hipSuccess ||
+              hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                  hipSuccess)
+            return bail(fail(MONO_EDEVICE, "device query failed"));
+          s->n_cu = std::max(cus, 1);
+          s->fuse_ok = 1;
+          s->grid_ny = s->grid_nxy / s->grid_nx;
+          s->grid_nz = (int)(s->n / s->grid_nxy);
+        }
       }
     }
   } else {
@@ -1696,6 +1818,8 @@ mono_status mono_get_info(mono_sim* s, int32_t inst, mono_info* out) {
   out->ell_width = s->layout == MONO_LAYOUT_ELL ? s->W : s->P;
   out->row_classes = s->n_classes;
   out->grid_rows = s->row_pattern;
+  out->diff_fused = s->fuse_ok;
+  if (s->dt > 0.0) out->diff_launches = diff_launches_per_half(s);
   return MONO_OK;
 }
 
@@ -1996,6 +2120,9 @@ mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
   if (c->react_sort < 0 || c->react_sort > 1) return fail(MONO_EINVAL, "bad sort flag");
   if (c->diff_classes < 0 || c->diff_classes > 1) return fail(MONO_EINVAL, "bad classes flag");
   if (c->diff_wave_rows < 0 || c->diff_wave_rows > 1) return fail(MONO_EINVAL, "bad rows flag");
+  if (c->diff_fuse < 0 || c->diff_fuse > 1) return fail(MONO_EINVAL, "bad fuse flag");
+  if (c->diff_fuse_planes < 0 || c->diff_fuse_planes > 4096)
+    return fail(MONO_EINVAL, "diff_fuse_planes must be in 0..4096");
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->lc.diff_block = c->diff_block;
   s->lc.diff_rpl = c->diff_rows_per_lane;
@@ -2005,6 +2132,8 @@ mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {
   s->lc.react_sort = c->react_sort;
   s->lc.diff_classes = c->diff_classes;
   s->lc.diff_wave_rows = c->diff_wave_rows;
+  s->lc.diff_fuse = c->diff_fuse;
+  s->lc.diff_fuse_planes = c->diff_fuse_planes;
   drop_graph(s);
   return MONO_OK;
 }
@@ -2019,6 +2148,8 @@ mono_status mono_get_launch(mono_sim* s, mono_launch* c) {
   c->react_sort = s->lc.react_sort;
   c->diff_classes = s->lc.diff_classes;
   c->diff_wave_rows = s->lc.diff_wave_rows;
+  c->diff_fuse = s->lc.diff_fuse;
+  c->diff_fuse_planes = s->lc.diff_fuse_planes;
   return MONO_OK;
 }
 

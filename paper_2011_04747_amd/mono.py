@@ -62,14 +62,16 @@ class Info(C.Structure):
                 ("step", C.c_int64), ("nnz", C.c_int64), ("l", C.c_int32), ("k_max", C.c_int32),
                 ("layout", C.c_int32), ("n_instances", C.c_int32), ("n_states", C.c_int32),
                 ("ell_width", C.c_int32), ("row_classes", C.c_int32),
-                ("grid_rows", C.c_int32)]
+                ("grid_rows", C.c_int32), ("diff_fused", C.c_int32),
+                ("diff_launches", C.c_int32)]
 
 
 class Launch(C.Structure):
     _fields_ = [("diff_block", C.c_int32), ("diff_rows_per_lane", C.c_int32),
                 ("diff_xcd_remap", C.c_int32), ("react_block", C.c_int32),
                 ("graph_steps", C.c_int32), ("react_sort", C.c_int32),
-                ("diff_classes", C.c_int32), ("diff_wave_rows", C.c_int32)]
+                ("diff_classes", C.c_int32), ("diff_wave_rows", C.c_int32),
+                ("diff_fuse", C.c_int32), ("diff_fuse_planes", C.c_int32)]
 
 
 class KTrace(C.Structure):
