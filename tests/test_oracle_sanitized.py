@@ -19,7 +19,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 ORACLE_TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_celltypes.py",
                 "tests/test_oracle_apd.py", "tests/test_adjoint_cpu.py",
-                "tests/test_oracle_fibrosis.py", "tests/test_oracle_time_pins.py"]
+                "tests/test_oracle_fibrosis.py", "tests/test_oracle_time_pins.py",
+                "tests/test_oracle_tp06_balance.py"]
 
 
 def test_oracle_tests_pass_under_asan_and_ubsan(tmp_path):
@@ -27,10 +28,10 @@ def test_oracle_tests_pass_under_asan_and_ubsan(tmp_path):
     from oracle import build as ob
     ob.build(sanitize=True)
     env = ob.sanitizer_env()
-    # the library's host-side model code is not part of the oracle; its
-    # finite-difference test needs the GPU library and stays out of this run
+    # the library's host-side model code is not part of the oracle; the
+    # tests that call it load the GPU library and stay out of this run
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-           "-m", "not gpu", "-k", "not library_substep_vjp"] + ORACLE_TESTS
+           "-m", "not gpu", "-k", "not library_substep_vjp and not kernel_tp06_code"] + ORACLE_TESTS
     r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     out = r.stdout[-6000:] + "\n" + r.stderr[-6000:]
     assert "AddressSanitizer" not in out and "runtime error:" not in out, out
