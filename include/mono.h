@@ -144,6 +144,9 @@ typedef struct {
   const int64_t *inst_node_off; /* n_instances+1 node offsets, or NULL if 1;
                                    no element may join two instances            */
   int32_t layout;               /* MONO_LAYOUT_*                                 */
+  int32_t sigma_device;         /* nonzero: sigma_node is device memory (FP64,
+                                   ready when the call is made); the library
+                                   copies it to the host for the FP64 assembly */
 } mono_mesh_desc;
 
 typedef struct {
@@ -419,6 +422,34 @@ mono_status mono_checkpoint_plan(int64_t n_segments, int32_t max_snapshots, int6
  * sum_i p_i[a] dL/dp_i[a].  Either pointer may be NULL.  Leaves the state
  * where the taped run ended.  FP64 accumulation of both gradients. */
 mono_status mono_backward(mono_sim *sim, double *grad_sigma, double *grad_params);
+
+/* The sensitivity problem with its inputs and outputs in device memory (for
+ * a differentiable caller whose tensors live on the GPU; the chain rule
+ * through the scalings is applied here).
+ *
+ * mono_set_param_scalings: multiply parameter rows rows[0..n-1] (host array,
+ * distinct, of the model's parameter rows; a cell-type or node-class row is
+ * EINVAL) of every node by the scalings c[0..n-1] (device memory, FP64,
+ * ready when the call is made; copied to the host, where uniform rows live
+ * as kernel arguments), relative to the parameters of the last
+ * mono_set_cell_model: a second call before the next mono_set_cell_model is
+ * ESTATE; a scaling that is zero or not finite is EINVAL.  Per-node rows are
+ * scaled on the device in the simulation precision.
+ *
+ * mono_forward_taped_device: mono_forward_taped writing the loss (FP64) to
+ * device memory loss instead of the host; synchronising.
+ *
+ * mono_backward_device: mono_backward writing dL/dsigma (n_nodes FP64) to
+ * device memory grad_sigma and, for the scalings of mono_set_param_scalings,
+ * dL/dc_j = sum_i base_i[rows_j] dL/dp_i[rows_j] = grad_params[rows_j] / c_j
+ * (n FP64, the same sums in the same order as mono_backward) to device
+ * memory grad_scalings; either may be NULL (grad_scalings must be NULL when
+ * no scalings were set: ESTATE).  Synchronising. */
+mono_status mono_set_param_scalings(mono_sim *sim, int32_t n, const int32_t *rows,
+                                    const double *scalings);
+mono_status mono_forward_taped_device(mono_sim *sim, int64_t n_steps, double dt,
+                                      int32_t ckpt_every, double *loss);
+mono_status mono_backward_device(mono_sim *sim, double *grad_sigma, double *grad_scalings);
 
 /* Test hooks.  `what`:
  *  MONO_DEBUG_KTRACE: arg -> mono_ktrace (device buffers n_steps x n_nodes,

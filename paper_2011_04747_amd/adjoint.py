@@ -7,7 +7,9 @@ conductivity scales sigma (which enter the FE stiffness through
 (sigma_i + sigma_j)/2 on every edge) and global multipliers of the TP06
 conductance rows g_Na, g_CaL, g_Kr, g_Ks, g_K1.  The forward pass runs the
 library's taped forward with uniform checkpoints; the backward pass runs the
-library's hand-written adjoint.  Everything numerical happens in libmono.
+library's hand-written adjoint.  Everything numerical happens in libmono,
+including the chain rule through the multipliers: torch supplies device
+memory (sigma, the multipliers, the loss and gradient outputs) and streams.
 """
 from __future__ import annotations
 
@@ -47,15 +49,14 @@ class AdjointProblem:
         self.replay_k = replay_k
         self.sim = None
 
-    def make_sim(self, sigma: np.ndarray, scalings: np.ndarray) -> mono.Sim:
-        mesh = self.w.mesh
-        m = W.Mesh(mesh.dim, mesh.xyz, mesh.etype, mesh.conn, mesh.D_elem, sigma,
-                   mesh.inst_node_off, mesh.inst_elem_off, mesh.grid_shape)
-        p = self.w.params.copy()
-        for r, c in zip(TP06_SCALING_ROWS, scalings):
-            p[r] = p[r] * float(c)
-        sim = mono.Sim(m, self.precision, stream=self.stream)
-        sim.set_cell_model(self.w.model, p, None, self.w.dt0)
+    def make_sim(self, sigma_device: int, scalings_device: int) -> mono.Sim:
+        """A simulation of the problem with the conductivity scales and the
+        row multipliers read from device addresses (n_nodes and 5 FP64
+        values, ready when called)."""
+        sim = mono.Sim(self.w.mesh, self.precision, stream=self.stream,
+                       sigma_device=sigma_device)
+        sim.set_cell_model(self.w.model, self.w.params, None, self.w.dt0)
+        sim.set_param_scalings(TP06_SCALING_ROWS, scalings_device)
         sim.set_lat_threshold(self.w.lat_threshold)
         for st in self.w.stimuli:
             sim.add_stimulus(st.nodes, st.t_on, st.duration, st.amplitude)
@@ -73,26 +74,33 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, sigma, scalings, problem):
-            sg = sigma.detach().to("cpu", torch.float64).numpy()
-            sc = scalings.detach().to("cpu", torch.float64).numpy()
-            sim = problem.make_sim(sg, sc)
-            loss = sim.forward_taped(problem.n_steps, problem.w.dt, problem.ckpt_every)
+            n = problem.w.mesh.n_nodes
+            if (not sigma.is_cuda or not scalings.is_cuda or sigma.shape != (n,)
+                    or scalings.shape != (len(TP06_SCALING_ROWS),)):
+                raise ValueError(f"sigma ({n},) and scalings ({len(TP06_SCALING_ROWS)},) "
+                                 f"must be CUDA tensors")
+            sg = sigma.detach().to(torch.float64).contiguous()
+            sc = scalings.detach().to(torch.float64).contiguous()
+            # the library reads both on its own stream
+            torch.cuda.current_stream(sigma.device).synchronize()
+            sim = problem.make_sim(sg.data_ptr(), sc.data_ptr())
+            loss = torch.empty((), dtype=torch.float64, device=sigma.device)
+            sim.forward_taped_device(problem.n_steps, problem.w.dt, problem.ckpt_every,
+                                     loss.data_ptr())
             ctx.sim = sim
-            ctx.sc = sc
             ctx.dev = sigma.device
-            return torch.tensor(loss, dtype=torch.float64, device=sigma.device)
+            return loss
 
         @staticmethod
         def backward(ctx, gout):
-            gs, gp = ctx.sim.backward()
+            n = ctx.sim.n
+            gs = torch.empty(n, dtype=torch.float64, device=ctx.dev)
+            gsc = torch.empty(len(TP06_SCALING_ROWS), dtype=torch.float64, device=ctx.dev)
+            ctx.sim.backward_device(gs.data_ptr(), gsc.data_ptr())
             ctx.sim.close()
             ctx.sim = None
-            # gp[a] = sum_i p_i[a] dL/dp_i[a]; p_i[a] = c_a base_i[a] gives
-            # dL/dc_a = gp[a] / c_a
-            gsc = np.array([gp[r] / c for r, c in zip(TP06_SCALING_ROWS, ctx.sc)])
-            g = gout.to("cpu", torch.float64)
-            return (torch.from_numpy(gs).to(ctx.dev) * g.to(ctx.dev),
-                    torch.from_numpy(gsc).to(ctx.dev) * g.to(ctx.dev), None)
+            g = gout.to(device=ctx.dev, dtype=torch.float64)
+            return gs * g, gsc * g, None
 
     return MonoAdjointFn
 

@@ -402,6 +402,37 @@ void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, 
 template void launch_sensor_sample<float>(const float*, const int32_t*, int, double*, hipStream_t);
 template void launch_sensor_sample<double>(const double*, const int32_t*, int, double*,
                                            hipStream_t);
+// x[i] *= c for i < n (one parameter row)
+template <typename T>
+__global__ void k_scale_row(T* x, int64_t n, T c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= c;
+}
+template <typename T>
+void launch_scale_row(T* x, int64_t n, T c, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_scale_row<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
+                     c);
+}
+template void launch_scale_row<float>(float*, int64_t, float, hipStream_t);
+template void launch_scale_row<double>(double*, int64_t, double, hipStream_t);
+
+// out[j] = (sum over q = 0, 1, ..., n-1 in that order of x[q * stride + col_j])
+// / div_j (div_j = 1: the plain sum), one thread per j: the sums a host loop
+// would form, bit for bit.
+__global__ void k_ordered_sums(const double* x, int64_t n, int stride, OrderedSums a,
+                               double* out) {
+  const int j = threadIdx.x;
+  if (j >= a.count) return;
+  double acc = 0.0;
+  for (int64_t q = 0; q < n; ++q) acc += x[q * stride + a.col[j]];
+  out[j] = acc / a.div[j];
+}
+void launch_ordered_sums(const double* x, int64_t n, int stride, const OrderedSums& a,
+                         double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_ordered_sums, dim3(1), dim3(64), 0, s, x, n, stride, a, out);
+}
+
 template void launch_adj_diffusion<float>(int, const AdjDiffArgs<float>&, hipStream_t);
 template void launch_adj_diffusion<double>(int, const AdjDiffArgs<double>&, hipStream_t);
 template void launch_adj_ionic<float>(int, const AdjIonArgs<float>&, hipStream_t);

@@ -297,6 +297,17 @@ struct SensorArgs {
 };
 template <typename T>
 void launch_sensor_loss(const T* V, const SensorArgs& a, hipStream_t s);
+// one parameter row scaled in place
+template <typename T>
+void launch_scale_row(T* x, int64_t n, T c, hipStream_t s);
+// out[j] = (sum_{q < n} x[q * stride + col[j]], in order) / div[j]
+struct OrderedSums {
+  int count;
+  int col[kMaxParams];
+  double div[kMaxParams];
+};
+void launch_ordered_sums(const double* x, int64_t n, int stride, const OrderedSums& a,
+                         double* out, hipStream_t s);
 template <typename T>
 void launch_sensor_sample(const T* V, const int32_t* sens, int ns, double* out, hipStream_t s);
 

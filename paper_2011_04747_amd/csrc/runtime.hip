@@ -200,6 +200,10 @@ struct mono_sim {
   int ckpt_schedule = MONO_CKPT_UNIFORM, ckpt_max_slots = 0;
   CkptPlan plan;                   // the binomial plan of the taped run
   int64_t ckpt_advances = 0;       // segment advances of the last reverse sweep
+  // parameter scalings of mono_set_param_scalings since the last cell model
+  int scal_n = -1;                 // -1: none set
+  int scal_rows[kMaxParams] = {};
+  double scal_vals[kMaxParams] = {};
   std::vector<void*> d_ckpt;       // state snapshots (segment starts)
   void* d_final = nullptr;         // state after the taped run
   void* d_seg_vsub = nullptr;      // ckpt_every x 2 l_max x Np
@@ -1190,8 +1194,31 @@ extern "C" {
 
 const char* mono_last_error(void) { return t_err.c_str(); }
 
+static mono_status create_mesh(const mono_mesh_desc* d, mono_sim** out);
+
 mono_status mono_create_mesh(const mono_mesh_desc* d, mono_sim** out) {
   if (!d || !out) return fail(MONO_EINVAL, "NULL argument");
+  if (!d->sigma_device || !d->sigma_node) return create_mesh(d, out);
+  // conductivity scales in device memory: copied to the host, where the FP64
+  // assembly runs
+  *out = nullptr;
+  if (d->n_nodes < 1 || d->n_nodes > (int64_t)INT32_MAX - 1024)
+    return fail(MONO_EINVAL, "n_nodes out of range");
+  hipPointerAttribute_t attr{};
+  if (hipPointerGetAttributes(&attr, d->sigma_node) != hipSuccess ||
+      attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(MONO_EINVAL, "sigma_device set but sigma_node is not device memory");
+  }
+  std::vector<double> sg((size_t)d->n_nodes);
+  HIP_TRY(hipMemcpy(sg.data(), d->sigma_node, sg.size() * 8, hipMemcpyDeviceToHost));
+  mono_mesh_desc h = *d;
+  h.sigma_node = sg.data();
+  h.sigma_device = 0;
+  return create_mesh(&h, out);
+}
+
+static mono_status create_mesh(const mono_mesh_desc* d, mono_sim** out) {
   *out = nullptr;
   if (d->dim < 1 || d->dim > 3) return fail(MONO_EINVAL, "dim must be 1, 2 or 3");
   if (d->etype != (1 << d->dim) && !(d->dim >= 2 && d->etype == d->dim + 1))
@@ -1536,6 +1563,7 @@ mono_status mono_set_cell_model(mono_sim* s, int32_t model, int32_t n_params,
       }
   }
   s->dt0 = dt0;
+  s->scal_n = -1;
   s->lat_thr = default_lat_threshold(model);
   s->step = 0;
   HIP_TRY(hipMemsetAsync(s->d_base, 0, 8, s->stream));
@@ -2097,6 +2125,94 @@ mono_status mono_backward(mono_sim* s, double* grad_sigma, double* grad_params) 
     }
   }
   return check_flag(s);
+}
+
+mono_status mono_set_param_scalings(mono_sim* s, int32_t n, const int32_t* rows,
+                                    const double* scalings) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (n < 1 || n > s->Pm || !rows || !scalings) return fail(MONO_EINVAL, "bad argument");
+  if (s->scal_n >= 0)
+    return fail(MONO_ESTATE, "scalings already set since the last mono_set_cell_model");
+  const bool label6 = s->model == MONO_MODEL_TP06_TYPES || s->model == MONO_MODEL_TP06_FIBRO;
+  for (int j = 0; j < n; ++j) {
+    if (rows[j] < 0 || rows[j] >= s->Pm) return fail(MONO_EINVAL, "parameter row out of range");
+    if (label6 && rows[j] == 6) return fail(MONO_EINVAL, "the type / class row is a label");
+    for (int k = 0; k < j; ++k)
+      if (rows[k] == rows[j]) return fail(MONO_EINVAL, "repeated parameter row");
+  }
+  hipPointerAttribute_t attr{};
+  if (hipPointerGetAttributes(&attr, scalings) != hipSuccess ||
+      attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(MONO_EINVAL, "scalings must be device memory");
+  }
+  double c[kMaxParams];
+  HIP_TRY(hipMemcpyAsync(c, scalings, (size_t)n * 8, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int j = 0; j < n; ++j)
+    if (!std::isfinite(c[j]) || c[j] == 0.0)
+      return fail(MONO_EINVAL, "scalings must be finite and nonzero");
+  for (int j = 0; j < n; ++j) {
+    const int a = rows[j];
+    if (s->par_pernode >> a & 1u) {
+      if (s->prec == MONO_F64)
+        launch_scale_row<double>((double*)s->d_par + (size_t)a * s->Np, s->n, c[j], s->stream);
+      else
+        launch_scale_row<float>((float*)s->d_par + (size_t)a * s->Np, s->n, (float)c[j],
+                                s->stream);
+    } else {
+      s->par_uniform[a] *= c[j];
+    }
+    s->scal_rows[j] = a;
+    s->scal_vals[j] = c[j];
+  }
+  HIP_TRY(hipGetLastError());
+  s->scal_n = n;
+  drop_graph(s);
+  return MONO_OK;
+}
+
+mono_status mono_forward_taped_device(mono_sim* s, int64_t n_steps, double dt, int32_t ckpt_every,
+                                      double* loss) {
+  if (!s || !loss) return fail(MONO_EINVAL, "NULL argument");
+  double L = 0.0;
+  mono_status st = mono_forward_taped(s, n_steps, dt, ckpt_every, &L);
+  if (st != MONO_OK) return st;
+  // the per-step losses summed on the device in the host's order
+  OrderedSums a{};
+  a.count = 1;
+  a.col[0] = 0;
+  a.div[0] = 1.0;
+  launch_ordered_sums(s->d_loss_steps, s->tape_steps, 1, a, loss, s->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MONO_OK;
+}
+
+mono_status mono_backward_device(mono_sim* s, double* grad_sigma, double* grad_scalings) {
+  mono_status st = require_model(s);
+  if (st != MONO_OK) return st;
+  if (grad_scalings && s->scal_n < 0)
+    return fail(MONO_ESTATE, "no scalings set (mono_set_param_scalings)");
+  st = mono_backward(s, nullptr, nullptr);
+  if (st != MONO_OK) return st;
+  if (grad_sigma)
+    HIP_TRY(hipMemcpyAsync(grad_sigma, s->d_gsig, s->n * 8, hipMemcpyDeviceToDevice, s->stream));
+  if (grad_scalings) {
+    // per-workgroup partial sums reduced in the order mono_backward uses,
+    // then the chain rule through p = c base
+    OrderedSums a{};
+    a.count = s->scal_n;
+    for (int j = 0; j < s->scal_n; ++j) {
+      a.col[j] = s->scal_rows[j];
+      a.div[j] = s->scal_vals[j];
+    }
+    launch_ordered_sums(s->d_gpart, (s->n + 255) / 256, kMaxParams, a, grad_scalings, s->stream);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MONO_OK;
 }
 
 mono_status mono_set_launch(mono_sim* s, const mono_launch* c) {

@@ -39,7 +39,8 @@ EXPORTS = ("mono_create_mesh", "mono_set_cell_model", "mono_set_lat_threshold",
            "mono_model_substep_host", "mono_model_vjp_host", "mono_set_sensors",
            "mono_forward_taped", "mono_backward", "mono_sample_sensors", "mono_set_allocator",
            "mono_track_apd", "mono_nrmse", "mono_set_checkpointing", "mono_checkpoint_info",
-           "mono_checkpoint_plan", "mono_sample_sensors_noalloc")
+           "mono_checkpoint_plan", "mono_sample_sensors_noalloc", "mono_set_param_scalings",
+           "mono_forward_taped_device", "mono_backward_device")
 
 
 class MonoError(RuntimeError):
@@ -53,7 +54,8 @@ class MeshDesc(C.Structure):
                 ("etype", C.c_int32), ("n_elems", C.c_int64), ("conn", C.c_void_p),
                 ("D_elem", C.c_void_p), ("sigma_node", C.c_void_p), ("prec", C.c_int32),
                 ("stream", C.c_void_p), ("n_instances", C.c_int32),
-                ("inst_node_off", C.c_void_p), ("layout", C.c_int32)]
+                ("inst_node_off", C.c_void_p), ("layout", C.c_int32),
+                ("sigma_device", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -154,6 +156,9 @@ def lib():
             "mono_checkpoint_info": [vp, vp],
             "mono_checkpoint_plan": [i64, i32, vp],
             "mono_sample_sensors_noalloc": [vp, i64, dbl, vp],
+            "mono_set_param_scalings": [vp, i32, vp, vp],
+            "mono_forward_taped_device": [vp, i64, dbl, i32, vp],
+            "mono_backward_device": [vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -220,7 +225,11 @@ def model_vjp_host(model, state, params, h, lam, clamp=False):
 class Sim:
     """One monodomain simulation on the GPU (a handle of libmono)."""
 
-    def __init__(self, mesh, precision: str = "f64", stream=None, layout: int = LAYOUT_AUTO):
+    def __init__(self, mesh, precision: str = "f64", stream=None, layout: int = LAYOUT_AUTO,
+                 sigma_device=None):
+        """sigma_device: address of n_nodes FP64 conductivity scales in device
+        memory, used instead of mesh.sigma (the library copies them for its
+        host-side assembly)."""
         L = lib()
         self.n = mesh.n_nodes
         self.precision = precision
@@ -230,11 +239,15 @@ class Sim:
         sig = None if mesh.sigma is None else _c(mesh.sigma, np.float64)
         off = None if mesh.inst_node_off is None else _c(mesh.inst_node_off, np.int64)
         self.stream = stream
+        if sigma_device is not None:
+            sig_ptr, on_dev = int(sigma_device), 1
+        else:
+            sig_ptr, on_dev = (None if sig is None else sig.ctypes.data), 0
         d = MeshDesc(mesh.dim, self.n, xyz.ctypes.data, mesh.etype, mesh.n_elems,
-                     conn.ctypes.data, D.ctypes.data, None if sig is None else sig.ctypes.data,
+                     conn.ctypes.data, D.ctypes.data, sig_ptr,
                      F64 if precision == "f64" else F32,
                      None if stream is None else int(stream), mesh.n_instances,
-                     None if off is None else off.ctypes.data, layout)
+                     None if off is None else off.ctypes.data, layout, on_dev)
         h = C.c_void_p()
         _check(L.mono_create_mesh(C.byref(d), C.byref(h)))
         self.h = h
@@ -381,6 +394,23 @@ class Sim:
         return {"schedule": ("uniform", "binomial")[int(out[0])], "snapshots": int(out[1]),
                 "segments": int(out[2]), "advances": int(out[3]),
                 "snapshot_bytes": int(out[4]), "tape_bytes": int(out[5])}
+
+    def set_param_scalings(self, rows, scalings_device):
+        """Scale parameter rows `rows` by n FP64 values at a device address."""
+        r = _c(rows, np.int32)
+        _check(lib().mono_set_param_scalings(self.h, len(r), r.ctypes.data,
+                                             C.c_void_p(int(scalings_device))))
+
+    def forward_taped_device(self, n_steps, dt, ckpt_every, loss_device):
+        """forward_taped with the loss written to a device address (FP64)."""
+        _check(lib().mono_forward_taped_device(self.h, int(n_steps), float(dt), int(ckpt_every),
+                                               C.c_void_p(int(loss_device))))
+
+    def backward_device(self, grad_sigma_device=None, grad_scalings_device=None):
+        """backward with dL/dsigma and dL/d(scalings) written to device addresses."""
+        _check(lib().mono_backward_device(
+            self.h, None if grad_sigma_device is None else C.c_void_p(int(grad_sigma_device)),
+            None if grad_scalings_device is None else C.c_void_p(int(grad_scalings_device))))
 
     def backward(self, n_params=None):
         """(dL/dsigma per node, derivative for a common multiplier of each parameter row)."""

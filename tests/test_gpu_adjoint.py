@@ -247,3 +247,109 @@ def test_binomial_checkpointing_equals_uniform(torch, kind, ckpt):
             assert L == ref[0]
             assert np.array_equal(gs, ref[1]) and np.array_equal(gp, ref[2]), (sched, slots)
         s.close()
+
+
+def _device_problem():
+    """A small ischemic slab: per-node K_o and g_Na rows (ischemic zone) and
+    uniform g_CaL .. g_K1 rows, so the scalings reach both kinds of row."""
+    rng = np.random.default_rng(8)
+    w = W.slab_ischemic(shape=(15, 13, 7), dx=0.02, t_end=6.0, s2_time=3.0)
+    w.sensors = np.sort(rng.choice(w.mesh.n_nodes, 40, replace=False)).astype(np.int32)
+    w.mesh.sigma = np.exp(0.1 * rng.standard_normal(w.mesh.n_nodes))
+    target = -80.0 + rng.uniform(-0.2, 0.2, (w.n_steps, len(w.sensors)))
+    return w, target
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_device_inputs_and_outputs_match_the_host_calls(torch, prec):
+    """sigma and the multipliers read from device memory, the loss and both
+    gradients written to device memory, with the chain rule through the
+    multipliers in the library: in FP64 the same bits as the host calls on
+    parameters scaled on the host (dL/dc = grad_params / c); in FP32 the
+    per-node rows are scaled in FP32 on the device, so within 1e-5."""
+    from paper_2011_04747_amd.adjoint import TP06_SCALING_ROWS
+    w, target = _device_problem()
+    assert w.params[1].min() != w.params[1].max()          # a per-node row is scaled
+    c = np.array([1.1, 0.9, 1.2, 0.8, 1.05])
+    # host calls
+    p = w.params.copy()
+    for r, cr in zip(TP06_SCALING_ROWS, c):
+        p[r] = p[r] * cr
+    h = mono.Sim(w.mesh, prec)
+    h.set_cell_model(w.model, p, None, w.dt0)
+    for st in w.stimuli:
+        h.add_stimulus(st.nodes, st.t_on, st.duration, st.amplitude)
+    h.set_sensors(w.sensors, target)
+    Lh = h.forward_taped(w.n_steps, w.dt, 7)
+    gsh, gph = h.backward()
+    h.close()
+    # device calls
+    sig = torch.tensor(w.mesh.sigma, dtype=torch.float64, device="cuda")
+    cd = torch.tensor(c, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def device_run(want_scalings):
+        d = mono.Sim(w.mesh, prec, sigma_device=sig.data_ptr())
+        d.set_cell_model(w.model, w.params, None, w.dt0)
+        d.set_param_scalings(TP06_SCALING_ROWS, cd.data_ptr())
+        for st in w.stimuli:
+            d.add_stimulus(st.nodes, st.t_on, st.duration, st.amplitude)
+        d.set_sensors(w.sensors, target)
+        loss = torch.zeros((), dtype=torch.float64, device="cuda")
+        gs = torch.full((w.mesh.n_nodes,), 7.0, dtype=torch.float64, device="cuda")
+        gc = torch.full((5,), 7.0, dtype=torch.float64, device="cuda")
+        d.forward_taped_device(w.n_steps, w.dt, 7, loss.data_ptr())
+        d.backward_device(gs.data_ptr(), gc.data_ptr() if want_scalings else None)
+        torch.cuda.synchronize()
+        d.close()
+        return float(loss.item()), gs.cpu().numpy(), gc.cpu().numpy()
+
+    Ld, gsd, gcd = device_run(True)
+    want = np.array([gph[r] / cr for r, cr in zip(TP06_SCALING_ROWS, c)])
+    if prec == "f64":
+        assert Ld == Lh
+        assert (gsd == gsh).all()
+        assert (gcd == want).all()
+    else:
+        assert Ld == pytest.approx(Lh, rel=1e-5)
+        assert np.abs(gsd - gsh).max() <= 1e-3 * np.abs(gsh).max()
+        assert np.abs(gcd - want).max() <= 1e-3 * np.abs(want).max()
+    # only the gradients asked for are written
+    L2, gs2, gc2 = device_run(False)
+    assert L2 == Ld and (gs2 == gsd).all() and (gc2 == 7.0).all()
+
+
+def test_device_scalings_are_checked(torch):
+    w, target = _device_problem()
+    good = torch.ones(5, dtype=torch.float64, device="cuda")
+    zero = torch.tensor([1.0, 0.0, 1.0, 1.0, 1.0], dtype=torch.float64, device="cuda")
+    host = np.ones(5)
+    s = mono.Sim.from_workload(w, "f64")
+    with pytest.raises(mono.MonoError):
+        s.set_param_scalings([1, 2, 3, 4, 5], zero.data_ptr())
+    with pytest.raises(mono.MonoError):
+        s.set_param_scalings([1, 2, 3, 4, 5], host.ctypes.data)     # host memory
+    with pytest.raises(mono.MonoError):
+        s.set_param_scalings([1, 1, 3, 4, 5], good.data_ptr())      # repeated row
+    with pytest.raises(mono.MonoError):
+        s.set_param_scalings([1, 2, 3, 4, 9], good.data_ptr())      # no such row
+    s.set_sensors(w.sensors, target)
+    s.forward_taped(w.n_steps, w.dt, 7)
+    out = torch.zeros(5, dtype=torch.float64, device="cuda")
+    with pytest.raises(mono.MonoError):                             # nothing scaled
+        s.backward_device(None, out.data_ptr())
+    s.close()
+    s = mono.Sim.from_workload(w, "f64")
+    s.set_param_scalings([1, 2, 3, 4, 5], good.data_ptr())
+    with pytest.raises(mono.MonoError):                             # twice
+        s.set_param_scalings([1, 2, 3, 4, 5], good.data_ptr())
+    s.close()
+    wt, _ = _problem("tp06types")
+    s = mono.Sim.from_workload(wt, "f64")
+    with pytest.raises(mono.MonoError):                             # the cell-type label
+        s.set_param_scalings([6], good.data_ptr())
+    s.close()
+    # a mesh whose sigma claims device memory but is not
+    sig = np.ones(w.mesh.n_nodes)
+    with pytest.raises(mono.MonoError):
+        mono.Sim(w.mesh, "f64", sigma_device=sig.ctypes.data)
