@@ -334,10 +334,12 @@ def full_slab():
 
 
 def _slab_tuned_launch():
+    """The committed tuned launch of the full-size FP32 slab."""
+    import glob
     import json
     import os
-    f = os.path.join(os.path.dirname(mono.__file__), "tuned",
-                     "gfx950_f32_stencil13_m2_n2060451_i1_nnz54541351.json")
+    (f,) = glob.glob(os.path.join(os.path.dirname(mono.__file__), "tuned",
+                                  "gfx950_f32_stencil13_m2_n2060451_i1_nnz54541351*.json"))
     with open(f) as fh:
         return json.load(fh)["launch"]
 
