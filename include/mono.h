@@ -404,8 +404,10 @@ mono_status mono_set_checkpointing(mono_sim *sim, int32_t schedule, int32_t max_
 
 /* Figures of the last taped run's schedule into out[6]: {schedule, snapshot
  * buffers, segments, whole-segment forward advances of the last
- * mono_backward, snapshot bytes, segment tape bytes}.  ESTATE before a taped
- * run. */
+ * mono_backward, snapshot bytes, segment tape bytes (two segment tapes in
+ * the uniform schedule when memory allows: one segment is recomputed on a
+ * second stream while the segment after it is reversed)}.  ESTATE before a
+ * taped run. */
 mono_status mono_checkpoint_info(mono_sim *sim, int64_t *out);
 
 /* The number of whole-segment forward advances the binomial plan needs to

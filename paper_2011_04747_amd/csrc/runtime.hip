@@ -209,6 +209,13 @@ struct mono_sim {
   void* d_seg_vsub = nullptr;      // ckpt_every x 2 l_max x Np
   void* d_seg_entry = nullptr;     // ckpt_every x S x Np
   uint8_t* d_seg_k = nullptr;      // ckpt_every x n
+  // a second segment tape (the uniform schedule recomputes one segment while
+  // the one after it is reversed) and the reverse sweep's own device clock
+  void* d_seg_vsub2 = nullptr;
+  void* d_seg_entry2 = nullptr;
+  uint8_t* d_seg_k2 = nullptr;
+  int64_t* d_base_rev = nullptr;
+  hipStream_t stream_aux = nullptr;  // library-created, for the recomputes
   void* d_lam = nullptr;           // S x Np adjoint of the state
   void* d_lamV2 = nullptr;         // Np, ping-pong partner of the V adjoint
   double* d_gsig = nullptr;        // Np
@@ -781,6 +788,10 @@ void free_tape(mono_sim* s) {
   dfree(s->d_seg_vsub);
   dfree(s->d_seg_entry);
   dfree(s->d_seg_k);
+  dfree(s->d_seg_vsub2);
+  dfree(s->d_seg_entry2);
+  dfree(s->d_seg_k2);
+  dfree(s->d_base_rev);
   dfree(s->d_lam);
   dfree(s->d_lamV2);
   dfree(s->d_gsig);
@@ -952,22 +963,38 @@ struct GraphPair {
     for (hipGraphExec_t g : {full, rest, fullq, restq})
       if (g) (void)hipGraphExecDestroy(g);
   }
+  // With step0 >= 0 (the run's first step) only the variants that the run's
+  // segments will pick are captured (of the segments whose index is
+  // seg_rem modulo seg_mod); otherwise all of them.
   template <class MK>
-  mono_status capture(mono_sim* s, MK make, int64_t n_steps, int64_t C) {
+  mono_status capture(mono_sim* s, MK make, int64_t n_steps, int64_t C, bool stimuli = true,
+                      int64_t step0 = -1, int seg_mod = 1, int seg_rem = 0) {
     const int64_t rest_n = n_steps % C;
+    const bool variants = stimuli && s->stim.n > 0;
+    bool need[2][2] = {{n_steps >= C, rest_n > 0}, {variants && n_steps >= C, variants && rest_n > 0}};
+    if (step0 >= 0) {
+      need[0][0] = need[0][1] = need[1][0] = need[1][1] = false;
+      for (int64_t t0 = 0; t0 < n_steps; t0 += C) {
+        if ((t0 / C) % seg_mod != seg_rem) continue;
+        const int64_t cn = std::min(C, n_steps - t0);
+        const bool q = variants && chunk_is_quiet(s, step0 + t0, cn);
+        need[q ? 1 : 0][cn == C ? 0 : 1] = true;
+      }
+    }
     mono_status st = MONO_OK;
-    for (int quiet = 0; quiet < (s->stim.n > 0 ? 2 : 1) && st == MONO_OK; ++quiet) {
+    for (int quiet = 0; quiet < 2 && st == MONO_OK; ++quiet) {
       s->quiet = quiet != 0;
-      if (n_steps >= C) st = capture_graph(s, make(C), quiet ? &fullq : &full);
-      if (st == MONO_OK && rest_n) st = capture_graph(s, make(rest_n), quiet ? &restq : &rest);
+      if (need[quiet][0]) st = capture_graph(s, make(C), quiet ? &fullq : &full);
+      if (st == MONO_OK && need[quiet][1])
+        st = capture_graph(s, make(rest_n), quiet ? &restq : &rest);
     }
     s->quiet = false;
     return st;
   }
   hipGraphExec_t pick(const mono_sim* s, int64_t step0, int64_t cn, int64_t C) const {
-    const bool q = chunk_is_quiet(s, step0, cn);
-    if (cn == C) return (q && fullq) ? fullq : full;
-    return (q && restq) ? restq : rest;
+    const bool q = (cn == C ? fullq : restq) && chunk_is_quiet(s, step0, cn);
+    if (cn == C) return q ? fullq : full;
+    return q ? restq : rest;
   }
 };
 
@@ -985,7 +1012,7 @@ mono_status forward_taped_t(mono_sim* s, int64_t n_steps, double* loss) {
       launch_advance_clock(s->d_base, cn, s->stream);
     };
   };
-  mono_status st = gp.capture(s, segment, n_steps, C);
+  mono_status st = gp.capture(s, segment, n_steps, C, true, s->step);
   if (st != MONO_OK) return st;
   // snapshot buffer of each segment start (-1: not stored): every start in
   // the uniform schedule; the binomial plan's first splits otherwise
@@ -1036,140 +1063,218 @@ mono_status backward_t(mono_sim* s) {
   const int64_t nck = (N + C - 1) / C;
   const int L = s->l_max, S = s->S;
   const size_t Np = s->Np;
-  T* const vsub = (T*)s->d_seg_vsub;
-  T* const ent = (T*)s->d_seg_entry;
-  auto segment = [=](int64_t cn) {
-    return [=]() {
-      for (int64_t t = 0; t < cn; ++t) {
-        T* vs = vsub + (size_t)t * 2 * L * Np;
-        T* vnext = (t + 1 < cn) ? vs + 2 * (size_t)L * Np : (T*)s->d_V[0];
-        enqueue_tape_step<T>(s, t, vs, ent + (size_t)t * S * Np, s->d_seg_k, cn, vnext);
-      }
-      T* lamV = (T*)s->d_lam;
-      T* lamW = (T*)s->d_lamV2;
-      for (int64_t t = cn - 1; t >= 0; --t) {
-        const T* vs = vsub + (size_t)t * 2 * L * Np;
-        const T* entry = ent + (size_t)t * S * Np;
-        for (int m = L - 1; m >= 0; --m) {
-          launch_adj_diffusion<T>(
-              s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)(L + m) * Np, m), s->stream);
-          std::swap(lamV, lamW);
+  // segment tape b (0, or 1 when the uniform schedule overlaps segments)
+  T* const vsubs[2] = {(T*)s->d_seg_vsub, (T*)s->d_seg_vsub2};
+  T* const ents[2] = {(T*)s->d_seg_entry, (T*)s->d_seg_entry2};
+  uint8_t* const ks[2] = {s->d_seg_k, s->d_seg_k2};
+  // recompute of a segment into tape b: the forward steps, writing what the
+  // reverse needs; the last step leaves the potential in the live state
+  auto recompute = [=](int b) {
+    return [=](int64_t cn) {
+      return [=]() {
+        for (int64_t t = 0; t < cn; ++t) {
+          T* vs = vsubs[b] + (size_t)t * 2 * L * Np;
+          T* vnext = (t + 1 < cn) ? vs + 2 * (size_t)L * Np : (T*)s->d_V[0];
+          enqueue_tape_step<T>(s, t, vs, ents[b] + (size_t)t * S * Np, ks[b], cn, vnext);
         }
-        AdjIonArgs<T> ai{};
-        ai.n = s->n;
-        ai.Np = s->Np;
-        ai.entry = entry;
-        ai.k = s->d_seg_k + (size_t)t * s->n;
-        ai.lam = (T*)s->d_lam;
-        ai.lamV = lamV;
-        ai.par = (const T*)s->d_par;
-        for (int q = 0; q < kMaxParams; ++q) ai.par_uniform[q] = (T)s->par_uniform[q];
-        ai.par_pernode = s->par_pernode;
-        ai.dt = s->dt;
-        ai.gpart = s->d_gpart;
-        ai.sort = s->lc.react_sort;
-        if (s->ns > 0) {
-          // the loss gradient at reaction entry goes in with the reaction's
-          // adjoint (one launch instead of two)
-          const SensorArgs sa = sensor_args(s, t);
-          ai.sens_of = s->d_sens_of;
-          ai.target = sa.target;
-          ai.ns = sa.ns;
-          ai.target_steps = sa.target_steps;
-          ai.clk = sa.clk;
-        }
-        launch_adj_ionic<T>(s->model, ai, s->stream);
-        for (int m = L - 1; m >= 0; --m) {
-          launch_adj_diffusion<T>(
-              s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)m * Np, m), s->stream);
-          std::swap(lamV, lamW);
-        }
-      }
-    };
-  };
-  GraphPair gp;
-  mono_status st = gp.capture(s, segment, N, C);
-  if (st != MONO_OK) return st;
-  // the schedule: segments reversed from the last to the first, each from a
-  // snapshot buffer; in the binomial schedule, forward advances of whole
-  // segments refill buffers in between
-  struct Act {
-    bool advance;
-    int64_t c;     // segment reversed, or first segment advanced over
-    int64_t m;     // segments advanced
-    int from, to;  // snapshot buffers (reverse: `from` only; -1: the live state)
-  };
-  std::vector<Act> acts;
-  if (s->ckpt_schedule == MONO_CKPT_UNIFORM) {
-    for (int64_t c = nck - 1; c >= 0; --c) acts.push_back({false, c, 0, (int)c, -1});
-  } else {
-    const CkptPlan& p = s->plan;
-    std::function<void(int64_t, int64_t, int, int)> revF = [&](int64_t first, int64_t k, int slot,
-                                                                int f) {
-      if (k == 1) {
-        acts.push_back({false, first, 0, slot, -1});
-        return;
-      }
-      const int64_t m = p.splitF[p.idx(k, f)];
-      if (k - m == 1) {
-        // advance to the last segment and reverse it from the live state
-        acts.push_back({true, first, m, slot, -1});
-        acts.push_back({false, first + m, 0, -1, -1});
-      } else {
-        acts.push_back({true, first, m, slot, slot + 1});
-        revF(first + m, k - m, slot + 1, f - 1);
-      }
-      revF(first, m, slot, f);
-    };
-    std::function<void(int64_t, int64_t, int, int)> revA = [&](int64_t first, int64_t k, int slot,
-                                                                int f) {
-      if (k == 1) {
-        acts.push_back({false, first, 0, slot, -1});
-        return;
-      }
-      const int64_t m = p.splitA[p.idx(k, f)];
-      if (m == 0) return revF(first, k, slot, f);
-      revA(first + m, k - m, slot + 1, f - 1);
-      revF(first, m, slot, f);
-    };
-    revA(0, nck, 0, p.width - 1);
-  }
-  // forward advances of whole segments (never the last, possibly shorter,
-  // one): plain outer steps, the clock advanced on the device
-  GraphPair adv;
-  bool have_adv = false;
-  s->ckpt_advances = 0;
-  for (const Act& a : acts) {
-    if (a.advance && !have_adv) {
-      auto plain = [s](int64_t cn) {
-        return [s, cn]() {
-          for (int64_t t = 0; t < cn; ++t) enqueue_loss_step<T>(s, t, false, nullptr, true);
-          launch_advance_clock(s->d_base, cn, s->stream);
-        };
       };
-      st = adv.capture(s, plain, C, C);
-      if (st != MONO_OK) return st;
-      have_adv = true;
+    };
+  };
+  // reverse of a segment from tape b (the sensors' targets by the reverse's
+  // own clock, d_base_rev, so that a recompute can run beside it)
+  auto reverse = [=](int b) {
+    return [=](int64_t cn) {
+      return [=]() {
+        T* lamV = (T*)s->d_lam;
+        T* lamW = (T*)s->d_lamV2;
+        for (int64_t t = cn - 1; t >= 0; --t) {
+          const T* vs = vsubs[b] + (size_t)t * 2 * L * Np;
+          const T* entry = ents[b] + (size_t)t * S * Np;
+          for (int m = L - 1; m >= 0; --m) {
+            launch_adj_diffusion<T>(
+                s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)(L + m) * Np, m),
+                s->stream);
+            std::swap(lamV, lamW);
+          }
+          AdjIonArgs<T> ai{};
+          ai.n = s->n;
+          ai.Np = s->Np;
+          ai.entry = entry;
+          ai.k = ks[b] + (size_t)t * s->n;
+          ai.lam = (T*)s->d_lam;
+          ai.lamV = lamV;
+          ai.par = (const T*)s->d_par;
+          for (int q = 0; q < kMaxParams; ++q) ai.par_uniform[q] = (T)s->par_uniform[q];
+          ai.par_pernode = s->par_pernode;
+          ai.dt = s->dt;
+          ai.gpart = s->d_gpart;
+          ai.sort = s->lc.react_sort;
+          if (s->ns > 0) {
+            // the loss gradient at reaction entry goes in with the reaction's
+            // adjoint (one launch instead of two)
+            SensorArgs sa = sensor_args(s, t);
+            sa.clk.base = s->d_base_rev;
+            ai.sens_of = s->d_sens_of;
+            ai.target = sa.target;
+            ai.ns = sa.ns;
+            ai.target_steps = sa.target_steps;
+            ai.clk = sa.clk;
+          }
+          launch_adj_ionic<T>(s->model, ai, s->stream);
+          for (int m = L - 1; m >= 0; --m) {
+            launch_adj_diffusion<T>(
+                s->layout, adj_diff_args<T>(s, lamV, lamW, vs + (size_t)m * Np, m), s->stream);
+            std::swap(lamV, lamW);
+          }
+        }
+      };
+    };
+  };
+  const bool overlap = s->ckpt_schedule == MONO_CKPT_UNIFORM && s->d_seg_vsub2 && nck > 1;
+  const int nbuf = overlap ? 2 : 1;
+  GraphPair rec[2], rev[2];
+  for (int b = 0; b < nbuf; ++b) {
+    // tape b serves the segments c with c % 2 == b when two tapes alternate
+    mono_status st = rec[b].capture(s, recompute(b), N, C, true, s->tape_step0, nbuf, b);
+    if (st == MONO_OK) st = rev[b].capture(s, reverse(b), N, C, false, s->tape_step0, nbuf, b);
+    if (st != MONO_OK) return st;
+  }
+  // one segment: its state from a snapshot buffer (or the live state), the
+  // recompute into tape b, then its reverse; with `aux` the recompute runs on
+  // the auxiliary stream (after the reverse that last read tape b) and the
+  // reverse on the simulation's stream after it
+  hipEvent_t ev[5] = {};
+  auto seg = [&](int64_t c, int from, int b, bool aux) -> mono_status {
+    const int64_t t0 = c * C, cn = std::min(C, N - t0);
+    hipStream_t R = s->stream;
+    if (aux) {
+      HIP_TRY(hipStreamWaitEvent(s->stream_aux, ev[2 + b], 0));    // tape b free
+      s->stream = s->stream_aux;
     }
-    if (a.advance) {
-      HIP_TRY(load_state(s, s->d_ckpt[a.from]));
-      launch_set_clock(s->d_base, s->tape_step0 + a.c * C, s->stream);
-      for (int64_t q = 0; q < a.m; ++q)
-        HIP_TRY(hipGraphLaunch(adv.pick(s, s->tape_step0 + (a.c + q) * C, C, C), s->stream));
-      if (a.to >= 0) HIP_TRY(save_state(s, s->d_ckpt[a.to]));
-      s->ckpt_advances += a.m;
-      continue;
-    }
-    const int64_t t0 = a.c * C, cn = std::min(C, N - t0);
-    if (a.from >= 0) {
-      HIP_TRY(load_state(s, s->d_ckpt[a.from], vsub));
+    hipError_t e = hipSuccess;
+    if (from >= 0) {
+      e = load_state(s, s->d_ckpt[from], vsubs[b]);
     } else {
       // the live state is the segment's start: its potential to the tape's
       // first slot, the other rows stay where the recompute reads them
-      HIP_TRY(hipMemcpyAsync(vsub, s->d_V[0], Np * s->es, hipMemcpyDeviceToDevice, s->stream));
+      e = hipMemcpyAsync(vsubs[b], s->d_V[0], Np * s->es, hipMemcpyDeviceToDevice, s->stream);
     }
-    launch_set_clock(s->d_base, s->tape_step0 + t0, s->stream);
-    HIP_TRY(hipGraphLaunch(gp.pick(s, s->tape_step0 + t0, cn, C), s->stream));
+    if (e == hipSuccess) {
+      launch_set_clock(s->d_base, s->tape_step0 + t0, s->stream);
+      e = hipGraphLaunch(rec[b].pick(s, s->tape_step0 + t0, cn, C), s->stream);
+    }
+    if (aux) {
+      if (e == hipSuccess) e = hipEventRecord(ev[b], s->stream);     // tape b written
+      s->stream = R;
+      if (e == hipSuccess) e = hipStreamWaitEvent(R, ev[b], 0);
+    }
+    HIP_TRY(e);
+    launch_set_clock(s->d_base_rev, s->tape_step0 + t0, R);
+    HIP_TRY(hipGraphLaunch(rev[b].pick(s, s->tape_step0 + t0, cn, C), R));
+    if (aux) HIP_TRY(hipEventRecord(ev[2 + b], R));               // tape b read
+    return MONO_OK;
+  };
+  mono_status st = MONO_OK;
+  s->ckpt_advances = 0;
+  if (overlap) {
+    // segments from the last to the first; the recompute of segment c - 1
+    // (auxiliary stream, tape (c - 1) % 2) runs while segment c is reversed
+    // (tape c % 2); everything before this point on the simulation's stream
+    // comes first
+    if (!s->stream_aux &&
+        hipStreamCreateWithFlags(&s->stream_aux, hipStreamNonBlocking) != hipSuccess)
+      return fail(MONO_EDEVICE, "stream creation failed");
+    for (hipEvent_t& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        st = fail(MONO_EDEVICE, "event creation failed");
+    if (st == MONO_OK) {
+      hipError_t e = hipEventRecord(ev[4], s->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->stream_aux, ev[4], 0);
+      for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipEventRecord(ev[2 + b], s->stream);
+      if (e != hipSuccess) st = fail(MONO_EDEVICE, "stream ordering failed");
+    }
+    for (int64_t c = nck - 1; c >= 0 && st == MONO_OK; --c)
+      st = seg(c, (int)c, (int)(c & 1), true);
+    // the simulation's stream has waited for the last recompute
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (st != MONO_OK) {
+      (void)hipStreamSynchronize(s->stream_aux);
+      return st;
+    }
+  } else {
+    // the schedule: segments reversed from the last to the first, each from a
+    // snapshot buffer; in the binomial schedule, forward advances of whole
+    // segments refill buffers in between
+    struct Act {
+      bool advance;
+      int64_t c;     // segment reversed, or first segment advanced over
+      int64_t m;     // segments advanced
+      int from, to;  // snapshot buffers (reverse: `from` only; -1: the live state)
+    };
+    std::vector<Act> acts;
+    if (s->ckpt_schedule == MONO_CKPT_UNIFORM) {
+      for (int64_t c = nck - 1; c >= 0; --c) acts.push_back({false, c, 0, (int)c, -1});
+    } else {
+      const CkptPlan& p = s->plan;
+      std::function<void(int64_t, int64_t, int, int)> revF = [&](int64_t first, int64_t k,
+                                                                  int slot, int f) {
+        if (k == 1) {
+          acts.push_back({false, first, 0, slot, -1});
+          return;
+        }
+        const int64_t m = p.splitF[p.idx(k, f)];
+        if (k - m == 1) {
+          // advance to the last segment and reverse it from the live state
+          acts.push_back({true, first, m, slot, -1});
+          acts.push_back({false, first + m, 0, -1, -1});
+        } else {
+          acts.push_back({true, first, m, slot, slot + 1});
+          revF(first + m, k - m, slot + 1, f - 1);
+        }
+        revF(first, m, slot, f);
+      };
+      std::function<void(int64_t, int64_t, int, int)> revA = [&](int64_t first, int64_t k,
+                                                                  int slot, int f) {
+        if (k == 1) {
+          acts.push_back({false, first, 0, slot, -1});
+          return;
+        }
+        const int64_t m = p.splitA[p.idx(k, f)];
+        if (m == 0) return revF(first, k, slot, f);
+        revA(first + m, k - m, slot + 1, f - 1);
+        revF(first, m, slot, f);
+      };
+      revA(0, nck, 0, p.width - 1);
+    }
+    // forward advances of whole segments (never the last, possibly shorter,
+    // one): plain outer steps, the clock advanced on the device
+    GraphPair adv;
+    bool have_adv = false;
+    for (const Act& a : acts) {
+      if (a.advance && !have_adv) {
+        auto plain = [s](int64_t cn) {
+          return [s, cn]() {
+            for (int64_t t = 0; t < cn; ++t) enqueue_loss_step<T>(s, t, false, nullptr, true);
+            launch_advance_clock(s->d_base, cn, s->stream);
+          };
+        };
+        st = adv.capture(s, plain, C, C);
+        if (st != MONO_OK) return st;
+        have_adv = true;
+      }
+      if (a.advance) {
+        HIP_TRY(load_state(s, s->d_ckpt[a.from]));
+        launch_set_clock(s->d_base, s->tape_step0 + a.c * C, s->stream);
+        for (int64_t q = 0; q < a.m; ++q)
+          HIP_TRY(hipGraphLaunch(adv.pick(s, s->tape_step0 + (a.c + q) * C, C, C), s->stream));
+        if (a.to >= 0) HIP_TRY(save_state(s, s->d_ckpt[a.to]));
+        s->ckpt_advances += a.m;
+        continue;
+      }
+      st = seg(a.c, a.from, 0, false);
+      if (st != MONO_OK) return st;
+    }
   }
   HIP_TRY(hipGetLastError());
   // leave the simulation where the taped forward run ended
@@ -1472,6 +1577,7 @@ void mono_destroy(mono_sim* s) {
   dfree(s->d_target);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->stream_aux) (void)hipStreamDestroy(s->stream_aux);
   delete s;
   g_live_sims.fetch_sub(1);
 }
@@ -2043,13 +2149,24 @@ mono_status mono_forward_taped(mono_sim* s, int64_t n_steps, double dt, int32_t 
   ok = ok && !dalloc((char**)&s->d_final, snap) &&
        !dalloc((char**)&s->d_seg_vsub, (size_t)C * 2 * s->l_max * s->Np * s->es) &&
        !dalloc((char**)&s->d_seg_entry, (size_t)C * s->S * s->Np * s->es) &&
-       !dalloc(&s->d_seg_k, (size_t)C * s->n) &&
+       !dalloc(&s->d_seg_k, (size_t)C * s->n) && !dalloc(&s->d_base_rev, 1) &&
        !dalloc((char**)&s->d_lam, (size_t)s->S * s->Np * s->es) &&
        !dalloc((char**)&s->d_lamV2, s->Np * s->es) && !dalloc(&s->d_gsig, s->Np) &&
        !dalloc(&s->d_gpart, nblk * kMaxParams) && !dalloc(&s->d_loss_steps, n_steps);
   if (!ok) {
     free_tape(s);
     return fail(MONO_ENOMEM, "not enough device memory for the checkpoints and tape");
+  }
+  // the uniform schedule's second segment tape (overlapped recompute); without
+  // the memory for it the segments are reversed one after the other
+  if (s->ckpt_schedule == MONO_CKPT_UNIFORM && nck > 1 &&
+      (dalloc((char**)&s->d_seg_vsub2, (size_t)C * 2 * s->l_max * s->Np * s->es) ||
+       dalloc((char**)&s->d_seg_entry2, (size_t)C * s->S * s->Np * s->es) ||
+       dalloc(&s->d_seg_k2, (size_t)C * s->n))) {
+    dfree(s->d_seg_vsub2);
+    dfree(s->d_seg_entry2);
+    dfree(s->d_seg_k2);
+    (void)hipGetLastError();
   }
   HIP_TRY(hipMemsetAsync(s->d_loss_steps, 0, n_steps * 8, s->stream));
   s->ckpt_every = (int)C;
@@ -2086,7 +2203,8 @@ mono_status mono_checkpoint_info(mono_sim* s, int64_t* out) {
   out[2] = (s->tape_steps + C - 1) / C;
   out[3] = s->ckpt_advances;
   out[4] = (int64_t)(s->d_ckpt.size() * snapshot_bytes(s));
-  out[5] = (int64_t)((size_t)C * (2 * L + s->S) * s->Np * s->es + (size_t)C * s->n);
+  out[5] = (int64_t)((s->d_seg_vsub2 ? 2 : 1) *
+                     ((size_t)C * (2 * L + s->S) * s->Np * s->es + (size_t)C * s->n));
   return MONO_OK;
 }
 
