@@ -172,12 +172,12 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t b0, ui
                                              const T* p, int k) {
   const uint32_t boff = lane * (uint32_t)sizeof(T);
   const uint32_t rs = (uint32_t)(a.Np * (int64_t)sizeof(T));
-  const int64_t i = b0 + lane;
   if (a.tape_st) {
     if (a.off32) {
       const __amdgpu_buffer_rsrc_t tp = rows_rsrc(a.tape_st + b0);
       for (int s = 1; s < M::S; ++s) st_row<T>(tp, boff, (uint32_t)(s - 1) * rs, y[s]);
     } else {
+      const int64_t i = b0 + lane;
       for (int s = 1; s < M::S; ++s) a.tape_st[(int64_t)(s - 1) * a.Np + i] = y[s];
     }
   }
@@ -190,6 +190,10 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t b0, ui
     const __amdgpu_buffer_rsrc_t st = rows_rsrc(a.st + b0);
     for (int s = 1; s < M::S; ++s) st_row<T>(st, boff, (uint32_t)(s - 1) * rs, y[s]);
   } else {
+    // the node index taken again from the byte offset, which stays live for
+    // the 32-bit path anyway, rather than a 64-bit index kept through the
+    // substep loop
+    const int64_t i = b0 + (int64_t)(boff / (uint32_t)sizeof(T));
     vo[i] = y[0];
     for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
   }
