@@ -447,7 +447,7 @@ __global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __r
 }
 
 // ---------------------------------------------------------------------------
-// L consecutive substeps (m0 .. m0+L-1 of a half step) in one launch, for
+// L consecutive substeps (a.m .. a.m + L - 1 of a half step) in one launch, for
 // structured 3D grids with row classes and one instance: temporal blocking.
 // A workgroup owns a tile of 64 - 2L consecutive x, ty = 16 - 2L y rows and
 // tz z planes.  Its 16 wavefronts are the tile's y rows widened by L on each
