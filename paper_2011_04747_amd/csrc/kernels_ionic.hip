@@ -192,8 +192,11 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t b0, ui
   } else {
     // the node index taken again from the byte offset, which stays live for
     // the 32-bit path anyway, rather than a 64-bit index kept through the
-    // substep loop
-    const int64_t i = b0 + (int64_t)(boff / (uint32_t)sizeof(T));
+    // substep loop (the empty asm hides that the offset came from the lane,
+    // so that the compiler does not reuse an index computed before the loop)
+    uint32_t off = boff;
+    __asm__ volatile("" : "+v"(off));
+    const int64_t i = b0 + (int64_t)(off / (uint32_t)sizeof(T));
     vo[i] = y[0];
     for (int s = 1; s < M::S; ++s) a.st[(int64_t)(s - 1) * a.Np + i] = y[s];
   }
