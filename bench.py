@@ -217,6 +217,33 @@ def _model_ops():
     return ops, ops["add"] + ops["mul"] + ops["div"] + ops["exp"] + ops["log"] + ops["sqrt"]
 
 
+def one_graph_run(w, prec, stream, launch, layout):
+    """The workload's whole interval from t = 0 captured as one HIP graph and
+    replayed by one launch (capture outside the timing), timed with events on
+    the simulation's stream."""
+    import torch
+    from paper_2011_04747_amd import mono
+    n = w.n_steps
+    sim = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream, layout=layout)
+    sim.set_launch(**dict(launch, graph_steps=min(n, 8192)))
+    t0 = time.perf_counter()
+    sim.step(n, w.dt, flags=mono.STEP_CAPTURE)
+    sim.sync()
+    capture_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(n, w.dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    sim.close()
+    return {"steps": n, "simulated_ms": n * w.dt, "graph_launches": (n + 8191) // 8192,
+            "ms": ms, "node_updates_per_s": w.mesh.n_nodes * n / (ms * 1e-3),
+            "capture_s": capture_s}
+
+
 def other_leg(kind, w, prec, stream, args, layout, name):
     """Throughput of another workload (or precision) over the same window,
     with the roofline of its diffusion and reaction kernels."""
@@ -678,6 +705,9 @@ def main():
         legs["batched"] = other_leg("batched", wb, "f32", stream, args, mono.LAYOUT_AUTO,
                                     f"batched_tp06_2d: 64 sheets, sides U{{50..400}} seed 4, "
                                     f"{wb.mesh.n_nodes} nodes, log-normal sigma, dt=0.1 ms")
+        # the whole 400 ms of all 64 instances as one graph launch
+        legs["batched"]["whole_run_one_graph"] = one_graph_run(
+            wb, "f32", stream, legs["batched"]["launch"], mono.LAYOUT_AUTO)
         del wb
         wt = W.slab_ischemic_tets(precision="f32", order="rcm")
         legs["tets"] = other_leg("tets", wt, "f32", stream, args, mono.LAYOUT_AUTO,
