@@ -732,3 +732,58 @@ def test_replayed_k_is_clamped(torch):
     assert np.array_equal(out[0][0], out[1][0])
     for a, b in zip(out[0][2], out[1][2]):
         assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# degenerate cases of the method
+# ---------------------------------------------------------------------------
+def test_daeti_reduces_to_ost_at_the_ost_step(torch):
+    """At dt = dt0 the reaction cap k_max = floor(dt/dt0) is 1 and, with
+    dt/2 below the stable diffusion step, l = 1: DAETI is then OST, the same
+    bits in V, every state and the activation times."""
+    w = W.sheet_tp06(n=41, dx=0.05, t_end=8.0)
+    out = []
+    for method in (mono.DAETI, mono.OST):
+        s = mono.Sim.from_workload(w, "f64")
+        s.set_method(method)
+        s.step(800, 0.01)
+        info = s.info()
+        assert info["l"] == 1 and info["k_max"] == 1, (method, info["l"], info["k_max"])
+        out.append([s.get(mono.FIELD_V), s.get(mono.FIELD_LAT), s.state(4), s.state(9)])
+        s.close()
+    for a, b in zip(*out):
+        assert (a == b).all()
+
+
+def _single_element(dim):
+    """One line, quad or hex element of side 0.01 cm (no row repeats a grid
+    pattern wide enough for the row-sharing kernel)."""
+    n = 2 ** dim
+    xyz = np.array([[(c >> a) & 1 for a in range(dim)] for c in range(n)], float) * 0.01
+    order = {1: [0, 1], 2: [0, 1, 3, 2], 3: [0, 1, 3, 2, 4, 5, 7, 6]}[dim]
+    conn = np.array([order], np.int32)
+    D = np.eye(dim)[None] * 0.001
+    return W.Mesh(dim, xyz, n, conn, D)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_single_element_meshes_fp64(torch, dim):
+    """The smallest meshes: one element, every node on the boundary and
+    stimulated; FP64 against the oracle with its substep counts replayed."""
+    m = _single_element(dim)
+    p = W.tp06_params(m.n_nodes)
+    st = W.Stimulus(np.arange(m.n_nodes, dtype=np.int32), 0.0, 1.0, W.STIM_AMP_TP06_PLANAR)
+    w = W.Workload("one_element", m, W.MODEL_TP06, p, [st], 0.1, 30.0, 0.01, "f64", -40.0)
+    o, s, levels, nflip = run_pair(torch, w, w.n_steps, every=50)
+    _assert_f64_levels(w, levels)
+    assert (s.get(mono.FIELD_LAT) > 0).all()
+
+
+def test_mesh_without_elements_is_rejected(torch):
+    """Nodes but no element: no diffusion operator, no stable step (eq. 3
+    divides by zero) — rejected at creation."""
+    m = W.Mesh(2, np.random.default_rng(0).uniform(0, 1, (5, 2)), 4,
+               np.zeros((0, 4), np.int32), np.zeros((0, 2, 2)))
+    with pytest.raises(mono.MonoError) as e:
+        mono.Sim(m, "f64")
+    assert e.value.code == -1
