@@ -33,14 +33,19 @@
 //     formulations carried over from ten Tusscher et al., Am. J. Physiol.
 //     286:H1573 (2004); optionally with the endocardial / M-cell variants
 //     per node (a seventh parameter).
-//     Parity unpinned: the TP06 rate equations (gate kinetics, current
-//     magnitudes).  The publication is not at hand, so only properties pin
-//     them (rest stability, upstroke, peak and APD90 ranges; for the cell
-//     types, the closed-form differences of dV/dt, the s-gate half points and
-//     the APD ordering); the GPU library's independent transcription agreeing
-//     with this one checks each against the other, not against the
-//     publication.  The model's charge and ion balance (every current moves
-//     its own ion; forward Euler keeps that linear invariant) is pinned.
+//     Parity unpinned: the numerical constants of the TP06 rate equations
+//     (half-activation voltages, slopes, time-constant fits, conductances).
+//     The publication is not at hand, so only properties pin them (rest
+//     stability, upstroke, peak and APD90 ranges; for the cell types, the
+//     closed-form differences of dV/dt, the s-gate half points and the APD
+//     ordering); the GPU library's independent transcription agreeing with
+//     this one checks each against the other, not against the publication.
+//     The model's structure is pinned: charge and ion balance (every current
+//     moves its own ion; forward Euler keeps that linear invariant), every
+//     current's zero at its Nernst potential and its outward sign above it,
+//     the L-type flux's reversal and removable singularity, the direction
+//     and range of every gate, and the membrane current as the sum of its
+//     parts.
 //
 // Build: g++ -O2 -fopenmp -ffp-contract=off -shared -fPIC (see build.py).
 

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE_TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_celltypes.py",
                 "tests/test_oracle_apd.py", "tests/test_adjoint_cpu.py",
                 "tests/test_oracle_fibrosis.py", "tests/test_oracle_time_pins.py",
-                "tests/test_oracle_tp06_balance.py"]
+                "tests/test_oracle_tp06_balance.py", "tests/test_oracle_tp06_properties.py"]
 
 
 def test_oracle_tests_pass_under_asan_and_ubsan(tmp_path):
