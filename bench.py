@@ -147,7 +147,7 @@ def time_window(w, prec, stream, steps, warmup, repeats, layout, tune):
     sim = mono.Sim.from_workload(w, prec, stream=stream.cuda_stream, layout=layout)
     sim.step(warmup, w.dt)
     launch = sim.launch()
-    if tune and prec == "f32":
+    if tune:
         from paper_2011_04747_amd import autotune
         launch = autotune.tune(sim, w.dt)
     sim.step(steps, w.dt, flags=mono.STEP_CAPTURE)
@@ -531,7 +531,7 @@ def main():
     # then the graphs the window replays (graph_steps steps and the remainder
     # of K) are captured outside it
     sim.step(args.warmup, w.dt)
-    if not args.no_tune and prec == "f32":
+    if not args.no_tune:
         from paper_2011_04747_amd import autotune
         launch = autotune.tune(sim, w.dt)
     sim.step(args.steps, w.dt, flags=mono.STEP_CAPTURE)

@@ -333,13 +333,13 @@ def full_slab():
     return w, _oracle(w)
 
 
-def _slab_tuned_launch():
-    """The committed tuned launch of the full-size FP32 slab."""
+def _slab_tuned_launch(prec="f32"):
+    """The committed tuned launch of the full-size slab in precision prec."""
     import glob
     import json
     import os
     (f,) = glob.glob(os.path.join(os.path.dirname(mono.__file__), "tuned",
-                                  "gfx950_f32_stencil13_m2_n2060451_i1_nnz54541351*.json"))
+                                  f"gfx950_{prec}_stencil13_m2_n2060451_i1_nnz54541351*.json"))
     with open(f) as fh:
         return json.load(fh)["launch"]
 
@@ -348,8 +348,9 @@ def _slab_tuned_launch():
                                          ("f64", "tuned"), ("f32", "tuned")])
 def test_full_slab_single_phases_sampled(torch, full_slab, prec, launch):
     """One diffusion substep and one reaction step of the full 2,060,451-node
-    slab, in the default launch shape and in the committed tuned one (the
-    shape the benchmark times), sampled row by row against the oracle."""
+    slab, in the default launch shape and in the committed tuned one of each
+    precision (the shapes the benchmark times), sampled row by row against
+    the oracle."""
     w, o = full_slab
     n = w.mesh.n_nodes
     o.prepare(w.dt)
@@ -358,7 +359,7 @@ def test_full_slab_single_phases_sampled(torch, full_slab, prec, launch):
     vprev = y0[0] - rng.uniform(-1.5, 1.5, n) * rng.choice([0.0, 0.01, 0.1, 1.0], n)
     s = mono.Sim.from_workload(w, prec)
     if launch == "tuned":
-        s.set_launch(**_slab_tuned_launch())
+        s.set_launch(**_slab_tuned_launch(prec))
     s.prepare(w.dt)
     rows = np.unique(np.concatenate([rng.integers(0, n, 3000), [0, 1, 200, n - 1, n - 2],
                                      np.arange(n - 300, n)]))
