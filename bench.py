@@ -254,17 +254,21 @@ def other_leg(kind, w, prec, stream, args, layout, name):
     _, f_model = _model_ops()
     flops = r["substeps_per_step"] * f_model
     peak = FP64_VECTOR_PEAK_TFLOPS if prec == "f64" else FP32_VECTOR_PEAK_TFLOPS
+    # committed HBM traffic of this workload and launch shape (FP32 counters)
+    tkey = kind if kind in ("batched", "tets") and prec == "f32" else None
     out = {"workload": name, "dtype": prec, "nodes": w.mesh.n_nodes, "steps": args.steps,
            "warmup": args.warmup, "value": r["node_updates_per_s"], "unit": "node-updates/s",
            "ms_per_step": r["ms_per_step"], "repeats_ms": r["repeats_ms"], "launch": launch,
            "l": r["L"], "mean_k": r["mean_k"],
            "diffusion": {"avg_us": r["diffusion_us"], "bytes_per_row": row_b,
+                         "traffic": _traffic("diffusion", tkey, launch),
                          "launches_per_half_step": info["diff_launches"] or r["L"],
                          "achieved_GBs": w.mesh.n_nodes * row_b / (r["diffusion_us"] * 1e-6) / 1e9,
                          "frac_hbm": w.mesh.n_nodes * row_b / (r["diffusion_us"] * 1e-6) / 1e9
                          / HBM_PEAK_GBS,
                          "ms_per_step": 2 * r["L"] * r["diffusion_us"] * 1e-3},
            "reaction": {"avg_us": r["reaction_us"],
+                        "traffic": _traffic("reaction", tkey, launch),
                         "achieved_TFLOPs": flops / (r["reaction_us"] * 1e-6) / 1e12,
                         "peak_TFLOPs": peak,
                         "frac": flops / (r["reaction_us"] * 1e-6) / 1e12 / peak}}
