@@ -323,25 +323,42 @@ __global__ __launch_bounds__(256) void k_adj_ionic(AdjIonArgs<T> a) {
       p[b] = (a.par_pernode >> b & 1u) ? a.par[(int64_t)b * a.Np + i] : a.par_uniform[b];
     const int k = a.k[i];
     const T h = (T)(a.dt / (double)k);
-    T ys[kAdjMaxK][M::S];
-    for (int s = 0; s < M::S; ++s) ys[0][s] = a.entry[(int64_t)s * a.Np + i];
-    for (int q = 1; q < k; ++q) {
-      for (int s = 0; s < M::S; ++s) ys[q][s] = ys[q - 1][s];
-      M::substep(ys[q], p, h, false);
-    }
     T lam[M::S];
     lam[0] = a.lamV[i];
     for (int s = 1; s < M::S; ++s) lam[s] = a.lam[(int64_t)s * a.Np + i];
     T gp[M::P];
     for (int b = 0; b < M::P; ++b) gp[b] = T(0);
-    for (int q = k - 1; q >= 0; --q) A::vjp(ys[q], p, h, lam, gp);
+    T v_entry;
+    if (k <= 2) {
+      // one or two substeps (most nodes outside upstrokes): both substep
+      // inputs stay in registers
+      T y0[M::S], y1[M::S];
+      for (int s = 0; s < M::S; ++s) y0[s] = y1[s] = a.entry[(int64_t)s * a.Np + i];
+      if (k == 2) M::substep(y1, p, h, false);
+      for (int q = k - 1; q >= 0; --q) {
+        T yq[M::S];
+        for (int s = 0; s < M::S; ++s) yq[s] = q ? y1[s] : y0[s];
+        A::vjp(yq, p, h, lam, gp);
+      }
+      v_entry = y0[0];
+    } else {
+      // the inputs of all k substeps, replayed forward, then reversed
+      T ys[kAdjMaxK][M::S];
+      for (int s = 0; s < M::S; ++s) ys[0][s] = a.entry[(int64_t)s * a.Np + i];
+      for (int q = 1; q < k; ++q) {
+        for (int s = 0; s < M::S; ++s) ys[q][s] = ys[q - 1][s];
+        M::substep(ys[q], p, h, false);
+      }
+      for (int q = k - 1; q >= 0; --q) A::vjp(ys[q], p, h, lam, gp);
+      v_entry = ys[0][0];
+    }
     // loss term of a sensor node: lam_V += 2 (V_entry - target)
     if (a.sens_of) {
       const int32_t sq = a.sens_of[i];
       const int64_t step = *a.clk.base + a.clk.g;
       if (sq >= 0 && step < a.target_steps)
         lam[0] = (T)((double)lam[0] +
-                     2.0 * ((double)ys[0][0] - a.target[step * a.ns + sq]));
+                     2.0 * ((double)v_entry - a.target[step * a.ns + sq]));
     }
     a.lamV[i] = lam[0];
     for (int s = 1; s < M::S; ++s) a.lam[(int64_t)s * a.Np + i] = lam[s];
