@@ -211,9 +211,10 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t b0, ui
 // the same either way, so both give the same bits.
 // Occupancy floor for the register allocator: 8 wavefronts per SIMD (at most
 // 64 registers) for FP32, so that four 512-lane workgroups fill a compute
-// unit; the TP06 substep then spills a few values outside its loop, which
-// costs less than the fourth workgroup gains (7 per SIMD, 72 registers, no
-// spill, fits only three).  No floor in FP64.
+// unit; the TP06 substep loop fits in them without spilling (the fallback
+// node index is rebuilt after the loop, see advance_cell).  No floor in FP64:
+// its substep needs twice the registers per value, and a floor of three or
+// four wavefronts per SIMD makes it spill and run slower than two.
 template <typename T>
 constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 8 : 1;
 
