@@ -165,7 +165,8 @@ typedef struct {
   int32_t n_states;
   int32_t ell_width;  /* ELL slots per row, or stencil offsets per instance    */
   int32_t row_classes; /* distinct stencil rows of a single instance when the
-                          diffusion can read rows by class, else 0             */
+                          diffusion can read rows by class (at most 65535
+                          classes, and each row array under 2 GiB), else 0    */
   int32_t grid_rows;   /* 1 when the stencil offsets are those of a structured
                           grid numbered x fastest (row-sharing diffusion)      */
   int32_t diff_fused;  /* 1 when the grid is a whole 3D nx x ny x nz block

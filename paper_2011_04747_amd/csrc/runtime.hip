@@ -1474,8 +1474,13 @@ static mono_status create_mesh(const mono_mesh_desc* d, mono_sim** out) {
     if (st != MONO_OK) return bail(st);
     if (hipMemcpy(s->d_off, sh.off.data(), sh.off.size() * 4, hipMemcpyHostToDevice))
       return bail(fail(MONO_EDEVICE, "upload failed"));
+    // the kernels that read rows by class (and the row-sharing and fused
+    // forms built on them) index rows with 32-bit byte offsets, so classes are
+    // used only where every row array stays below 2 GiB; larger meshes keep
+    // the per-row stencil with 64-bit indices
     RowClasses rc;
-    if (build_row_classes(sh, s->n, s->Np, s->prec == MONO_F32, 65535, rc)) {
+    const bool narrow = s->Np * (int64_t)s->es < ((int64_t)1 << 31);
+    if (narrow && build_row_classes(sh, s->n, s->Np, s->prec == MONO_F32, 65535, rc)) {
       if (dalloc(&s->d_cls, rc.cls.size()) ||
           dalloc((char**)&s->d_ctab, rc.table.size() * s->es))
         return bail(fail(MONO_ENOMEM, "device allocation failed"));
