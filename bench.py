@@ -206,6 +206,19 @@ def _diff_row_bytes(info, launch, es):
     return b
 
 
+def _react_node_bytes(w, info, es):
+    """Algorithmic HBM bytes per node of one reaction launch (value size es):
+    the S states (V among them), V_prev, the FP64 activation time and the
+    per-node parameter rows read; the S states, V_prev and the 1-byte k
+    written.  Parameter rows that are uniform over the mesh travel as kernel
+    arguments and are not counted."""
+    import numpy as np
+    p = np.asarray(w.params) if w.params is not None else np.zeros((0, 1))
+    pernode = sum(1 for r in range(p.shape[0]) if (p[r] != p[r][0]).any())
+    S = info["n_states"]
+    return (S + 1 + pernode) * es + 8 + (S + 1) * es + 1
+
+
 def _model_ops():
     """Operation count of one TP06 substep at the library's initial state."""
     from paper_2011_04747_amd import mono
@@ -269,6 +282,9 @@ def other_leg(kind, w, prec, stream, args, layout, name):
                          "ms_per_step": 2 * r["L"] * r["diffusion_us"] * 1e-3},
            "reaction": {"avg_us": r["reaction_us"],
                         "traffic": _traffic("reaction", tkey, launch),
+                        "bytes_per_node": _react_node_bytes(w, info, es),
+                        "frac_hbm": w.mesh.n_nodes * _react_node_bytes(w, info, es)
+                        / (r["reaction_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
                         "achieved_TFLOPs": flops / (r["reaction_us"] * 1e-6) / 1e12,
                         "peak_TFLOPs": peak,
                         "frac": flops / (r["reaction_us"] * 1e-6) / 1e12 / peak}}
@@ -664,6 +680,11 @@ def main():
                   "avg_us_per_launch_events": r_event_us,
                   "traffic": _traffic("reaction", tkey, launch)}
     react_roof["frac"] = react_roof["achieved"] / vpeak
+    # the same launch against the HBM roofline (the bound where k is small)
+    rb = n * _react_node_bytes(w, info, es)
+    react_roof["hbm"] = {"bytes_per_node": rb / n, "bytes": rb,
+                         "achieved": rb / (r_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": rb / (r_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
     dominant = react_roof if react_total >= diff_total else diff_roof
     roofline = {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
     roofline["kernel"] = dominant["kernel"]
