@@ -208,15 +208,16 @@ def _diff_row_bytes(info, launch, es):
 
 def _react_node_bytes(w, info, es):
     """Algorithmic HBM bytes per node of one reaction launch (value size es):
-    the S states (V among them), V_prev, the FP64 activation time and the
-    per-node parameter rows read; the S states, V_prev and the 1-byte k
-    written.  Parameter rows that are uniform over the mesh travel as kernel
-    arguments and are not counted."""
+    the S states (V among them), V_prev and the per-node parameter rows read;
+    the S states, V_prev and the 1-byte k written.  Parameter rows that are
+    uniform over the mesh travel as kernel arguments, and the FP64 activation
+    time is read and written only where V crosses the threshold in that
+    step, so neither is counted."""
     import numpy as np
     p = np.asarray(w.params) if w.params is not None else np.zeros((0, 1))
     pernode = sum(1 for r in range(p.shape[0]) if (p[r] != p[r][0]).any())
     S = info["n_states"]
-    return (S + 1 + pernode) * es + 8 + (S + 1) * es + 1
+    return (S + 1 + pernode) * es + (S + 1) * es + 1
 
 
 def _model_ops():
