@@ -353,9 +353,17 @@ __device__ __forceinline__ void st_raw(__amdgpu_buffer_rsrc_t r, uint32_t off, T
         0);
 }
 
+// Occupancy floor: in FP32 with one or two row groups per wavefront the
+// kernel fits 64 registers without spilling, i.e. 8 wavefronts per SIMD (two
+// groups otherwise take 66 registers and 7 wavefronts, 2% slower per launch
+// on the 3D slab); four groups would spill under the floor, FP64 needs more.
+template <typename T, int ITER>
+constexpr int kRowsWavesPerEU = (sizeof(T) == 4 && ITER <= 2) ? 8 : 1;
+
 template <typename T, int P, int BLOCK, int ITER>
-__global__ __launch_bounds__(BLOCK) void k_diff_rows(DiffArgs<T> a, const T* __restrict__ ctab,
-                                                     const int32_t* __restrict__ wcls) {
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(kRowsWavesPerEU<T, ITER>))) void k_diff_rows(
+    DiffArgs<T> a, const T* __restrict__ ctab, const int32_t* __restrict__ wcls) {
   using RP = RowPattern<P>;
   constexpr int NC = RP::NC;
   constexpr int WR = kWaveRows;
