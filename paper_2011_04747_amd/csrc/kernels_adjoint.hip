@@ -138,19 +138,12 @@ __global__ __launch_bounds__(256) void k_adj_diff_rows(AdjDiffArgs<T> a,
     if (g >= ngroups) break;
     const int i = (int)(g * WR) + lane - 1;
     const bool produce = lane >= 1 && lane <= WR && i < n;
-    T ul[NC], ur[NC], vl[NC], vr[NC], sl[NC], sr[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      ul[k] = lane_shift<1>(uc[it][k]);
-      ur[k] = lane_shift<-1>(uc[it][k]);
-      vl[k] = lane_shift<1>(vc[it][k]);
-      vr[k] = lane_shift<-1>(vc[it][k]);
-      sl[k] = SIGU ? sc[it][k] : lane_shift<1>(sc[it][k]);
-      sr[k] = SIGU ? sc[it][k] : lane_shift<-1>(sc[it][k]);
-    }
-    auto pick = [](const T* c, const T* l, const T* r, int k, int d) -> T {
-      return d > 0 ? l[k] : (d < 0 ? r[k] : c[k]);
+    // the x-neighbours are taken from the adjacent lanes where each is used,
+    // so that only the row centres stay live through the sweep
+    auto pick = [](const T* c, int k, int d) -> T {
+      return d > 0 ? lane_shift<1>(c[k]) : (d < 0 ? lane_shift<-1>(c[k]) : c[k]);
     };
+    auto pick_s = [&](int k, int d) -> T { return SIGU ? sc[it][k] : pick(sc[it], k, d); };
     const T ui = uc[it][0], vi = vc[it][0], si = sc[it][0];
     T acc = T(0), gs = T(0);
     auto sweep = [&](auto w) {
@@ -158,9 +151,9 @@ __global__ __launch_bounds__(256) void k_adj_diff_rows(AdjDiffArgs<T> a,
       for (int p = 0; p < P; ++p) {
         const int kf = RP::fk(p), df = RP::fd(p), kb = RP::bk(p), db = RP::bd(p);
         const T wf = w[p], wb = w[P + p];
-        const T uf = pick(uc[it], ul, ur, kf, df), ub = pick(uc[it], ul, ur, kb, db);
-        const T vf = pick(vc[it], vl, vr, kf, df), vb = pick(vc[it], vl, vr, kb, db);
-        const T sf = pick(sc[it], sl, sr, kf, df), sb = pick(sc[it], sl, sr, kb, db);
+        const T uf = pick(uc[it], kf, df), ub = pick(uc[it], kb, db);
+        const T vf = pick(vc[it], kf, df), vb = pick(vc[it], kb, db);
+        const T sf = pick_s(kf, df), sb = pick_s(kb, db);
         acc += wf * (uf - ui) + wb * (ub - ui);
         gs += wf * xrcp(si + sf) * (ui - uf) * (vf - vi);
         gs += wb * xrcp(si + sb) * (ui - ub) * (vb - vi);
