@@ -14,16 +14,31 @@
 namespace mono {
 
 // --- arithmetic primitives --------------------------------------------------
-// FP64 uses IEEE division and the accurate math library throughout.  FP32
-// uses the hardware reciprocal, exp2 and log2 instructions (about 1 ulp each,
-// no denormals) in place of the correctly rounded multi-instruction
+// FP32 uses the hardware reciprocal, exp2 and log2 instructions (about 1 ulp
+// each, no denormals) in place of the correctly rounded multi-instruction
 // sequences; the difference is at the 1e-6 relative level, far inside the
 // FP32 tolerances, and cuts the substep's instruction count severalfold.
+// FP64 on the device forms its reciprocal, exp2 and log2 below (within a few
+// ulp for the finite, normal, in-range arguments the models pass, without the
+// library's handling of denormals, infinities and NaN); the rest of FP64, and
+// the host, use the math library.
 __host__ __device__ __forceinline__ double xexp(double x) { return exp(x); }
 __host__ __device__ __forceinline__ double xexpm1(double x) { return expm1(x); }
 __host__ __device__ __forceinline__ double xlog(double x) { return log(x); }
 __host__ __device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
-__host__ __device__ __forceinline__ double xrcp(double x) { return 1.0 / x; }
+#if defined(__HIP_DEVICE_COMPILE__)
+// 1/b from the hardware estimate and two Newton steps r <- r + r (1 - b r)
+// (each squares the relative error; the last leaves about an ulp)
+__device__ __forceinline__ double xrcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+#else
+__host__ __device__ inline double xrcp(double x) { return 1.0 / x; }
+#endif
 __host__ __device__ __forceinline__ double xfloor(double x) { return floor(x); }
 __host__ __device__ __forceinline__ float xexpm1(float x) { return expm1f(x); }
 __host__ __device__ __forceinline__ float xfloor(float x) { return floorf(x); }
@@ -46,8 +61,55 @@ inline float xrcp(float x) { return 1.0f / x; }
 // base conversion.
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
-__host__ __device__ __forceinline__ double xexp2(double x) { return exp2(x); }
-__host__ __device__ __forceinline__ double xlog2(double x) { return log2(x); }
+#if defined(__HIP_DEVICE_COMPILE__)
+// coefficients of the Taylor series of 2^f = e^(f ln 2), (ln 2)^k / k!, and of
+// the series of atanh(s)/s in s^2, 1/(2k + 1), as compile-time constants
+template <int K>
+struct Exp2Coef {
+  static constexpr double v = Exp2Coef<K - 1>::v * kLn2 / K;
+};
+template <>
+struct Exp2Coef<0> {
+  static constexpr double v = 1.0;
+};
+// sum_{k >= K} c_k f^(k - K) to degree 13 by Horner's rule
+template <int K>
+__device__ __forceinline__ double exp2_series(double f) {
+  if constexpr (K == 13)
+    return Exp2Coef<13>::v;
+  else
+    return __builtin_fma(exp2_series<K + 1>(f), f, Exp2Coef<K>::v);
+}
+template <int K>
+__device__ __forceinline__ double atanh_series(double t) {
+  if constexpr (K == 11)
+    return 1.0 / 23.0;
+  else
+    return __builtin_fma(atanh_series<K + 1>(t), t, 1.0 / (2 * K + 1));
+}
+// 2^x = 2^n 2^f with n = rint(x), |f| <= 1/2: the series to degree 13 (its
+// remainder is below 2^-56 of the sum for |f ln 2| <= 0.35), then the
+// exponent added to n.
+__device__ __forceinline__ double xexp2(double x) {
+  const double n = __builtin_rint(x);
+  return __builtin_amdgcn_ldexp(exp2_series<0>(x - n), (int)n);
+}
+// log2 x = e + log2 m with x = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m =
+// 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...) with s = (m - 1)/(m + 1),
+// |s| <= 0.172, to the term s^23 (the next is below 2^-58 of the sum).
+__device__ __forceinline__ double xlog2(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool lo = m < 0.7071067811865476;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double s = (m - 1.0) * xrcp(m + 1.0);
+  return __builtin_fma(s * atanh_series<0>(s * s), 2.0 * kLog2e, (double)e);
+}
+#else
+__host__ __device__ inline double xexp2(double x) { return exp2(x); }
+__host__ __device__ inline double xlog2(double x) { return log2(x); }
+#endif
 // xlog2c: the same for operands that do not change inside the substep loop
 // (parameters), in a form the compiler may move out of the loop
 __host__ __device__ __forceinline__ double xlog2c(double x) { return log2(x); }

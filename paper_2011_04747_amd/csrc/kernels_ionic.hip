@@ -212,11 +212,12 @@ __device__ __forceinline__ void advance_cell(const IonArgs<T>& a, int64_t b0, ui
 // Occupancy floor for the register allocator: 8 wavefronts per SIMD (at most
 // 64 registers) for FP32, so that four 512-lane workgroups fill a compute
 // unit; the TP06 substep loop fits in them without spilling (the fallback
-// node index is rebuilt after the loop, see advance_cell).  No floor in FP64:
-// its substep needs twice the registers per value, and a floor of three or
-// four wavefronts per SIMD makes it spill and run slower than two.
+// node index is rebuilt after the loop, see advance_cell).  FP64: 2 per SIMD
+// (256 registers; without a floor the allocator also takes accumulation
+// registers and leaves one), since its substep needs twice the registers per
+// value and a floor of three or four makes it spill and run slower.
 template <typename T>
-constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 8 : 1;
+constexpr int kIonWavesPerEU = sizeof(T) == 4 ? 8 : 2;
 
 template <typename T, class M, int BLOCK, bool SORT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kIonWavesPerEU<T>)))
