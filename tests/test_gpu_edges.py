@@ -99,3 +99,36 @@ def test_adjoint_without_sensors_is_zero(torch, prec):
     assert loss == 0.0
     assert not np.any(gs) and not np.any(gp)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_forced_unstable_diffusion_latches(torch, prec):
+    """Failure injection from the host: l forced below the Gershgorin bound
+    of eq. 3 makes the explicit diffusion unstable, the potential grows
+    without bound, turns non-finite and the simulation latches (ENONFINITE at
+    the next synchronising call, ESTATE for further steps), the same chain
+    as a non-finite state set directly.  The same run at its own l stays
+    finite."""
+    w = W.slab_ischemic(shape=(21, 19, 9), t_end=60.0)
+    rng = np.random.default_rng(5)
+    ok = mono.Sim.from_workload(w, prec)
+    ok.prepare(w.dt)
+    assert ok.info()["l"] >= 3
+    v0 = ok.get(mono.FIELD_V) + rng.uniform(-1.0, 1.0, w.mesh.n_nodes)
+    ok.set(mono.FIELD_V, v0)
+    ok.step(300, w.dt)
+    ok.sync()
+    assert np.isfinite(ok.get(mono.FIELD_V)).all()
+    ok.close()
+    s = mono.Sim.from_workload(w, prec)
+    s.set(mono.FIELD_V, v0)
+    s.force_l(1)
+    with pytest.raises(mono.MonoError) as e:
+        for _ in range(60):
+            s.step(10, w.dt)
+            s.sync()
+    assert mono.STATUS[e.value.code] == "ENONFINITE"
+    with pytest.raises(mono.MonoError) as e:
+        s.step(1, w.dt)
+    assert mono.STATUS[e.value.code] == "ESTATE"
+    s.close()
